@@ -1,0 +1,317 @@
+"""Seeded synthetic inputs for the UGKS step: meshes, velocity grids, gas data.
+
+This module only builds inputs.  It holds none of the scheme's arithmetic
+(no equilibria, fluxes, reconstructions or updates); both the HIP library and
+the CPU oracle consume what it returns.  Every random choice is drawn from a
+splitmix64 stream with an explicit seed.
+
+Units follow the usual kinetic non-dimensionalisation: gas constant R = 1/2,
+free-stream density and temperature 1, so the most probable speed
+sqrt(2 R T) is 1 and lambda = 1/(2 R T) = 1/T.
+
+A case is a plain dict:
+
+  mesh   : dim, cell_volume[nc], cell_centroid[nc,dim], face_cells[nf,2]
+           (right = -1 on a boundary), face_normal[nf,dim] (unit, left->right,
+           outward on a boundary), face_area[nf], face_centroid[nf,dim]
+           (in the left cell's frame), face_shift[nf,dim] (added to the right
+           cell's centroid to place its periodic image next to the left cell),
+           face_bc[nf] (0 interior/periodic, 1 inflow, 2 outflow, 3 wall),
+           face_bc_id[nf] (row of gas['bc_prim']).
+  vgrid  : dim, u[nv,dim], w[nv]   (velocity points and quadrature weights,
+           Section 2.3: the integral over velocity space is sum_k Q_k V_k).
+  gas    : Pr, omega, mu_ref, cfl, dt_override, limiter (0 none, 1
+           Venkatakrishnan), limiter_k, bc_prim[nbc, dim+2] (rho, U, T).
+  prim0  : [nc, dim+2] initial (rho, U, T) per cell.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+BC_INTERIOR, BC_INFLOW, BC_OUTFLOW, BC_WALL = 0, 1, 2, 3
+GAMMA = 5.0 / 3.0          # monatomic gas (argon), three translational DOF
+R_GAS = 0.5
+
+
+# --------------------------------------------------------------------------
+# splitmix64 (Steele, Lea, Flood 2014): the seeded stream behind every choice
+# --------------------------------------------------------------------------
+class SplitMix64:
+    MASK = (1 << 64) - 1
+
+    def __init__(self, seed: int):
+        self.state = seed & self.MASK
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & self.MASK
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & self.MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & self.MASK
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        """Uniform double in [0, 1) from the top 53 bits."""
+        return (self.next_u64() >> 11) * (1.0 / (1 << 53))
+
+    def bit(self) -> int:
+        return self.next_u64() >> 63
+
+
+# --------------------------------------------------------------------------
+# physical parameters -> model inputs
+# --------------------------------------------------------------------------
+def vhs_mu_ref(kn: float, omega: float, l_ref: float) -> float:
+    """Reference viscosity of a VHS gas (alpha = 1) whose mean free path at
+    rho = T = 1 is kn * l_ref, in units with sqrt(2 R T_inf) = 1."""
+    return 15.0 * math.sqrt(math.pi) / (2.0 * (5.0 - 2.0 * omega) * (7.0 - 2.0 * omega)) * kn * l_ref
+
+
+def sound_speed(T: float = 1.0) -> float:
+    return math.sqrt(GAMMA * R_GAS * T)
+
+
+# --------------------------------------------------------------------------
+# 2D polygon meshes
+# --------------------------------------------------------------------------
+def _polygon_geometry(pts: np.ndarray):
+    x, y = pts[:, 0], pts[:, 1]
+    xn, yn = np.roll(x, -1), np.roll(y, -1)
+    cross = x * yn - xn * y
+    area = 0.5 * cross.sum()
+    cx = ((x + xn) * cross).sum() / (6.0 * area)
+    cy = ((y + yn) * cross).sum() / (6.0 * area)
+    return area, np.array([cx, cy])
+
+
+def build_mesh_2d(cells, classify_boundary=None):
+    """Assemble face data from polygons.
+
+    cells: list of polygons, counter-clockwise; each vertex is (vid, x, y)
+    where vid identifies the vertex across periodic images and (x, y) is its
+    position in that cell's own frame.
+    classify_boundary(xf, n) -> (bc, bc_id) for faces with one cell.
+    """
+    nc = len(cells)
+    vol = np.zeros(nc)
+    cen = np.zeros((nc, 2))
+    edges = {}
+    for c, poly in enumerate(cells):
+        pts = np.array([[p[1], p[2]] for p in poly], dtype=np.float64)
+        a, g = _polygon_geometry(pts)
+        if a <= 0:
+            raise ValueError(f"cell {c} is not counter-clockwise")
+        vol[c], cen[c] = a, g
+        m = len(poly)
+        for e in range(m):
+            va, vb = poly[e], poly[(e + 1) % m]
+            key = (min(va[0], vb[0]), max(va[0], vb[0]))
+            edges.setdefault(key, []).append((c, np.array(va[1:]), np.array(vb[1:])))
+    fc, fn, fa, fx, fs, fbc, fid = [], [], [], [], [], [], []
+    for key in sorted(edges, key=lambda k: tuple(sorted(e[0] for e in edges[k])) + k):
+        ent = sorted(edges[key], key=lambda e: e[0])
+        c0, pa, pb = ent[0]
+        d = pb - pa
+        length = float(np.hypot(d[0], d[1]))
+        normal = np.array([d[1], -d[0]]) / length  # outward for a CCW polygon
+        mid = 0.5 * (pa + pb)
+        if len(ent) == 2:
+            c1, qa, qb = ent[1]
+            shift = mid - 0.5 * (qa + qb)
+            fc.append((c0, c1)); fbc.append(BC_INTERIOR); fid.append(0)
+        elif len(ent) == 1:
+            shift = np.zeros(2)
+            if classify_boundary is None:
+                raise ValueError("boundary edge in a mesh declared closed")
+            bc, bid = classify_boundary(mid, normal)
+            fc.append((c0, -1)); fbc.append(bc); fid.append(bid)
+        else:
+            raise ValueError("edge shared by more than two cells")
+        fn.append(normal); fa.append(length); fx.append(mid); fs.append(shift)
+    return dict(
+        dim=2,
+        cell_volume=vol,
+        cell_centroid=cen,
+        face_cells=np.array(fc, dtype=np.int32).reshape(-1, 2),
+        face_normal=np.array(fn).reshape(-1, 2),
+        face_area=np.array(fa),
+        face_centroid=np.array(fx).reshape(-1, 2),
+        face_shift=np.array(fs).reshape(-1, 2),
+        face_bc=np.array(fbc, dtype=np.int32),
+        face_bc_id=np.array(fid, dtype=np.int32),
+    )
+
+
+def periodic_triangles(nx=20, ny=10, lx=2.0, ly=1.0, seed=0, split="random"):
+    """nx*ny quads on [0,lx]x[0,ly], each cut on a diagonal chosen by the
+    seeded stream (split='random'), or all on the same one ('up'/'down').
+    Periodic in both directions."""
+    rng = SplitMix64(seed)
+    dx, dy = lx / nx, ly / ny
+
+    def v(i, j):
+        return ((i % nx) * ny + (j % ny), i * dx, j * dy)
+
+    cells = []
+    for i in range(nx):
+        for j in range(ny):
+            p00, p10, p11, p01 = v(i, j), v(i + 1, j), v(i + 1, j + 1), v(i, j + 1)
+            if split == "random":
+                diag = rng.bit()
+            else:
+                diag = 0 if split == "up" else 1
+            if diag == 0:   # cut p00 -- p11
+                cells.append([p00, p10, p11]); cells.append([p00, p11, p01])
+            else:           # cut p10 -- p01
+                cells.append([p00, p10, p01]); cells.append([p10, p11, p01])
+    return build_mesh_2d(cells)
+
+
+def periodic_quads(nx, ny, lx=1.0, ly=1.0):
+    dx, dy = lx / nx, ly / ny
+
+    def v(i, j):
+        return ((i % nx) * ny + (j % ny), i * dx, j * dy)
+
+    cells = [[v(i, j), v(i + 1, j), v(i + 1, j + 1), v(i, j + 1)]
+             for i in range(nx) for j in range(ny)]
+    return build_mesh_2d(cells)
+
+
+def channel_quads(nx, ny, lx=1.0, ly=1.0, y_bc=(BC_WALL, 1)):
+    """Quads periodic in x, bounded in y by faces of type y_bc."""
+    dx, dy = lx / nx, ly / ny
+
+    def v(i, j):
+        return ((i % nx) * (ny + 1) + j, i * dx, j * dy)
+
+    cells = [[v(i, j), v(i + 1, j), v(i + 1, j + 1), v(i, j + 1)]
+             for i in range(nx) for j in range(ny)]
+    return build_mesh_2d(cells, classify_boundary=lambda xf, n: y_bc)
+
+
+def cylinder_ogrid(n_theta=200, n_r=95, r_wall=1.0, r_far=15.0, h_first=1e-3,
+                   n_tri_rings=5, u_inf=(1.0, 0.0), seed=0):
+    """O-grid around a cylinder of radius r_wall out to r_far.  Radial spacing
+    grows geometrically from h_first at the wall.  The outer n_tri_rings rings
+    are cut into triangles on seeded diagonals.  Boundary faces: wall (3, id 1)
+    on the cylinder; on the far field inflow (1, id 0) where u_inf . n < 0,
+    else outflow (2, id 0)."""
+    rng = SplitMix64(seed)
+    span = r_far - r_wall
+    # growth ratio g with h (g^n - 1)/(g - 1) = span
+    lo, hi = 1.0 + 1e-12, 2.0
+    for _ in range(200):
+        g = 0.5 * (lo + hi)
+        s = h_first * (g ** n_r - 1.0) / (g - 1.0)
+        lo, hi = (g, hi) if s < span else (lo, g)
+    radii = np.empty(n_r + 1)
+    radii[0] = r_wall
+    h = h_first
+    for j in range(n_r):
+        radii[j + 1] = radii[j] + h
+        h *= g
+    radii[-1] = r_far
+    th = 2.0 * math.pi * np.arange(n_theta) / n_theta
+
+    def v(i, j):
+        ii = i % n_theta
+        return (j * n_theta + ii, radii[j] * math.cos(th[ii]), radii[j] * math.sin(th[ii]))
+
+    cells = []
+    for j in range(n_r):
+        for i in range(n_theta):
+            p00, p10, p11, p01 = v(i, j), v(i, j + 1), v(i + 1, j + 1), v(i + 1, j)
+            # (r, theta) ordering: r outward then theta forward is CCW
+            if j >= n_r - n_tri_rings:
+                if rng.bit() == 0:
+                    cells.append([p00, p10, p11]); cells.append([p00, p11, p01])
+                else:
+                    cells.append([p00, p10, p01]); cells.append([p10, p11, p01])
+            else:
+                cells.append([p00, p10, p11, p01])
+    uinf = np.asarray(u_inf, dtype=np.float64)
+    r_mid = 0.5 * (r_wall + r_far)
+
+    def classify(xf, n):
+        if math.hypot(xf[0], xf[1]) < r_mid:
+            return (BC_WALL, 1)
+        return (BC_INFLOW, 0) if float(uinf @ n) < 0.0 else (BC_OUTFLOW, 0)
+
+    return build_mesh_2d(cells, classify_boundary=classify)
+
+
+# --------------------------------------------------------------------------
+# velocity grids
+# --------------------------------------------------------------------------
+def trapezoid_1d(n: int, half_width: float, center: float = 0.0):
+    x = center + np.linspace(-half_width, half_width, n)
+    w = np.full(n, 2.0 * half_width / (n - 1))
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    return x, w
+
+
+def tensor_vgrid(n, half_width, dim=2, center=None):
+    """Cartesian velocity grid, trapezoid weights.  Point k = (a, b[, c]) is
+    stored at k = (a * n + b) * n + c: the last axis is contiguous."""
+    center = np.zeros(dim) if center is None else np.asarray(center, dtype=np.float64)
+    axes = [trapezoid_1d(n, half_width, center[d]) for d in range(dim)]
+    grids = np.meshgrid(*[a[0] for a in axes], indexing="ij")
+    wg = np.meshgrid(*[a[1] for a in axes], indexing="ij")
+    u = np.stack([g.reshape(-1) for g in grids], axis=1)
+    w = np.prod(np.stack([g.reshape(-1) for g in wg], axis=1), axis=1)
+    return dict(dim=dim, u=np.ascontiguousarray(u), w=np.ascontiguousarray(w))
+
+
+# --------------------------------------------------------------------------
+# the named workloads
+# --------------------------------------------------------------------------
+def gas_params(Pr, omega, mu_ref, cfl=0.8, limiter=1, limiter_k=1.0, bc_prim=None,
+               dt_override=0.0, dim=2):
+    if bc_prim is None:
+        bc_prim = np.zeros((1, dim + 2)); bc_prim[0, 0] = 1.0; bc_prim[0, -1] = 1.0
+    return dict(Pr=float(Pr), omega=float(omega), mu_ref=float(mu_ref), cfl=float(cfl),
+                dt_override=float(dt_override), limiter=int(limiter), limiter_k=float(limiter_k),
+                bc_prim=np.ascontiguousarray(np.asarray(bc_prim, dtype=np.float64)))
+
+
+def case_periodic_wave(nx=20, ny=10, nv=28, half_width=6.0, kn=0.1, seed=0, Pr=1.0,
+                       omega=0.5, amp=0.1, limiter=1, split="random"):
+    """2D plain case: 400 triangles (20x10 quads cut on seeded diagonals) on
+    [0,2]x[0,1], periodic; 28x28 trapezoid velocity grid on [-6,6]^2; BGK,
+    Kn = 0.1; rho = 1 + amp sin(pi x), U = 0, T = 1; CFL 0.8."""
+    mesh = periodic_triangles(nx, ny, 2.0, 1.0, seed=seed, split=split)
+    vg = tensor_vgrid(nv, half_width, 2)
+    gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 1.0), limiter=limiter)
+    x = mesh["cell_centroid"][:, 0]
+    prim0 = np.zeros((len(x), 4))
+    prim0[:, 0] = 1.0 + amp * np.sin(math.pi * x)
+    prim0[:, 3] = 1.0
+    return dict(name=f"periodic_tri_{2*nx*ny}_v{nv}x{nv}", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+
+
+def case_cylinder(n_theta=200, n_r=95, n_tri_rings=5, nv=60, half_width=15.0, ma=5.0, kn=0.1,
+                  Pr=2.0 / 3.0, omega=0.81, t_wall=1.0, h_first=1e-3, r_far=15.0, seed=0):
+    """2D hypersonic cylinder: unit-radius cylinder, far field radius 15,
+    200 x 95 O-grid with the outer 5 rings cut into triangles (20,000 cells),
+    first layer 1e-3; Shakhov Pr = 2/3, Ma = 5, Kn = 0.1 on the diameter,
+    isothermal wall at T_inf; 60 x 60 trapezoid grid on [-15,15]^2;
+    free-stream Maxwellian start."""
+    u_inf = ma * sound_speed(1.0)
+    mesh = cylinder_ogrid(n_theta, n_r, 1.0, r_far, h_first, n_tri_rings, (u_inf, 0.0), seed)
+    vg = tensor_vgrid(nv, half_width, 2)
+    bc = np.array([[1.0, u_inf, 0.0, 1.0],       # free stream
+                   [1.0, 0.0, 0.0, t_wall]])     # wall (rho unused)
+    gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 2.0), bc_prim=bc)
+    nc = len(mesh["cell_volume"])
+    prim0 = np.tile(bc[0], (nc, 1))
+    return dict(name=f"cylinder_{nc}_v{nv}x{nv}", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+
+
+def n_comp(dim: int) -> int:
+    """Stored reduced distributions per (cell, velocity): h and b in 2D
+    (one internal velocity component), h only in 3D (no internal component
+    for a monatomic gas, so b is identically zero)."""
+    return 2 if dim == 2 else 1
