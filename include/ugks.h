@@ -1,0 +1,150 @@
+/*
+ * ugks.h -- C ABI of the MI355X (gfx950) memory-saving UGKS library.
+ *
+ * One handle advances one flow case of the unified gas-kinetic scheme on an
+ * unstructured mesh, as set out in Y. Zhang, Y. Wei, W. Long, K. Xu,
+ * "An efficiency and memory-saving programming paradigm for the unified
+ * gas-kinetic scheme" (arXiv:2412.06546):
+ *   - model: BGK-Shakhov equation reduced to h = int f dxi and
+ *     b = int xi^2 f dxi (Sections 2.1-2.2, Eq. BGKReduce);
+ *   - discretisation: finite volumes in physical space, a weighted point set
+ *     in velocity space (Section 2.3, Eqs. BGKdis, microscopicFlux,
+ *     macroscopicUpdata, macroscopicFlux);
+ *   - interface flux from the integral solution (Section 2.4,
+ *     Eq. fullSolution), ghost-cell far field and Maxwellian isothermal wall
+ *     (Section 2.5, Eq. maxWalldes), trapezoid source (Section 2.6);
+ *   - the two-stage update of f (Section 3.2, Eqs. microS1 and microS2) and
+ *     the step order of Algorithm 1.
+ * Only f (h and b, or h alone in 3D) is stored per (cell, velocity); slopes
+ * and residuals of f live in registers for the duration of one step.
+ *
+ * Units: the gas constant is R = 1/2, so lambda = 1/(2 R T) = 1/T and
+ * p = rho T / 2.  The gas is monatomic (no internal degrees of freedom):
+ * in 2D the reduced distributions are h and b (one internal velocity
+ * component), in 3D only h.
+ *
+ * Conventions shared by all entry points:
+ *   - Every pointer argument is a HOST pointer unless stated otherwise.
+ *   - Inputs are read during the call only and copied to device memory; the
+ *     handle owns every device allocation, and ugks_destroy frees them.
+ *   - Status codes: 0 = success, negative = UGKS_ERR_*; no C++ exception
+ *     crosses the ABI.  ugks_last_error() returns the text of the last
+ *     failure on that handle (or of the last failed ugks_create when the
+ *     handle is NULL).
+ *   - All work of a handle is queued on the HIP stream given at creation;
+ *     entry points that return host data synchronise that stream.
+ */
+#ifndef UGKS_H
+#define UGKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UGKS_OK 0
+#define UGKS_ERR_ARG (-1)         /* invalid argument: sizes, pointers, mesh topology */
+#define UGKS_ERR_ALLOC (-2)       /* device or host allocation failed */
+#define UGKS_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define UGKS_ERR_NONPHYSICAL (-4) /* rho <= 0, T <= 0 or a non-finite value appeared */
+#define UGKS_ERR_STATE (-5)       /* call not valid in the handle's current state */
+
+/* face boundary types */
+#define UGKS_BC_INTERIOR 0 /* interior or periodic face: two cells */
+#define UGKS_BC_INFLOW 1   /* far field, ghost = bc_prim[face_bc_id] */
+#define UGKS_BC_OUTFLOW 2  /* far field, ghost = the interior cell's state */
+#define UGKS_BC_WALL 3     /* Maxwellian isothermal wall (U_w, T_w) = bc_prim[face_bc_id] */
+
+/* f storage precision; every macroscopic quantity and every coefficient is FP64 */
+#define UGKS_F64 0
+#define UGKS_F32 1
+
+/* Physical mesh (Section 2.3): finite volumes Omega_i with faces S_ij. */
+typedef struct {
+    int dim;                     /* 2 or 3 */
+    int n_cells, n_faces;
+    const double *cell_volume;   /* [n_cells] |Omega_i| (area in 2D) */
+    const double *cell_centroid; /* [n_cells][dim] */
+    const int *face_cells;       /* [n_faces][2]: left, right; right = -1 on a boundary */
+    const double *face_normal;   /* [n_faces][dim] unit, from left to right (outward on a boundary) */
+    const double *face_area;     /* [n_faces] S_ij (length in 2D) */
+    const double *face_centroid; /* [n_faces][dim], in the left cell's frame */
+    const double *face_shift;    /* [n_faces][dim] or NULL: added to the right cell's centroid
+                                    to place its periodic image next to the left cell */
+    const int *face_bc;          /* [n_faces] UGKS_BC_*, or NULL for all interior */
+    const int *face_bc_id;       /* [n_faces] row of ugks_gas_t.bc_prim, or NULL for 0 */
+} ugks_mesh_t;
+
+/* Discrete velocity space (Section 2.3): points u_k with weights V_k, so that
+ * int Q du = sum_k Q_k V_k.  A Cartesian (tensor-product) point set, with the
+ * last axis contiguous, is detected and uses separable exponentials. */
+typedef struct {
+    int dim;           /* must equal the mesh's */
+    int n_vel;
+    const double *u;   /* [n_vel][dim] */
+    const double *w;   /* [n_vel] V_k */
+} ugks_vgrid_t;
+
+/* Gas and scheme parameters. */
+typedef struct {
+    double Pr;          /* Prandtl number of the Shakhov model (1 = BGK) */
+    double omega;       /* viscosity exponent: mu = mu_ref T^omega, tau = mu / p */
+    double mu_ref;      /* viscosity at T = 1 */
+    double cfl;         /* CFL number of the time step */
+    double dt_override; /* > 0: use this time step instead of the CFL one */
+    double limiter_k;   /* Venkatakrishnan constant K: eps^2 = (K |Omega_i|^(1/dim))^3 */
+    int limiter;        /* 0 none (unlimited least squares), 1 Venkatakrishnan */
+    int fstore;         /* UGKS_F64 or UGKS_F32 storage of f */
+    int n_bc;
+    const double *bc_prim; /* [n_bc][dim+2]: (rho, U, T); walls use (U_w, T_w) */
+} ugks_gas_t;
+
+typedef struct ugks ugks_t;
+
+/* Create a case.  prim0 [n_cells][dim+2] holds the initial (rho, U, T) of
+ * each cell; f^0 is the discrete Maxwellian of it, and W^0 and q^0 are the
+ * discrete moments of f^0.  stream is a hipStream_t (NULL = default stream).
+ * The time step is fixed at creation (the velocity grid does not change):
+ * dt = cfl * min over cells and velocities of
+ *      |Omega_i| / sum_faces S max(0, u_k . n_outward).
+ * Returns UGKS_OK and *out, or an error code (*out = NULL). */
+int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas,
+                const double *prim0, void *stream, ugks_t **out);
+
+/* Advance nsteps time steps (Algorithm 1 each).  residual_out (nullable,
+ * [dim+2]) receives the L2 norm over cells of W^{n+1} - W^n of the last
+ * step, per conservative component.  Returns UGKS_ERR_NONPHYSICAL if a cell
+ * lost positivity or finiteness (checked once at the end of the call). */
+int ugks_step(ugks_t *h, int nsteps, double *residual_out);
+
+/* Copy the conservative variables W [n_cells][dim+2] = (rho, rho U, rho E)
+ * and the heat flux q [n_cells][dim] (nullable) to host memory. */
+int ugks_macros(ugks_t *h, double *W_out, double *q_out);
+
+/* Copy f to host memory as FP64 [n_cells][n_comp][n_vel] (n_comp = 2 in 2D:
+ * h then b; 1 in 3D). */
+int ugks_get_f(ugks_t *h, double *f_out);
+
+/* Replace f with a host array laid out as in ugks_get_f; W and q become its
+ * discrete moments (checkpoint restart or a non-equilibrium start). */
+int ugks_set_f(ugks_t *h, const double *f_in);
+
+double ugks_dt(const ugks_t *h);            /* time step, or -1 for a NULL handle */
+int ugks_n_comp(const ugks_t *h);           /* stored components per (cell, velocity) */
+long ugks_step_count(const ugks_t *h);      /* steps taken since creation */
+size_t ugks_footprint_bytes(const ugks_t *h); /* device bytes owned by the handle */
+int ugks_is_tensor_grid(const ugks_t *h);   /* 1 if the separable velocity path is used */
+
+/* Device pointer and layout of the current f (for zero-copy inspection):
+ * [n_cells][n_comp][n_vel] in the storage precision; valid until the next
+ * ugks_step or ugks_destroy. */
+const void *ugks_device_f(const ugks_t *h);
+
+void ugks_destroy(ugks_t *h);
+const char *ugks_last_error(const ugks_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

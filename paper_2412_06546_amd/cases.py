@@ -315,3 +315,11 @@ def n_comp(dim: int) -> int:
     (one internal velocity component), h only in 3D (no internal component
     for a monatomic gas, so b is identically zero)."""
     return 2 if dim == 2 else 1
+
+
+def case_cylinder_small(n_theta=40, n_r=16, n_tri_rings=2, nv=24, half_width=15.0, ma=5.0, kn=0.1,
+                        h_first=1e-2, seed=0, Pr=2.0 / 3.0):
+    """Cut-down of the hypersonic cylinder (same physics, wall, far field and
+    mixed quad/triangle mesh) that the oracle steps in about a second."""
+    return case_cylinder(n_theta=n_theta, n_r=n_r, n_tri_rings=n_tri_rings, nv=nv, half_width=half_width, ma=ma,
+                         kn=kn, h_first=h_first, seed=seed, Pr=Pr)

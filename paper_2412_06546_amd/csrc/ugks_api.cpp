@@ -1,0 +1,456 @@
+// ugks_api.cpp -- host side of the MI355X UGKS library: input validation,
+// mesh preprocessing (stencils, least-squares weights, limiter constants),
+// device memory, the CFL time step, and the C ABI declared in ugks.h.
+#include "../../include/ugks.h"
+#include "ugks_internal.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ugx;
+
+struct ugks {
+    int dim = 0, nc = 0, nf = 0, nv = 0, ncomp = 0, fstore = 0, nbc = 0;
+    hipStream_t stream = nullptr;
+    Params P{};
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *cgeo = nullptr, *fgeo = nullptr, *feq = nullptr;
+    double *u = nullptr, *w = nullptr, *bcp = nullptr, *W = nullptr, *q = nullptr, *gW = nullptr, *dW2 = nullptr;
+    double *cell_dt = nullptr, *res = nullptr;
+    int *err = nullptr;
+    double dt = 0.0;
+    long nstep = 0;
+    int tensor = 0;
+    size_t bytes = 0;
+    std::string msg;
+};
+
+static std::string g_create_error;
+
+namespace {
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+template <typename T> T *dev_alloc(ugks_t *h, size_t n)
+{
+    void *p = nullptr;
+    size_t b = sizeof(T) * (n ? n : 1);
+    if (hipMalloc(&p, b) != hipSuccess) throw Fail{UGKS_ERR_ALLOC, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    h->bytes += b;
+    return static_cast<T *>(p);
+}
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw Fail{UGKS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync H2D");
+}
+
+// A velocity set laid out as a Cartesian product with the last axis
+// contiguous: u_k = (x_a, y_b[, z_c]) at k = (a * ny + b) * nz + c.
+int detect_tensor(int D, int nv, const double *u)
+{
+    int n_last = 1;
+    while (n_last < nv && u[(size_t)n_last * D + 0] == u[0]) ++n_last;
+    if (D == 2) {
+        if (nv % n_last) return 0;
+        int na = nv / n_last;
+        for (int a = 0; a < na; ++a)
+            for (int b = 0; b < n_last; ++b) {
+                size_t k = (size_t)a * n_last + b;
+                if (u[k * 2] != u[(size_t)a * n_last * 2] || u[k * 2 + 1] != u[(size_t)b * 2 + 1]) return 0;
+            }
+        return 1;
+    }
+    int nz = 1;
+    while (nz < nv && u[(size_t)nz * 3 + 1] == u[1] && u[(size_t)nz * 3] == u[0]) ++nz;
+    if (nv % n_last || n_last % nz) return 0;
+    int ny = n_last / nz, nx = nv / n_last;
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int c = 0; c < nz; ++c) {
+                size_t k = ((size_t)a * ny + b) * nz + c;
+                if (u[k * 3] != u[(size_t)a * n_last * 3] || u[k * 3 + 1] != u[(size_t)b * nz * 3 + 1] ||
+                    u[k * 3 + 2] != u[(size_t)c * 3 + 2])
+                    return 0;
+            }
+    return 1;
+}
+
+template <int D>
+void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg, std::vector<FaceGeo<D>> &fgv,
+                    double limiter_k)
+{
+    constexpr int MF = Dim<D>::MF;
+    const int nc = m->n_cells, nf = m->n_faces;
+    cg.assign(nc, CellGeo<D>{});
+    fgv.assign(nf, FaceGeo<D>{});
+    std::vector<int> slot_count(nc, 0);
+    for (int f = 0; f < nf; ++f) {
+        const int l = m->face_cells[2 * f], r = m->face_cells[2 * f + 1];
+        const int bc = m->face_bc ? m->face_bc[f] : UGKS_BC_INTERIOR;
+        const int bid = m->face_bc_id ? m->face_bc_id[f] : 0;
+        if (l < 0 || l >= nc || r >= nc || r < -1) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": cell index out of range"};
+        if ((r < 0) != (bc != UGKS_BC_INTERIOR))
+            throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": boundary type does not match its cells"};
+        if (bc < 0 || bc > 3) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": unknown boundary type"};
+        if (bc != UGKS_BC_INTERIOR && bc != UGKS_BC_OUTFLOW && (bid < 0 || bid >= h->nbc))
+            throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": boundary state index out of range"};
+        if (!(m->face_area[f] > 0.0)) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": non-positive area"};
+        FaceGeo<D> &F = fgv[f];
+        F.l = l;
+        F.r = r;
+        F.bc = bc;
+        F.bcid = bid;
+        F.area = m->face_area[f];
+        for (int d = 0; d < D; ++d) {
+            const double sh = m->face_shift ? m->face_shift[(size_t)f * D + d] : 0.0;
+            F.n[d] = m->face_normal[(size_t)f * D + d];
+            F.dl[d] = m->face_centroid[(size_t)f * D + d] - m->cell_centroid[(size_t)l * D + d];
+            F.dr[d] = r >= 0 ? m->face_centroid[(size_t)f * D + d] - sh - m->cell_centroid[(size_t)r * D + d] : 0.0;
+        }
+        for (int s = 0; s < 2; ++s) {
+            const int c = s == 0 ? l : r;
+            if (c < 0) continue;
+            const int j = slot_count[c]++;
+            if (j >= MF) throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + " has more than " + std::to_string(MF) + " faces"};
+            CellGeo<D> &g = cg[c];
+            g.face[j] = f;
+            g.side[j] = s;
+            g.nb[j] = s == 0 ? r : l;
+            for (int d = 0; d < D; ++d) g.dvec[j][d] = s == 0 ? F.dl[d] : F.dr[d];
+        }
+    }
+    for (int c = 0; c < nc; ++c) {
+        CellGeo<D> &g = cg[c];
+        g.nf = slot_count[c];
+        if (g.nf < D + 1) throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + " has fewer than dim+1 faces"};
+        if (!(m->cell_volume[c] > 0.0)) throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + ": non-positive volume"};
+        g.inv_vol = 1.0 / m->cell_volume[c];
+        const double kh = limiter_k * std::pow(m->cell_volume[c], 1.0 / D);
+        g.eps2 = kh * kh * kh;
+        for (int j = g.nf; j < MF; ++j) {
+            g.face[j] = 0;
+            g.nb[j] = -1;
+            g.back[j] = 0;
+            g.side[j] = 0;
+        }
+        // least-squares normal matrix over face neighbours (periodic images)
+        double G[9] = {0}, dn[MF][D];
+        for (int j = 0; j < g.nf; ++j) {
+            const int n = g.nb[j];
+            for (int d = 0; d < D; ++d) dn[j][d] = 0.0;
+            if (n < 0) continue;
+            const int f = g.face[j];
+            for (int d = 0; d < D; ++d) {
+                const double sh = m->face_shift ? m->face_shift[(size_t)f * D + d] : 0.0;
+                dn[j][d] = m->cell_centroid[(size_t)n * D + d] + (g.side[j] == 0 ? sh : -sh) - m->cell_centroid[(size_t)c * D + d];
+            }
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) G[a * D + b] += dn[j][a] * dn[j][b];
+            // slot of the same face in the neighbour (the opposite side)
+            const CellGeo<D> &gn = cg[n];
+            int bj = -1;
+            for (int t = 0; t < slot_count[n]; ++t)
+                if (gn.face[t] == f && gn.side[t] != g.side[j]) bj = t;
+            if (bj < 0) throw Fail{UGKS_ERR_ARG, "inconsistent face adjacency at face " + std::to_string(f)};
+            g.back[j] = bj;
+        }
+        double Gi[9] = {0}, tr = 0.0, det;
+        for (int a = 0; a < D; ++a) tr += G[a * D + a];
+        const double tol = 1e-10 * std::pow(tr / D, D);
+        if (D == 2) {
+            det = G[0] * G[3] - G[1] * G[2];
+            if (det > tol) {
+                Gi[0] = G[3] / det;
+                Gi[1] = -G[1] / det;
+                Gi[2] = -G[2] / det;
+                Gi[3] = G[0] / det;
+            }
+        } else {
+            const double c00 = G[4] * G[8] - G[5] * G[7], c01 = G[5] * G[6] - G[3] * G[8], c02 = G[3] * G[7] - G[4] * G[6];
+            det = G[0] * c00 + G[1] * c01 + G[2] * c02;
+            if (det > tol) {
+                Gi[0] = c00 / det;
+                Gi[1] = (G[2] * G[7] - G[1] * G[8]) / det;
+                Gi[2] = (G[1] * G[5] - G[2] * G[4]) / det;
+                Gi[3] = c01 / det;
+                Gi[4] = (G[0] * G[8] - G[2] * G[6]) / det;
+                Gi[5] = (G[2] * G[3] - G[0] * G[5]) / det;
+                Gi[6] = c02 / det;
+                Gi[7] = (G[1] * G[6] - G[0] * G[7]) / det;
+                Gi[8] = (G[0] * G[4] - G[1] * G[3]) / det;
+            }
+        }
+        for (int j = 0; j < MF; ++j)
+            for (int a = 0; a < D; ++a) {
+                double s = 0.0;
+                if (j < g.nf)
+                    for (int b = 0; b < D; ++b) s += Gi[a * D + b] * dn[j][b];
+                g.lsq[j][a] = s;
+            }
+    }
+}
+
+template <int D> void create_d(ugks_t *h, const ugks_mesh_t *m, const ugks_gas_t *gas)
+{
+    std::vector<CellGeo<D>> cg;
+    std::vector<FaceGeo<D>> fgv;
+    build_geometry<D>(h, m, cg, fgv, gas->limiter_k);
+    h->cgeo = dev_alloc<CellGeo<D>>(h, cg.size());
+    h->fgeo = dev_alloc<FaceGeo<D>>(h, fgv.size());
+    h->feq = dev_alloc<FaceEq<D>>(h, fgv.size());
+    upload(h->cgeo, cg.data(), sizeof(CellGeo<D>) * cg.size(), h->stream);
+    upload(h->fgeo, fgv.data(), sizeof(FaceGeo<D>) * fgv.size(), h->stream);
+    hip_check(hipMemsetAsync(h->feq, 0, sizeof(FaceEq<D>) * fgv.size(), h->stream), "hipMemsetAsync");
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+}
+
+int fail(ugks_t *h, const Fail &e)
+{
+    if (h) h->msg = e.msg;
+    else g_create_error = e.msg;
+    return e.code;
+}
+
+void release(ugks_t *h)
+{
+    void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
+                    h->cell_dt, h->res, h->err};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas,
+                           const double *prim0, void *stream, ugks_t **out)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return UGKS_ERR_ARG;
+    }
+    *out = nullptr;
+    ugks_t *h = new (std::nothrow) ugks_t();
+    if (!h) {
+        g_create_error = "host allocation failed";
+        return UGKS_ERR_ALLOC;
+    }
+    try {
+        if (!mesh || !vgrid || !gas || !prim0) throw Fail{UGKS_ERR_ARG, "NULL argument"};
+        const int D = mesh->dim;
+        if (D != 2 && D != 3) throw Fail{UGKS_ERR_ARG, "dim must be 2 or 3"};
+        if (vgrid->dim != D) throw Fail{UGKS_ERR_ARG, "velocity grid and mesh dimensions differ"};
+        if (mesh->n_cells <= 0 || mesh->n_faces <= 0 || vgrid->n_vel <= 0)
+            throw Fail{UGKS_ERR_ARG, "empty mesh or velocity grid"};
+        if (vgrid->n_vel > 16384) throw Fail{UGKS_ERR_ARG, "more than 16384 discrete velocities"};
+        if (!mesh->cell_volume || !mesh->cell_centroid || !mesh->face_cells || !mesh->face_normal || !mesh->face_area ||
+            !mesh->face_centroid || !vgrid->u || !vgrid->w)
+            throw Fail{UGKS_ERR_ARG, "NULL mesh or velocity array"};
+        if (gas->fstore != UGKS_F64 && gas->fstore != UGKS_F32) throw Fail{UGKS_ERR_ARG, "fstore must be UGKS_F64 or UGKS_F32"};
+        if (!(gas->Pr > 0.0) || !(gas->mu_ref > 0.0) || !(gas->cfl > 0.0) || gas->limiter_k < 0.0)
+            throw Fail{UGKS_ERR_ARG, "Pr, mu_ref and cfl must be positive, limiter_k non-negative"};
+        if (gas->n_bc < 0 || (gas->n_bc > 0 && !gas->bc_prim)) throw Fail{UGKS_ERR_ARG, "bc_prim missing"};
+        h->dim = D;
+        h->nc = mesh->n_cells;
+        h->nf = mesh->n_faces;
+        h->nv = vgrid->n_vel;
+        h->ncomp = D == 2 ? 2 : 1;
+        h->fstore = gas->fstore;
+        h->nbc = gas->n_bc;
+        h->stream = static_cast<hipStream_t>(stream);
+        for (int i = 0; i < h->nc; ++i) {
+            const double *p = prim0 + (size_t)i * (D + 2);
+            if (!(p[0] > 0.0) || !(p[D + 1] > 0.0)) throw Fail{UGKS_ERR_ARG, "prim0: rho and T must be positive"};
+        }
+        if (D == 2) create_d<2>(h, mesh, gas);
+        else create_d<3>(h, mesh, gas);
+        h->tensor = detect_tensor(D, h->nv, vgrid->u);
+
+        const size_t nv = h->nv, nc = h->nc;
+        std::vector<double> uT((size_t)D * nv);
+        for (size_t k = 0; k < nv; ++k)
+            for (int d = 0; d < D; ++d) uT[(size_t)d * nv + k] = vgrid->u[k * D + d];
+        h->u = dev_alloc<double>(h, uT.size());
+        h->w = dev_alloc<double>(h, nv);
+        h->bcp = dev_alloc<double>(h, (size_t)std::max(1, h->nbc) * (D + 2));
+        h->W = dev_alloc<double>(h, nc * (D + 2));
+        h->q = dev_alloc<double>(h, nc * D);
+        h->gW = dev_alloc<double>(h, nc * (D + 2) * D);
+        h->dW2 = dev_alloc<double>(h, nc * (D + 2));
+        h->cell_dt = dev_alloc<double>(h, nc);
+        h->res = dev_alloc<double>(h, D + 2);
+        h->err = dev_alloc<int>(h, 2);
+        double *prim_d = dev_alloc<double>(h, nc * (D + 2));
+        const size_t fbytes = nc * h->ncomp * nv * (h->fstore ? sizeof(float) : sizeof(double));
+        for (int b = 0; b < 2; ++b) {
+            hip_check(hipMalloc(&h->f[b], fbytes), "hipMalloc of f");
+            h->bytes += fbytes;
+        }
+        upload(h->u, uT.data(), sizeof(double) * uT.size(), h->stream);
+        upload(h->w, vgrid->w, sizeof(double) * nv, h->stream);
+        if (h->nbc) upload(h->bcp, gas->bc_prim, sizeof(double) * h->nbc * (D + 2), h->stream);
+        upload(prim_d, prim0, sizeof(double) * nc * (D + 2), h->stream);
+        const int err0[2] = {0, 0x7fffffff};
+        upload(h->err, err0, sizeof(err0), h->stream);
+
+        Params &P = h->P;
+        P.dim = D;
+        P.fstore = h->fstore;
+        P.nc = h->nc;
+        P.nf = h->nf;
+        P.nv = h->nv;
+        P.Pr = gas->Pr;
+        P.omega = gas->omega;
+        P.mu_ref = gas->mu_ref;
+        P.limiter = gas->limiter ? 1 : 0;
+        P.cgeo = h->cgeo;
+        P.fgeo = h->fgeo;
+        P.feq = h->feq;
+        P.u = h->u;
+        P.w = h->w;
+        P.bc_prim = h->bcp;
+        P.W = h->W;
+        P.q = h->q;
+        P.gW = h->gW;
+        P.dW2 = h->dW2;
+        P.err = h->err;
+
+        // time step (Alg. 1 line 1), fixed for the run
+        hip_check(launch_cfl(P, h->cell_dt, h->stream), "k_cfl launch");
+        std::vector<double> cdt(nc);
+        hip_check(hipMemcpyAsync(cdt.data(), h->cell_dt, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream), "copy dt");
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        double mn = DBL_MAX;
+        for (double v : cdt) mn = std::min(mn, v);
+        h->dt = gas->dt_override > 0.0 ? gas->dt_override : gas->cfl * mn;
+        if (!(h->dt > 0.0) || h->dt >= DBL_MAX) throw Fail{UGKS_ERR_ARG, "could not form a time step"};
+        P.dt = h->dt;
+
+        hip_check(launch_init(P, prim_d, h->f[0], h->stream), "k_init launch");
+        hip_check(launch_moments(P, h->f[0], h->stream), "k_moments launch");
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        (void)hipFree(prim_d);
+        h->bytes -= sizeof(double) * nc * (D + 2);
+    } catch (const Fail &e) {
+        int code = fail(nullptr, e);
+        release(h);
+        delete h;
+        return code;
+    }
+    *out = h;
+    return UGKS_OK;
+}
+
+extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
+{
+    if (!h) return UGKS_ERR_ARG;
+    if (nsteps < 0) return fail(h, Fail{UGKS_ERR_ARG, "nsteps < 0"});
+    try {
+        for (int s = 0; s < nsteps; ++s) {
+            hip_check(launch_step(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "step launch");
+            h->cur ^= 1;
+            h->nstep++;
+        }
+        int err[2];
+        hip_check(hipMemcpyAsync(err, h->err, sizeof(err), hipMemcpyDeviceToHost, h->stream), "copy error flag");
+        if (residual_out && nsteps > 0) {
+            hip_check(launch_residual(h->P, h->res, h->stream), "residual launch");
+            hip_check(hipMemcpyAsync(residual_out, h->res, sizeof(double) * (h->dim + 2), hipMemcpyDeviceToHost, h->stream),
+                      "copy residual");
+        }
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (err[0]) return fail(h, Fail{UGKS_ERR_NONPHYSICAL, "non-physical state (rho <= 0, T <= 0 or non-finite) first at cell " + std::to_string(err[1])});
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_macros(ugks_t *h, double *W_out, double *q_out)
+{
+    if (!h) return UGKS_ERR_ARG;
+    try {
+        if (W_out)
+            hip_check(hipMemcpyAsync(W_out, h->W, sizeof(double) * h->nc * (h->dim + 2), hipMemcpyDeviceToHost, h->stream), "copy W");
+        if (q_out) hip_check(hipMemcpyAsync(q_out, h->q, sizeof(double) * h->nc * h->dim, hipMemcpyDeviceToHost, h->stream), "copy q");
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_get_f(ugks_t *h, double *f_out)
+{
+    if (!h || !f_out) return UGKS_ERR_ARG;
+    try {
+        const size_t n = (size_t)h->nc * h->ncomp * h->nv;
+        if (h->fstore == UGKS_F64) {
+            hip_check(hipMemcpyAsync(f_out, h->f[h->cur], sizeof(double) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        } else {
+            std::vector<float> tmp(n);
+            hip_check(hipMemcpyAsync(tmp.data(), h->f[h->cur], sizeof(float) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+            for (size_t i = 0; i < n; ++i) f_out[i] = tmp[i];
+        }
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
+{
+    if (!h || !f_in) return UGKS_ERR_ARG;
+    try {
+        const size_t n = (size_t)h->nc * h->ncomp * h->nv;
+        if (h->fstore == UGKS_F64) {
+            upload(h->f[h->cur], f_in, sizeof(double) * n, h->stream);
+            hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        } else {
+            std::vector<float> tmp(n);
+            for (size_t i = 0; i < n; ++i) tmp[i] = (float)f_in[i];
+            upload(h->f[h->cur], tmp.data(), sizeof(float) * n, h->stream);
+            hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        }
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" double ugks_dt(const ugks_t *h) { return h ? h->dt : -1.0; }
+extern "C" int ugks_n_comp(const ugks_t *h) { return h ? h->ncomp : 0; }
+extern "C" long ugks_step_count(const ugks_t *h) { return h ? h->nstep : -1; }
+extern "C" size_t ugks_footprint_bytes(const ugks_t *h) { return h ? h->bytes : 0; }
+extern "C" int ugks_is_tensor_grid(const ugks_t *h) { return h ? h->tensor : 0; }
+extern "C" const void *ugks_device_f(const ugks_t *h) { return h ? h->f[h->cur] : nullptr; }
+
+extern "C" void ugks_destroy(ugks_t *h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    release(h);
+    delete h;
+}
+
+extern "C" const char *ugks_last_error(const ugks_t *h) { return h ? h->msg.c_str() : g_create_error.c_str(); }

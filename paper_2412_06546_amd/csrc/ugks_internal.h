@@ -1,0 +1,85 @@
+// ugks_internal.h -- device data layout and launch interface shared by the
+// host library (ugks_api.cpp) and the gfx950 kernels (ugks_kernels.hip).
+// Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ugx {
+
+// Faces per cell: 2D triangles/quads (<= 4), 3D tets/prisms/hexes (<= 6).
+template <int D> struct Dim;
+template <> struct Dim<2> {
+    static constexpr int MF = 4;  // max faces per cell
+    static constexpr int NC = 2;  // stored components: h, b
+    static constexpr int M = 1;   // internal velocity components (xi)
+    static constexpr int NW = 4;  // conservative variables
+};
+template <> struct Dim<3> {
+    static constexpr int MF = 6;
+    static constexpr int NC = 1;  // b is identically zero without internal components
+    static constexpr int M = 0;
+    static constexpr int NW = 5;
+};
+
+// Per-cell stencil record, read with wave-uniform (scalar) loads.
+template <int D> struct alignas(16) CellGeo {
+    static constexpr int MF = Dim<D>::MF;
+    int nf;          // faces of the cell
+    int face[MF];    // face index per slot
+    int nb[MF];      // neighbour across the slot's face, -1 on a boundary
+    int back[MF];    // slot index of this face in the neighbour's record
+    int side[MF];    // 0: the cell is the face's left cell, 1: right
+    double inv_vol;  // 1 / |Omega_i|
+    double eps2;     // Venkatakrishnan epsilon^2
+    double dvec[MF][D];  // centroid -> face centroid, in this cell's frame
+    double lsq[MF][D];   // least-squares weights: grad = sum_j lsq_j (f_j - f_i)
+};
+
+template <int D> struct alignas(16) FaceGeo {
+    int l, r, bc, bcid;
+    double n[D];   // unit normal, left -> right
+    double area;
+    double dl[D];  // left centroid -> face centroid
+    double dr[D];  // right centroid (its periodic image) -> face centroid
+};
+
+// Interface equilibrium (Alg. 1 line 3).  For boundary faces only
+// (rho, U, lam) and pref are used: ghost Maxwellian (inflow), wall Maxwellian
+// with unit density (wall).
+template <int D> struct alignas(16) FaceEq {
+    static constexpr int NW = D + 2;
+    double rho, U[D], lam;
+    double pref;          // rho (lam/pi)^{D/2}
+    double shk;           // 4 (1 - Pr) lam^2 / (5 rho)
+    double a[D][NW];      // spatial slopes of g0
+    double A[NW];         // time slope of g0
+    double q[D];          // interface heat flux
+    double c[5];          // time integrals of c1..c5 over the step
+};
+
+struct Params {
+    int dim, fstore;
+    int nc, nf, nv;
+    double dt, Pr, omega, mu_ref;
+    int limiter;
+    // device arrays
+    const void *cgeo, *fgeo;
+    void *feq;
+    const double *u;   // [dim][nv] (structure of arrays)
+    const double *w;   // [nv]
+    const double *bc_prim;  // [n_bc][dim+2]
+    double *W, *q;     // [nc][dim+2], [nc][dim]
+    double *gW;        // [nc][dim+2][dim] limited gradients of W
+    double *dW2;       // [nc][dim+2] squared change of W in the last step
+    int *err;          // [2]: flag, first bad cell
+};
+
+hipError_t launch_cfl(const Params &p, double *cell_dt, hipStream_t s);
+hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_t s);
+hipError_t launch_moments(const Params &p, const void *f, hipStream_t s);
+hipError_t launch_step(const Params &p, const void *f_in, void *f_out, hipStream_t s);
+hipError_t launch_residual(const Params &p, double *out, hipStream_t s);
+
+}  // namespace ugx

@@ -1,0 +1,938 @@
+// ugks_kernels.hip -- gfx950 kernels of the memory-saving UGKS time step.
+//
+// Reference: Zhang, Wei, Long, Xu, "An efficiency and memory-saving
+// programming paradigm for the unified gas-kinetic scheme", arXiv:2412.06546.
+//
+// One step (Algorithm 1 of Section 3.2) is three launches on one stream:
+//   k_cell_grad  per cell:  limited least-squares gradient of W (line 2)
+//   k_face_eq    per face:  interface equilibrium g0, its space and time
+//                           slopes, heat flux and time integrals (line 3)
+//   k_sweep      per cell, one workgroup owning the cell's whole velocity
+//                slab (lines 4-11 fused): for every velocity the limited
+//                slope of f is rebuilt in registers (own cell, and upwind
+//                neighbours when the neighbour is upwind), the interface
+//                flux of Eq. fullSolution is integrated over the step, the
+//                stage-1 value of Eq. microS1 is kept in registers, the wall
+//                density is reduced over velocities, W^{n+1} and q^{n+1}
+//                come from workgroup reductions of the same registers, and
+//                stage 2 (Eq. microS2) is applied before the single store.
+// f is stored [cell][component][velocity]; lanes run over velocities, so a
+// wavefront reads 64 consecutive velocities of one cell (coalesced) and all
+// geometry and face data are wave-uniform (scalar loads).  f is read from
+// one buffer and written to the other (ping-pong): no slope or residual of f
+// ever reaches memory.
+#include "ugks_internal.h"
+
+#include <cfloat>
+#include <cmath>
+
+namespace ugx {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int N_DOF = 3;  // translational + internal degrees of freedom (monatomic)
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+template <int D> __device__ __forceinline__ double pow_lam_pi(double lam)
+{
+    double r = lam / kPi;
+    if constexpr (D == 2) return r;
+    else return r * sqrt(r);
+}
+
+template <int BS, int N, typename Op>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double *lds, Op op)
+{
+    // butterfly inside the wavefront, then the wavefront results in fixed order
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[n] = op(v[n], __shfl_xor(v[n], off, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int n = 0; n < N; ++n) lds[wid * N + n] = v[n];
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double s = lds[n];
+#pragma unroll
+        for (int w = 1; w < BS / 64; ++w) s = op(s, lds[w * N + n]);
+        v[n] = s;
+    }
+    __syncthreads();
+}
+
+struct OpAdd {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMax {
+    __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+
+template <int D> struct Prim {
+    double rho, U[D], lam;
+};
+
+template <int D> __device__ __forceinline__ Prim<D> to_prim(const double *W)
+{
+    Prim<D> p;
+    p.rho = W[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        p.U[d] = W[1 + d] / p.rho;
+        ke += p.U[d] * p.U[d];
+    }
+    p.lam = N_DOF * p.rho / (4.0 * (W[D + 1] - 0.5 * p.rho * ke));
+    return p;
+}
+
+__device__ __forceinline__ double collision_time(double rho, double lam, double mu_ref, double omega)
+{
+    double T = 1.0 / lam;
+    return mu_ref * pow(T, omega) / (0.5 * rho * T);
+}
+
+// Reduced Maxwellian and Shakhov correction at u (Section 2.2):
+// H = pref e^{-lam c^2}, B = M/(2 lam) H,
+// H+ = shk (c.q)(2 lam c^2 - 2 - D) H, B+ = shk (c.q)(2 lam c^2 - D) M H / (2 lam)
+template <int D>
+__device__ __forceinline__ void equilibrium(const double (&u)[D], const double (&U)[D], double lam, double pref,
+                                            double shk, const double (&q)[D], double &Hp, double &Bp)
+{
+    constexpr int M = Dim<D>::M;
+    double c2 = 0.0, cq = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double c = u[d] - U[d];
+        c2 += c * c;
+        cq += c * q[d];
+    }
+    double H = pref * exp(-lam * c2);
+    double s = shk * cq;
+    Hp = H + s * (2.0 * lam * c2 - 2.0 - D) * H;
+    if constexpr (M > 0) {
+        double B = (M / (2.0 * lam)) * H;
+        Bp = B + s * (2.0 * lam * c2 - D) * B;
+    } else {
+        Bp = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// limited least-squares slope of f_k in cell c (Section 3.1, step 2)
+// ------------------------------------------------------------------------
+template <int D, typename FT>
+__device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const FT *__restrict__ f, int nv, int k,
+                                              int limiter, double (&fc)[Dim<D>::NC], double (&gr)[Dim<D>::NC][D])
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
+    double fmx[NC], fmn[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        fc[m] = static_cast<double>(f[((size_t)c * NC + m) * nv + k]);
+        fmx[m] = fmn[m] = fc[m];
+#pragma unroll
+        for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
+    }
+    const int nf = g.nf;
+#pragma unroll
+    for (int j = 0; j < MF; ++j) {
+        if (j >= nf) break;
+        const int n = g.nb[j];
+        if (n < 0) continue;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            double fj = static_cast<double>(f[((size_t)n * NC + m) * nv + k]);
+            double df = fj - fc[m];
+#pragma unroll
+            for (int d = 0; d < D; ++d) gr[m][d] += g.lsq[j][d] * df;
+            fmx[m] = fmax(fmx[m], fj);
+            fmn[m] = fmin(fmn[m], fj);
+        }
+    }
+    if (!limiter) return;
+    // phi = min(1, min_faces phi_f), compared as fractions to avoid one
+    // division per face
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        double bn = 1.0, bd = 1.0;
+#pragma unroll
+        for (int j = 0; j < MF; ++j) {
+            if (j >= nf) break;
+            double dm = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) dm += gr[m][d] * g.dvec[j][d];
+            if (dm == 0.0) continue;
+            double dp = dm > 0.0 ? fmx[m] - fc[m] : fmn[m] - fc[m];
+            double num = dp * dp + g.eps2 + 2.0 * dm * dp;
+            double den = dp * dp + 2.0 * dm * dm + dm * dp + g.eps2;
+            if (num * bd < bn * den) {
+                bn = num;
+                bd = den;
+            }
+        }
+        double phi = bn / bd;
+#pragma unroll
+        for (int d = 0; d < D; ++d) gr[m][d] *= phi;
+    }
+}
+
+// Time-integrated interface value of h (and b) at velocity u (Eq. fullSolution
+// integrated over [0, dt]); val is the upwind reconstruction at the face and
+// ug = u . grad of the upwind cell.
+template <int D>
+__device__ __forceinline__ void interface_integral(const FaceEq<D> &e, const double (&u)[D], double u2, double Pr,
+                                                   const double (&val)[Dim<D>::NC], const double (&ug)[Dim<D>::NC],
+                                                   double (&I)[Dim<D>::NC])
+{
+    constexpr int M = Dim<D>::M, NW = D + 2;
+    double c2 = 0.0, cq = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double c = u[d] - e.U[d];
+        c2 += c * c;
+        cq += c * e.q[d];
+    }
+    const double lam = e.lam;
+    const double H0 = e.pref * exp(-lam * c2);
+    const double s = e.shk * cq;
+    const double eqH = H0 + s * (2.0 * lam * c2 - 2.0 - D) * H0;
+    double Pd = 0.0, Ed = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double pa = e.a[d][0] + 0.5 * e.a[d][NW - 1] * u2;
+#pragma unroll
+        for (int c = 0; c < D; ++c) pa += e.a[d][1 + c] * u[c];
+        Pd += u[d] * pa;
+        Ed += u[d] * e.a[d][NW - 1];
+    }
+    double PA = e.A[0] + 0.5 * e.A[NW - 1] * u2;
+#pragma unroll
+    for (int c = 0; c < D; ++c) PA += e.A[1 + c] * u[c];
+    if constexpr (M > 0) {
+        const double B0 = (M / (2.0 * lam)) * H0;
+        const double eqB = B0 + s * (2.0 * lam * c2 - D) * B0;
+        const double xi4 = (M * (M + 2) / (4.0 * lam * lam)) * H0;  // int xi^4 g0 dxi
+        const double gH = Pd * H0 + 0.5 * Ed * B0, gB = Pd * B0 + 0.5 * Ed * xi4;
+        const double tH = PA * H0 + 0.5 * e.A[NW - 1] * B0, tB = PA * B0 + 0.5 * e.A[NW - 1] * xi4;
+        I[0] = e.c[0] * val[0] + e.c[1] * ug[0] + e.c[2] * eqH + e.c[3] * gH + e.c[4] * tH;
+        I[1] = e.c[0] * val[1] + e.c[1] * ug[1] + e.c[2] * eqB + e.c[3] * gB + e.c[4] * tB;
+    } else {
+        const double gH = Pd * H0, tH = PA * H0;
+        I[0] = e.c[0] * val[0] + e.c[1] * ug[0] + e.c[2] * eqH + e.c[3] * gH + e.c[4] * tH;
+    }
+}
+
+// ------------------------------------------------------------------------
+// time step: per cell, the largest upwind outflow over the velocities
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_cfl(Params p, double *cell_dt)
+{
+    const int i = blockIdx.x;
+    const CellGeo<D> &g = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    double mx[1] = {0.0};
+    for (int k = threadIdx.x; k < p.nv; k += 256) {
+        double out = 0.0;
+        for (int j = 0; j < g.nf; ++j) {
+            const FaceGeo<D> &F = fg[g.face[j]];
+            double un = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) un += p.u[d * p.nv + k] * F.n[d];
+            if (g.side[j]) un = -un;
+            if (un > 0.0) out += F.area * un;
+        }
+        mx[0] = fmax(mx[0], out);
+    }
+    __shared__ double lds[4];
+    block_reduce<256>(mx, lds, OpMax{});
+    if (threadIdx.x == 0) cell_dt[i] = mx[0] > 0.0 ? (1.0 / g.inv_vol) / mx[0] : DBL_MAX;
+}
+
+// ------------------------------------------------------------------------
+// initial state: discrete Maxwellian of (rho, U, T)
+// ------------------------------------------------------------------------
+template <int D, typename FT>
+__global__ __launch_bounds__(256) void k_init(Params p, const double *__restrict__ prim0, FT *__restrict__ f)
+{
+    constexpr int NC = Dim<D>::NC;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)p.nc * p.nv) return;
+    const int i = (int)(t / p.nv), k = (int)(t % p.nv);
+    const double *pr = prim0 + (size_t)i * (D + 2);
+    double u[D], U[D], zq[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        u[d] = p.u[d * p.nv + k];
+        U[d] = pr[1 + d];
+        zq[d] = 0.0;
+    }
+    const double lam = 1.0 / pr[D + 1];
+    double H, B;
+    equilibrium<D>(u, U, lam, pr[0] * pow_lam_pi<D>(lam), 0.0, zq, H, B);
+    f[((size_t)i * NC + 0) * p.nv + k] = static_cast<FT>(H);
+    if constexpr (NC > 1) f[((size_t)i * NC + 1) * p.nv + k] = static_cast<FT>(B);
+}
+
+// ------------------------------------------------------------------------
+// W and q as direct discrete moments of f (start, or after a set_f)
+// ------------------------------------------------------------------------
+template <int D, typename FT>
+__global__ __launch_bounds__(256) void k_moments(Params p, const FT *__restrict__ f)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2;
+    const int i = blockIdx.x;
+    __shared__ double lds[4 * NW];
+    double m[NW];
+#pragma unroll
+    for (int n = 0; n < NW; ++n) m[n] = 0.0;
+    for (int k = threadIdx.x; k < p.nv; k += 256) {
+        double h = static_cast<double>(f[((size_t)i * NC) * p.nv + k]);
+        double b = NC > 1 ? static_cast<double>(f[((size_t)i * NC + NC - 1) * p.nv + k]) : 0.0;
+        double w = p.w[k], u2 = 0.0;
+        m[0] += w * h;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double ud = p.u[d * p.nv + k];
+            m[1 + d] += w * ud * h;
+            u2 += ud * ud;
+        }
+        m[NW - 1] += w * 0.5 * (u2 * h + b);
+    }
+    block_reduce<256>(m, lds, OpAdd{});
+    Prim<D> pr = to_prim<D>(m);
+    double qq[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qq[d] = 0.0;
+    for (int k = threadIdx.x; k < p.nv; k += 256) {
+        double h = static_cast<double>(f[((size_t)i * NC) * p.nv + k]);
+        double b = NC > 1 ? static_cast<double>(f[((size_t)i * NC + NC - 1) * p.nv + k]) : 0.0;
+        double c[D], c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            c[d] = p.u[d * p.nv + k] - pr.U[d];
+            c2 += c[d] * c[d];
+        }
+        double wt = 0.5 * p.w[k] * (c2 * h + b);
+#pragma unroll
+        for (int d = 0; d < D; ++d) qq[d] += wt * c[d];
+    }
+    block_reduce<256>(qq, lds, OpAdd{});
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int n = 0; n < NW; ++n) p.W[(size_t)i * NW + n] = m[n];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.q[(size_t)i * D + d] = qq[d];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Alg. 1 line 2: limited gradients of the conservative variables
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_cell_grad(Params p)
+{
+    constexpr int NW = D + 2, MF = Dim<D>::MF;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= p.nc) return;
+    const CellGeo<D> &g = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    double gr[NW][D], Wi[NW];
+    for (int m = 0; m < NW; ++m) {
+        Wi[m] = p.W[(size_t)i * NW + m];
+        double mx = Wi[m], mn = Wi[m];
+        for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
+        for (int j = 0; j < g.nf; ++j) {
+            int n = g.nb[j];
+            if (n < 0) continue;
+            double wj = p.W[(size_t)n * NW + m];
+            for (int d = 0; d < D; ++d) gr[m][d] += g.lsq[j][d] * (wj - Wi[m]);
+            mx = fmax(mx, wj);
+            mn = fmin(mn, wj);
+        }
+        if (p.limiter) {
+            double phi = 1.0;
+            for (int j = 0; j < g.nf; ++j) {
+                double dm = 0.0;
+                for (int d = 0; d < D; ++d) dm += gr[m][d] * g.dvec[j][d];
+                if (dm == 0.0) continue;
+                double dp = dm > 0.0 ? mx - Wi[m] : mn - Wi[m];
+                double ph = (dp * dp + g.eps2 + 2.0 * dm * dp) / (dp * dp + 2.0 * dm * dm + dm * dp + g.eps2);
+                phi = fmin(phi, ph);
+            }
+            for (int d = 0; d < D; ++d) gr[m][d] *= phi;
+        }
+    }
+    // first order where a reconstructed face state is not physical
+    bool bad = false;
+    for (int j = 0; j < g.nf; ++j) {
+        double Wf[NW], ke = 0.0;
+        for (int m = 0; m < NW; ++m) {
+            Wf[m] = Wi[m];
+            for (int d = 0; d < D; ++d) Wf[m] += gr[m][d] * g.dvec[j][d];
+        }
+        for (int d = 0; d < D; ++d) ke += Wf[1 + d] * Wf[1 + d];
+        if (!(Wf[0] > 0.0) || !(Wf[NW - 1] - 0.5 * ke / Wf[0] > 0.0)) bad = true;
+    }
+    (void)MF;
+    for (int m = 0; m < NW; ++m)
+        for (int d = 0; d < D; ++d) p.gW[((size_t)i * NW + m) * D + d] = bad ? 0.0 : gr[m][d];
+}
+
+// ------------------------------------------------------------------------
+// Alg. 1 line 3: interface equilibrium state and time coefficients
+// ------------------------------------------------------------------------
+// Solve <psi (a . psi)>_{g} = Delta for a Maxwellian (rho-normalised
+// moments, N = 3 degrees of freedom), in closed form.
+template <int D>
+__device__ void slope_solve(const double (&U)[D], double lam, const double *Dl, double *a)
+{
+    constexpr int NW = D + 2;
+    double U2 = 0.0, UR = 0.0, R[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        U2 += U[d] * U[d];
+        R[d] = Dl[1 + d] - U[d] * Dl[0];
+        UR += U[d] * R[d];
+    }
+    const double K2 = U2 + N_DOF / (2.0 * lam);
+    const double RE = 2.0 * Dl[NW - 1] - K2 * Dl[0];
+    const double aE = (4.0 * lam * lam / N_DOF) * (RE - 2.0 * UR);
+    double Ua = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        a[1 + d] = 2.0 * lam * R[d] - U[d] * aE;
+        Ua += U[d] * a[1 + d];
+    }
+    a[NW - 1] = aE;
+    a[0] = Dl[0] - Ua - 0.5 * aE * K2;
+}
+
+// -sum_d <psi u_d (a^d . psi)>_g  (Gaussian moments to fifth order)
+template <int D>
+__device__ void compat_rhs(const double (&U)[D], double lam, const double (*a)[D + 2], double *r)
+{
+    constexpr int NW = D + 2, N = N_DOF;
+    const double s = 1.0 / (2.0 * lam);
+    double U2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) U2 += U[d] * U[d];
+    const double E = 0.5 * (U2 + N * s);
+    const double c4 = U2 + (N + 4) * s, c2 = s * (U2 + (N + 2) * s);
+    const double e2 = 0.25 * (U2 * U2 + 2.0 * (N + 4) * s * U2 + (N + 2) * (N + 4) * s * s);
+    for (int m = 0; m < NW; ++m) r[m] = 0.0;
+    for (int d = 0; d < D; ++d) {
+        const double *ad = a[d];
+        const double a0 = ad[0], aE = ad[NW - 1];
+        // row 0
+        double t = U[d] * a0 + U[d] * (E + s) * aE;
+        for (int c = 0; c < D; ++c) t += (U[c] * U[d] + (c == d ? s : 0.0)) * ad[1 + c];
+        r[0] -= t;
+        // momentum rows
+        for (int b = 0; b < D; ++b) {
+            double tb = (U[b] * U[d] + (b == d ? s : 0.0)) * a0;
+            for (int c = 0; c < D; ++c) {
+                double m3 = U[b] * U[c] * U[d] +
+                            s * ((c == d ? U[b] : 0.0) + (b == d ? U[c] : 0.0) + (b == c ? U[d] : 0.0));
+                tb += m3 * ad[1 + c];
+            }
+            tb += 0.5 * (U[b] * U[d] * c4 + (b == d ? c2 : 0.0)) * aE;
+            r[1 + b] -= tb;
+        }
+        // energy row
+        double te = U[d] * (E + s) * a0 + U[d] * e2 * aE;
+        for (int c = 0; c < D; ++c) te += 0.5 * (U[c] * U[d] * c4 + (c == d ? c2 : 0.0)) * ad[1 + c];
+        r[NW - 1] -= te;
+    }
+}
+
+__device__ void time_integrals(double dt, double tau, double *c)
+{
+    const double x = dt / tau;
+    if (x < 1.0) {
+        // Taylor series (the closed forms cancel catastrophically for small x)
+        double term[31];
+        term[0] = 1.0;
+        for (int m = 1; m <= 30; ++m) term[m] = term[m - 1] * x / m;
+        double s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+        for (int m = 30; m >= 1; --m) {
+            const double t = (m & 1) ? term[m] : -term[m];
+            s1 += t;
+            if (m >= 2) {
+                s2 += (m - 1) * t;
+                s3 -= t;
+            }
+            if (m >= 3) {
+                s4 -= (m - 2) * t;
+                s5 += t;
+            }
+        }
+        c[0] = tau * s1;
+        c[1] = tau * tau * s2;
+        c[2] = tau * s3;
+        c[3] = tau * tau * s4;
+        c[4] = tau * tau * s5;
+    } else {
+        const double e = exp(-x), ome = -expm1(-x);
+        c[0] = tau * ome;
+        c[1] = tau * dt * e - tau * tau * ome;
+        c[2] = dt - tau * ome;
+        c[3] = 2.0 * tau * tau * ome - tau * dt * (1.0 + e);
+        c[4] = 0.5 * dt * dt - tau * dt + tau * tau * ome;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(128) void k_face_eq(Params p)
+{
+    constexpr int NW = D + 2;
+    const int f = blockIdx.x * 128 + threadIdx.x;
+    if (f >= p.nf) return;
+    const FaceGeo<D> &F = static_cast<const FaceGeo<D> *>(p.fgeo)[f];
+    FaceEq<D> &e = static_cast<FaceEq<D> *>(p.feq)[f];
+    if (F.bc != 0) {
+        // boundary: store the Maxwellian the incoming particles come from
+        double rho, U[D], lam;
+        if (F.bc == 2) {
+            Prim<D> pr = to_prim<D>(p.W + (size_t)F.l * NW);
+            rho = pr.rho;
+            lam = pr.lam;
+            for (int d = 0; d < D; ++d) U[d] = pr.U[d];
+        } else {
+            const double *bp = p.bc_prim + (size_t)F.bcid * NW;
+            rho = F.bc == 3 ? 1.0 : bp[0];
+            for (int d = 0; d < D; ++d) U[d] = bp[1 + d];
+            lam = 1.0 / bp[NW - 1];
+        }
+        e.rho = rho;
+        e.lam = lam;
+        for (int d = 0; d < D; ++d) e.U[d] = U[d];
+        e.pref = rho * pow_lam_pi<D>(lam);
+        e.shk = 0.0;
+        return;
+    }
+    // reconstructed states on both sides
+    double Wl[NW], Wr[NW];
+    for (int m = 0; m < NW; ++m) {
+        Wl[m] = p.W[(size_t)F.l * NW + m];
+        Wr[m] = p.W[(size_t)F.r * NW + m];
+        for (int d = 0; d < D; ++d) {
+            Wl[m] += p.gW[((size_t)F.l * NW + m) * D + d] * F.dl[d];
+            Wr[m] += p.gW[((size_t)F.r * NW + m) * D + d] * F.dr[d];
+        }
+    }
+    // W0 from the two half-Maxwellians in the face-normal frame
+    double W0[NW];
+    for (int m = 0; m < NW; ++m) W0[m] = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        Prim<D> pr = to_prim<D>(side == 0 ? Wl : Wr);
+        double Un = 0.0;
+        for (int d = 0; d < D; ++d) Un += pr.U[d] * F.n[d];
+        double Ut[D], ut2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+            Ut[d] = pr.U[d] - Un * F.n[d];
+            ut2 += Ut[d] * Ut[d];
+        }
+        const double t = sqrt(pr.lam) * Un;
+        const double g = exp(-pr.lam * Un * Un) / (2.0 * sqrt(kPi * pr.lam));
+        double m0, m1;
+        if (side == 0) {
+            m0 = 0.5 * erfc(-t);
+            m1 = Un * m0 + g;
+        } else {
+            m0 = 0.5 * erfc(t);
+            m1 = Un * m0 - g;
+        }
+        const double m2 = Un * m1 + m0 / (2.0 * pr.lam);
+        W0[0] += pr.rho * m0;
+        for (int d = 0; d < D; ++d) W0[1 + d] += pr.rho * (m1 * F.n[d] + Ut[d] * m0);
+        W0[NW - 1] += 0.5 * pr.rho * (m2 + (ut2 + (N_DOF - 1) / (2.0 * pr.lam)) * m0);
+    }
+    Prim<D> p0 = to_prim<D>(W0);
+    e.rho = p0.rho;
+    e.lam = p0.lam;
+    for (int d = 0; d < D; ++d) e.U[d] = p0.U[d];
+    e.pref = p0.rho * pow_lam_pi<D>(p0.lam);
+    e.shk = 4.0 * (1.0 - p.Pr) * p0.lam * p0.lam / (5.0 * p0.rho);
+    // spatial slopes from the averaged limited gradients
+    for (int d = 0; d < D; ++d) {
+        double Dl[NW];
+        for (int m = 0; m < NW; ++m)
+            Dl[m] = 0.5 * (p.gW[((size_t)F.l * NW + m) * D + d] + p.gW[((size_t)F.r * NW + m) * D + d]) / p0.rho;
+        slope_solve<D>(p0.U, p0.lam, Dl, e.a[d]);
+    }
+    double rhs[NW];
+    compat_rhs<D>(p0.U, p0.lam, e.a, rhs);
+    slope_solve<D>(p0.U, p0.lam, rhs, e.A);
+    for (int d = 0; d < D; ++d) e.q[d] = 0.5 * (p.q[(size_t)F.l * D + d] + p.q[(size_t)F.r * D + d]);
+    const double tau0 = collision_time(p0.rho, p0.lam, p.mu_ref, p.omega);
+    time_integrals(p.dt, tau0, e.c);
+}
+
+// ------------------------------------------------------------------------
+// Alg. 1 lines 4-11, fused: the sweep over one cell's velocity slab
+// ------------------------------------------------------------------------
+template <int D, typename FT, int BS, int VPT>
+__global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
+    const int i = blockIdx.x;
+    const int tid = threadIdx.x;
+    const CellGeo<D> *cg = static_cast<const CellGeo<D> *>(p.cgeo);
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
+    const CellGeo<D> &gi = cg[i];
+    const int nv = p.nv, nf = gi.nf;
+    const double dt = p.dt, Pr = p.Pr;
+    __shared__ double lds[(BS / 64) * (2 * MF > NW ? 2 * MF : NW)];
+
+    // state at t^n
+    double Wn[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
+    const Prim<D> pn = to_prim<D>(Wn);
+    const double tau_n = collision_time(pn.rho, pn.lam, p.mu_ref, p.omega);
+    double qn[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qn[d] = p.q[(size_t)i * D + d];
+    const double pref_n = pn.rho * pow_lam_pi<D>(pn.lam);
+    const double shk_n = 4.0 * (1.0 - Pr) * pn.lam * pn.lam / (5.0 * pn.rho);
+    const double hdt_tau = 0.5 * dt / tau_n;
+
+    int has_wall = 0;
+    for (int j = 0; j < nf; ++j) has_wall |= (fg[gi.face[j]].bc == 3);
+
+    double acc[VPT][NC];
+    double mom[NW];
+    double wsum[2 * MF];  // per slot: incident mass flux, reflected unit-density flux
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2 * MF; ++j) wsum[j] = 0.0;
+
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+        const int k = s * BS + tid;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[s][c] = 0.0;
+        if (s * BS >= nv) continue;
+        if (k < nv) {
+            double u[D], u2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                u[d] = p.u[d * nv + k];
+                u2 += u[d] * u[d];
+            }
+            const double wk = p.w[k];
+            double fi[NC], gri[NC][D];
+            limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+            double out[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) out[c] = 0.0;
+#pragma unroll
+            for (int j = 0; j < MF; ++j) {
+                if (j >= nf) break;
+                const int f = gi.face[j];
+                const FaceGeo<D> &F = fg[f];
+                double un = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+                double I[NC];
+                if (F.bc == 0) {
+                    const bool self_up = (un > 0.0) == (gi.side[j] == 0);
+                    double val[NC], ug[NC];
+                    if (self_up) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            val[c] = fi[c];
+                            ug[c] = 0.0;
+#pragma unroll
+                            for (int d = 0; d < D; ++d) {
+                                val[c] += gri[c][d] * gi.dvec[j][d];
+                                ug[c] += u[d] * gri[c][d];
+                            }
+                        }
+                    } else {
+                        const int n = gi.nb[j];
+                        const CellGeo<D> &gn = cg[n];
+                        const int bj = gi.back[j];
+                        double fn[NC], grn[NC][D];
+                        limited_slope<D, FT>(gn, n, fin, nv, k, p.limiter, fn, grn);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            val[c] = fn[c];
+                            ug[c] = 0.0;
+#pragma unroll
+                            for (int d = 0; d < D; ++d) {
+                                val[c] += grn[c][d] * gn.dvec[bj][d];
+                                ug[c] += u[d] * grn[c][d];
+                            }
+                        }
+                    }
+                    interface_integral<D>(fe[f], u, u2, Pr, val, ug, I);
+                } else if (un > 0.0) {
+                    // outgoing through a wall or far-field face: free transport
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        double v = fi[c], ug = 0.0;
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            v += gri[c][d] * gi.dvec[j][d];
+                            ug += u[d] * gri[c][d];
+                        }
+                        I[c] = dt * v - 0.5 * dt * dt * ug;
+                    }
+                    if (F.bc == 3) wsum[2 * j] += wk * un * I[0];
+                } else {
+                    const FaceEq<D> &e = fe[f];
+                    double c2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        double cc = u[d] - e.U[d];
+                        c2 += cc * cc;
+                    }
+                    const double H = e.pref * exp(-e.lam * c2);
+                    if (F.bc == 3) {
+                        // reflected part waits for the wall density
+                        wsum[2 * j + 1] += wk * un * dt * H;
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) I[c] = 0.0;
+                    } else {
+                        I[0] = dt * H;
+                        if constexpr (NC > 1) I[1] = dt * (M / (2.0 * e.lam)) * H;
+                    }
+                }
+                const double sa = (gi.side[j] ? -F.area : F.area) * un;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) out[c] += sa * I[c];
+            }
+            // Eq. microS1 with the source at t^n
+            double fpn[NC];
+            {
+                double H, B;
+                equilibrium<D>(u, pn.U, pn.lam, pref_n, shk_n, qn, H, B);
+                fpn[0] = H;
+                if constexpr (NC > 1) fpn[1] = B;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[s][c] = fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]);
+            // moments of the net outflow (Eq. macroscopicFlux summed over faces)
+            mom[0] += wk * out[0];
+#pragma unroll
+            for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
+            mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
+        }
+    }
+
+    // Alg. 1 line 9: wall density from zero net mass flux, then the reflected flux
+    if (has_wall) {
+        block_reduce<BS>(wsum, lds, OpAdd{});
+#pragma unroll
+        for (int s = 0; s < VPT; ++s) {
+            const int k = s * BS + tid;
+            if (s * BS >= nv) continue;
+            if (k >= nv) continue;
+            double u[D], u2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                u[d] = p.u[d * nv + k];
+                u2 += u[d] * u[d];
+            }
+            const double wk = p.w[k];
+            double out[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) out[c] = 0.0;
+#pragma unroll
+            for (int j = 0; j < MF; ++j) {
+                if (j >= nf) break;
+                const int f = gi.face[j];
+                const FaceGeo<D> &F = fg[f];
+                if (F.bc != 3) continue;
+                double un = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+                if (un > 0.0) continue;
+                const FaceEq<D> &e = fe[f];
+                const double rho_w = -wsum[2 * j] / wsum[2 * j + 1];
+                double c2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    double cc = u[d] - e.U[d];
+                    c2 += cc * cc;
+                }
+                const double Hw = rho_w * e.pref * exp(-e.lam * c2);
+                const double sa = F.area * un * dt;
+                out[0] += sa * Hw;
+                if constexpr (NC > 1) out[1] += sa * (M / (2.0 * e.lam)) * Hw;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[s][c] -= out[c] * gi.inv_vol;
+            mom[0] += wk * out[0];
+#pragma unroll
+            for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
+            mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
+        }
+    }
+
+    // Alg. 1 line 10: Eq. macroscopicUpdata
+    block_reduce<BS>(mom, lds, OpAdd{});
+    double W1[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) W1[m] = Wn[m] - mom[m] * gi.inv_vol;
+    const Prim<D> p1 = to_prim<D>(W1);
+    const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
+
+    // heat flux of the stage-1 distribution about U^{n+1}
+    double qt[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qt[d] = 0.0;
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+        const int k = s * BS + tid;
+        if (s * BS >= nv) continue;
+        if (k >= nv) continue;
+        double c[D], c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            c[d] = p.u[d * nv + k] - p1.U[d];
+            c2 += c[d] * c[d];
+        }
+        const double wt = 0.5 * p.w[k] * (c2 * acc[s][0] + (NC > 1 ? acc[s][NC - 1] : 0.0));
+#pragma unroll
+        for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
+    }
+    block_reduce<BS>(qt, lds, OpAdd{});
+    double q1[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q1[d] = qt[d] / (1.0 + Pr * dt / (2.0 * tau1));
+
+    // Alg. 1 line 11: Eq. microS2
+    const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
+    const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
+    const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+        const int k = s * BS + tid;
+        if (s * BS >= nv) continue;
+        if (k >= nv) continue;
+        double u[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) u[d] = p.u[d * nv + k];
+        double H, B;
+        equilibrium<D>(u, p1.U, p1.lam, pref_1, shk_1, q1, H, B);
+        const double fp[2] = {H, B};
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            fout[((size_t)i * NC + c) * nv + k] = static_cast<FT>((acc[s][c] + a1 * fp[c]) * inv1);
+    }
+    if (tid == 0) {
+        bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            ok = ok && isfinite(W1[m]);
+            p.W[(size_t)i * NW + m] = W1[m];
+            const double dw = W1[m] - Wn[m];
+            p.dW2[(size_t)i * NW + m] = dw * dw;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.q[(size_t)i * D + d] = q1[d];
+        if (!ok) {
+            atomicOr(p.err, 1);
+            atomicMin(p.err + 1, i);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// L2 norm over cells of the last step's change of W (fixed order)
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_residual(Params p, double *out)
+{
+    constexpr int NW = D + 2;
+    __shared__ double lds[4 * NW];
+    double s[NW];
+    for (int m = 0; m < NW; ++m) s[m] = 0.0;
+    for (int i = threadIdx.x; i < p.nc; i += 256)
+        for (int m = 0; m < NW; ++m) s[m] += p.dW2[(size_t)i * NW + m];
+    block_reduce<256>(s, lds, OpAdd{});
+    if (threadIdx.x == 0)
+        for (int m = 0; m < NW; ++m) out[m] = sqrt(s[m]);
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+template <int D> hipError_t cfl_d(const Params &p, double *cell_dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cfl<D>, dim3(p.nc), dim3(256), 0, s, p, cell_dt);
+    return hipGetLastError();
+}
+hipError_t launch_cfl(const Params &p, double *cell_dt, hipStream_t s)
+{
+    return p.dim == 2 ? cfl_d<2>(p, cell_dt, s) : cfl_d<3>(p, cell_dt, s);
+}
+
+template <int D, typename FT> hipError_t init_d(const Params &p, const double *prim0, void *f, hipStream_t s)
+{
+    size_t n = (size_t)p.nc * p.nv;
+    hipLaunchKernelGGL((k_init<D, FT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, prim0,
+                       static_cast<FT *>(f));
+    return hipGetLastError();
+}
+hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_t s)
+{
+    if (p.dim == 2) return p.fstore ? init_d<2, float>(p, prim0, f, s) : init_d<2, double>(p, prim0, f, s);
+    return p.fstore ? init_d<3, float>(p, prim0, f, s) : init_d<3, double>(p, prim0, f, s);
+}
+
+template <int D, typename FT> hipError_t moments_d(const Params &p, const void *f, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_moments<D, FT>), dim3(p.nc), dim3(256), 0, s, p, static_cast<const FT *>(f));
+    return hipGetLastError();
+}
+hipError_t launch_moments(const Params &p, const void *f, hipStream_t s)
+{
+    if (p.dim == 2) return p.fstore ? moments_d<2, float>(p, f, s) : moments_d<2, double>(p, f, s);
+    return p.fstore ? moments_d<3, float>(p, f, s) : moments_d<3, double>(p, f, s);
+}
+
+template <int D, typename FT, int BS, int VPT>
+void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sweep<D, FT, BS, VPT>), dim3(p.nc), dim3(BS), 0, s, p, static_cast<const FT *>(fi),
+                       static_cast<FT *>(fo));
+}
+
+template <int D, typename FT> hipError_t step_d(const Params &p, const void *fi, void *fo, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_grad<D>, dim3((p.nc + 255) / 256), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_face_eq<D>, dim3((p.nf + 127) / 128), dim3(128), 0, s, p);
+    const int nv = p.nv;
+    if (nv <= 256) sweep_launch<D, FT, 256, 1>(p, fi, fo, s);
+    else if (nv <= 512) sweep_launch<D, FT, 256, 2>(p, fi, fo, s);
+    else if (nv <= 1024) sweep_launch<D, FT, 256, 4>(p, fi, fo, s);
+    else if (nv <= 2048) sweep_launch<D, FT, 256, 8>(p, fi, fo, s);
+    else if (nv <= 4096) sweep_launch<D, FT, 256, 16>(p, fi, fo, s);
+    else if (nv <= 8192) sweep_launch<D, FT, 512, 16>(p, fi, fo, s);
+    else if (nv <= 16384) sweep_launch<D, FT, 1024, 16>(p, fi, fo, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+hipError_t launch_step(const Params &p, const void *fi, void *fo, hipStream_t s)
+{
+    if (p.dim == 2) return p.fstore ? step_d<2, float>(p, fi, fo, s) : step_d<2, double>(p, fi, fo, s);
+    return p.fstore ? step_d<3, float>(p, fi, fo, s) : step_d<3, double>(p, fi, fo, s);
+}
+
+hipError_t launch_residual(const Params &p, double *out, hipStream_t s)
+{
+    if (p.dim == 2) hipLaunchKernelGGL(k_residual<2>, dim3(1), dim3(256), 0, s, p, out);
+    else hipLaunchKernelGGL(k_residual<3>, dim3(1), dim3(256), 0, s, p, out);
+    return hipGetLastError();
+}
+
+}  // namespace ugx

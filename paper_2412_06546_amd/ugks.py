@@ -1,0 +1,194 @@
+"""ctypes binding of libugks.so (include/ugks.h): argument marshalling only.
+
+Every step of the scheme runs in the HIP library; this module converts numpy
+arrays into the C structs, passes torch's current HIP stream, and turns
+status codes into exceptions.  It raises at import of the library when the
+built libugks.so is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libugks.so")
+
+UGKS_OK, UGKS_ERR_ARG, UGKS_ERR_ALLOC, UGKS_ERR_HIP, UGKS_ERR_NONPHYSICAL, UGKS_ERR_STATE = 0, -1, -2, -3, -4, -5
+UGKS_F64, UGKS_F32 = 0, 1
+_ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
+             -5: "UGKS_ERR_STATE"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class ugks_mesh_t(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_cells", C.c_int), ("n_faces", C.c_int),
+                ("cell_volume", _dp), ("cell_centroid", _dp), ("face_cells", _ip),
+                ("face_normal", _dp), ("face_area", _dp), ("face_centroid", _dp), ("face_shift", _dp),
+                ("face_bc", _ip), ("face_bc_id", _ip)]
+
+
+class ugks_vgrid_t(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_vel", C.c_int), ("u", _dp), ("w", _dp)]
+
+
+class ugks_gas_t(C.Structure):
+    _fields_ = [("Pr", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double), ("cfl", C.c_double),
+                ("dt_override", C.c_double), ("limiter_k", C.c_double), ("limiter", C.c_int),
+                ("fstore", C.c_int), ("n_bc", C.c_int), ("bc_prim", _dp)]
+
+
+class UgksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libugks.so and declare the C ABI.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run paper_2412_06546_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(path)
+    L.ugks_create.restype = C.c_int
+    L.ugks_create.argtypes = [C.POINTER(ugks_mesh_t), C.POINTER(ugks_vgrid_t), C.POINTER(ugks_gas_t), _dp,
+                              C.c_void_p, C.POINTER(C.c_void_p)]
+    L.ugks_step.restype = C.c_int
+    L.ugks_step.argtypes = [C.c_void_p, C.c_int, _dp]
+    L.ugks_macros.restype = C.c_int
+    L.ugks_macros.argtypes = [C.c_void_p, _dp, _dp]
+    L.ugks_get_f.restype = C.c_int
+    L.ugks_get_f.argtypes = [C.c_void_p, _dp]
+    L.ugks_set_f.restype = C.c_int
+    L.ugks_set_f.argtypes = [C.c_void_p, _dp]
+    L.ugks_dt.restype = C.c_double
+    L.ugks_dt.argtypes = [C.c_void_p]
+    L.ugks_n_comp.restype = C.c_int
+    L.ugks_n_comp.argtypes = [C.c_void_p]
+    L.ugks_step_count.restype = C.c_long
+    L.ugks_step_count.argtypes = [C.c_void_p]
+    L.ugks_footprint_bytes.restype = C.c_size_t
+    L.ugks_footprint_bytes.argtypes = [C.c_void_p]
+    L.ugks_is_tensor_grid.restype = C.c_int
+    L.ugks_is_tensor_grid.argtypes = [C.c_void_p]
+    L.ugks_device_f.restype = C.c_void_p
+    L.ugks_device_f.argtypes = [C.c_void_p]
+    L.ugks_destroy.restype = None
+    L.ugks_destroy.argtypes = [C.c_void_p]
+    L.ugks_last_error.restype = C.c_char_p
+    L.ugks_last_error.argtypes = [C.c_void_p]
+    _lib = L
+    return L
+
+
+def _check(L, h, code):
+    if code != UGKS_OK:
+        raise UgksError(code, L.ugks_last_error(h).decode())
+
+
+def current_stream_handle():
+    """torch's current HIP stream as a hipStream_t (None = default stream)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+class Solver:
+    """A flow case on the GPU: ugks_create ... ugks_destroy."""
+
+    def __init__(self, case, fstore: str = "f64", stream=None):
+        L = self._L = load_library()
+        m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
+        self.dim = int(m["dim"])
+        self.nc = len(m["cell_volume"])
+        self.nv = len(vg["w"])
+        keep = self._keep = []
+
+        def d(x):
+            a = np.ascontiguousarray(x, dtype=np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(_dp)
+
+        def i(x):
+            a = np.ascontiguousarray(x, dtype=np.int32)
+            keep.append(a)
+            return a.ctypes.data_as(_ip)
+
+        mesh = ugks_mesh_t(self.dim, self.nc, len(m["face_area"]), d(m["cell_volume"]), d(m["cell_centroid"]),
+                           i(m["face_cells"]), d(m["face_normal"]), d(m["face_area"]), d(m["face_centroid"]),
+                           d(m["face_shift"]) if m.get("face_shift") is not None else None,
+                           i(m["face_bc"]), i(m["face_bc_id"]))
+        vgrid = ugks_vgrid_t(self.dim, self.nv, d(vg["u"]), d(vg["w"]))
+        bc = np.asarray(gas["bc_prim"], dtype=np.float64)
+        g = ugks_gas_t(gas["Pr"], gas["omega"], gas["mu_ref"], gas["cfl"], gas["dt_override"], gas["limiter_k"],
+                       int(gas["limiter"]), UGKS_F32 if fstore == "f32" else UGKS_F64, bc.shape[0], d(bc))
+        if stream is None:
+            stream = current_stream_handle()
+        self.stream = stream
+        h = C.c_void_p()
+        code = L.ugks_create(C.byref(mesh), C.byref(vgrid), C.byref(g), d(case["prim0"]), stream, C.byref(h))
+        _check(L, None, code)
+        self._h = h
+        self.ncomp = L.ugks_n_comp(h)
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ugks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def dt(self) -> float:
+        return self._L.ugks_dt(self._h)
+
+    @property
+    def step_count(self) -> int:
+        return self._L.ugks_step_count(self._h)
+
+    @property
+    def footprint_bytes(self) -> int:
+        return self._L.ugks_footprint_bytes(self._h)
+
+    @property
+    def tensor_grid(self) -> bool:
+        return bool(self._L.ugks_is_tensor_grid(self._h))
+
+    def step(self, n: int = 1, residual: bool = False):
+        r = np.zeros(self.dim + 2) if residual else None
+        _check(self._L, self._h, self._L.ugks_step(self._h, int(n), r.ctypes.data_as(_dp) if residual else None))
+        return r
+
+    def macros(self):
+        W = np.zeros((self.nc, self.dim + 2))
+        q = np.zeros((self.nc, self.dim))
+        _check(self._L, self._h, self._L.ugks_macros(self._h, W.ctypes.data_as(_dp), q.ctypes.data_as(_dp)))
+        return W, q
+
+    def f(self):
+        f = np.zeros((self.nc, self.ncomp, self.nv))
+        _check(self._L, self._h, self._L.ugks_get_f(self._h, f.ctypes.data_as(_dp)))
+        return f
+
+    def set_f(self, f):
+        a = np.ascontiguousarray(f, dtype=np.float64)
+        assert a.shape == (self.nc, self.ncomp, self.nv)
+        _check(self._L, self._h, self._L.ugks_set_f(self._h, a.ctypes.data_as(_dp)))
