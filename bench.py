@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X memory-saving UGKS step.
+
+Workload: the 2D hypersonic cylinder -- 20,000 unstructured cells (200 x 95
+O-grid, outer 5 rings cut into triangles) around a unit cylinder in a
+15-radius far field, Shakhov Pr = 2/3, Ma = 5, Kn = 0.1, isothermal wall,
+60 x 60 velocity grid on [-15, 15]^2: 72 million cell-velocity updates per
+step.  A step is one full time step of the scheme (macro gradients,
+interface equilibria, fused sweep with wall, macro update, heat flux and
+both stages of the f update) on inputs resident in HBM.
+
+Prints one JSON line: cell-velocity updates/s, the fused sweep kernel's
+achieved HBM bandwidth against the 8 TB/s peak (live HIP-event timing of
+that kernel on its stream), and the FP64 CPU oracle timed on the host on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cylinder20k_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2412_06546_amd", "csrc", "ugks_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(fstore: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = f"traffic_bytes_per_launch_{fstore}"
+    return float(vals[key]) if key in vals else None
+
+
+def copy_calibration(nbytes: int, reps: int):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def cpu_baseline(case, target_s: float, max_steps: int):
+    """The FP64 oracle as it stands, on the host cores, on the same workload;
+    set-up (time step, initial state) excluded."""
+    import oracle
+    nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
+    o = oracle.Oracle(case)
+    steps, t = 0, 0.0
+    while steps < max_steps and t < target_s:
+        t0 = time.perf_counter()
+        o.step(1)
+        t += time.perf_counter() - t0
+        steps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nc * nv * steps / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} full steps of the same {nc}-cell x {nv}-velocity workload ({t:.1f} s, "
+                      f"OpenMP over cells, gcc -O2)"}
+
+
+def run_gpu(case, fstore: str, steps: int, warmup: int):
+    import torch
+    from paper_2412_06546_amd import ugks
+    s = ugks.Solver(case, fstore=fstore)
+    nc, nv, ncomp = s.nc, s.nv, s.ncomp
+    s.step(warmup)
+    torch.cuda.synchronize()
+    s.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    sweep_ms, pro_ms, n = s.profile_read()
+    s.profile(False)
+    W, _ = s.macros()
+    bytes_per_value = 8 if fstore == "f64" else 4
+    alg_bytes = nc * nv * ncomp * bytes_per_value * 2      # read f once, write f once
+    sweep_avg_s = sweep_ms / n / 1e3
+    out = dict(ms_per_step=ms / steps, wall_s=wall, updates_per_s=nc * nv * steps / (ms / 1e3),
+               sweep_ms_avg=sweep_ms / n, prologue_ms_avg=pro_ms / n, alg_bytes=alg_bytes,
+               achieved_gbs=alg_bytes / sweep_avg_s / 1e9, footprint_bytes=s.footprint_bytes,
+               finite=bool((W[:, 0] > 0).all()))
+    s.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--fstore", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of this many bytes (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(velocity-space sharding over RCCL is a design, not code). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, 5)
+        return
+
+    from paper_2412_06546_amd import cases
+    case = cases.case_cylinder()
+    nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
+    print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
+    main_run = run_gpu(case, args.fstore, args.steps, args.warmup)
+    print(f"# gpu {args.fstore}: {main_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    other = None
+    if not args.no_secondary:
+        fs2 = "f32" if args.fstore == "f64" else "f64"
+        r2 = run_gpu(case, fs2, max(5, args.steps // 2), args.warmup)
+        other = {"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
+                 "sweep_ms": r2["sweep_ms_avg"], "achieved_gbs": r2["achieved_gbs"]}
+        print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    traffic = measured_traffic(args.fstore)
+    roofline = {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(main_run["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": "k_sweep", "kernel_ms": round(main_run["sweep_ms_avg"], 4),
+                "alg_bytes_per_launch": main_run["alg_bytes"]}
+    line = {
+        "metric": "cell-velocity updates/s",
+        "value": main_run["updates_per_s"],
+        "unit": "cell-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.fstore,
+        "data": "synthetic",
+        "config": {"workload": f"{case['name']}: 2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall",
+                   "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64",
+                   "prologue_ms": round(main_run["prologue_ms_avg"], 4),
+                   "footprint_bytes": main_run["footprint_bytes"]},
+        "roofline": roofline,
+    }
+    if other:
+        line["other_precision"] = other
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds, 5)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

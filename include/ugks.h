@@ -136,9 +136,25 @@ long ugks_step_count(const ugks_t *h);      /* steps taken since creation */
 size_t ugks_footprint_bytes(const ugks_t *h); /* device bytes owned by the handle */
 int ugks_is_tensor_grid(const ugks_t *h);   /* 1 if the separable velocity path is used */
 
-/* Device pointer and layout of the current f (for zero-copy inspection):
- * [n_cells][n_comp][n_vel] in the storage precision; valid until the next
- * ugks_step or ugks_destroy. */
+/* Timing of the step's kernels with HIP events on the handle's stream.
+ * ugks_profile(h, 1) resets the counters and records events around every
+ * launch from then on (0 stops).  ugks_profile_read gives ms_out[0] = total
+ * milliseconds in the fused sweep kernel, ms_out[1] = total in the two
+ * prologue kernels (macro gradients and interface equilibria), and the
+ * number of steps timed. */
+int ugks_profile(ugks_t *h, int enable);
+int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
+
+/* The library stores velocities in its own order (by direction, so that the
+ * lanes of a wavefront agree on upwind sides).  perm_out [n_vel] receives,
+ * for each stored position, the caller's velocity index.  ugks_get_f and
+ * ugks_set_f use the caller's order. */
+int ugks_velocity_order(const ugks_t *h, int *perm_out);
+
+/* Device pointer of the current f (for zero-copy inspection):
+ * [n_cells][n_comp][n_vel] in the storage precision and the library's
+ * velocity order (ugks_velocity_order); valid until the next ugks_step or
+ * ugks_destroy. */
 const void *ugks_device_f(const ugks_t *h);
 
 void ugks_destroy(ugks_t *h);

@@ -293,12 +293,18 @@ def case_periodic_wave(nx=20, ny=10, nv=28, half_width=6.0, kn=0.1, seed=0, Pr=1
 
 
 def case_cylinder(n_theta=200, n_r=95, n_tri_rings=5, nv=60, half_width=15.0, ma=5.0, kn=0.1,
-                  Pr=2.0 / 3.0, omega=0.81, t_wall=1.0, h_first=1e-3, r_far=15.0, seed=0):
+                  Pr=2.0 / 3.0, omega=0.81, t_wall=1.0, h_first=1e-3, r_far=15.0, seed=0,
+                  start="potential", wall_layer=0.2):
     """2D hypersonic cylinder: unit-radius cylinder, far field radius 15,
     200 x 95 O-grid with the outer 5 rings cut into triangles (20,000 cells),
     first layer 1e-3; Shakhov Pr = 2/3, Ma = 5, Kn = 0.1 on the diameter,
-    isothermal wall at T_inf; 60 x 60 trapezoid grid on [-15,15]^2;
-    free-stream Maxwellian start."""
+    isothermal wall at T_inf; 60 x 60 trapezoid grid on [-15,15]^2.
+
+    start='potential': rho = T = 1 with the incompressible potential flow
+    around the cylinder, brought to rest at the wall over a layer of
+    thickness wall_layer (U * (1 - exp(-(r - 1)/wall_layer))).
+    start='freestream': uniform free stream (impulsive start; the leeward
+    first-layer cells empty within tens of steps)."""
     u_inf = ma * sound_speed(1.0)
     mesh = cylinder_ogrid(n_theta, n_r, 1.0, r_far, h_first, n_tri_rings, (u_inf, 0.0), seed)
     vg = tensor_vgrid(nv, half_width, 2)
@@ -307,7 +313,26 @@ def case_cylinder(n_theta=200, n_r=95, n_tri_rings=5, nv=60, half_width=15.0, ma
     gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 2.0), bc_prim=bc)
     nc = len(mesh["cell_volume"])
     prim0 = np.tile(bc[0], (nc, 1))
+    if start == "potential":
+        x = mesh["cell_centroid"]
+        r = np.hypot(x[:, 0], x[:, 1])
+        th = np.arctan2(x[:, 1], x[:, 0])
+        ur = u_inf * (1.0 - 1.0 / r ** 2) * np.cos(th)
+        ut = -u_inf * (1.0 + 1.0 / r ** 2) * np.sin(th)
+        damp = 1.0 - np.exp(-(r - 1.0) / wall_layer)
+        prim0[:, 1] = (ur * np.cos(th) - ut * np.sin(th)) * damp
+        prim0[:, 2] = (ur * np.sin(th) + ut * np.cos(th)) * damp
+    elif start != "freestream":
+        raise ValueError(start)
     return dict(name=f"cylinder_{nc}_v{nv}x{nv}", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+
+
+def case_cylinder_small(n_theta=40, n_r=16, n_tri_rings=2, nv=24, half_width=15.0, ma=5.0, kn=0.1,
+                        h_first=1e-2, seed=0, Pr=2.0 / 3.0, start="potential"):
+    """Cut-down of the hypersonic cylinder (same physics, wall, far field and
+    mixed quad/triangle mesh) that the oracle steps in about a second."""
+    return case_cylinder(n_theta=n_theta, n_r=n_r, n_tri_rings=n_tri_rings, nv=nv, half_width=half_width, ma=ma,
+                         kn=kn, h_first=h_first, seed=seed, Pr=Pr, start=start)
 
 
 def n_comp(dim: int) -> int:
@@ -315,11 +340,3 @@ def n_comp(dim: int) -> int:
     (one internal velocity component), h only in 3D (no internal component
     for a monatomic gas, so b is identically zero)."""
     return 2 if dim == 2 else 1
-
-
-def case_cylinder_small(n_theta=40, n_r=16, n_tri_rings=2, nv=24, half_width=15.0, ma=5.0, kn=0.1,
-                        h_first=1e-2, seed=0, Pr=2.0 / 3.0):
-    """Cut-down of the hypersonic cylinder (same physics, wall, far field and
-    mixed quad/triangle mesh) that the oracle steps in about a second."""
-    return case_cylinder(n_theta=n_theta, n_r=n_r, n_tri_rings=n_tri_rings, nv=nv, half_width=half_width, ma=ma,
-                         kn=kn, h_first=h_first, seed=seed, Pr=Pr)

@@ -23,13 +23,19 @@ struct ugks {
     int cur = 0;
     void *cgeo = nullptr, *fgeo = nullptr, *feq = nullptr;
     double *u = nullptr, *w = nullptr, *bcp = nullptr, *W = nullptr, *q = nullptr, *gW = nullptr, *dW2 = nullptr;
-    double *cell_dt = nullptr, *res = nullptr;
-    int *err = nullptr;
+    double *cell_dt = nullptr, *res = nullptr, *u1d = nullptr;
+    int *err = nullptr, *kidx = nullptr;
     double dt = 0.0;
     long nstep = 0;
     int tensor = 0;
     size_t bytes = 0;
     std::string msg;
+    // optional per-launch timing: events around the prologue and the sweep
+    int profiling = 0;
+    std::vector<hipEvent_t> ev;  // 3 per step: before prologue, before sweep, after sweep
+    double prof_ms[2] = {0.0, 0.0};
+    long prof_n = 0;
+    std::vector<int> perm;  // internal velocity index -> caller's index
 };
 
 static std::string g_create_error;
@@ -62,33 +68,79 @@ void upload(void *dst, const void *src, size_t bytes, hipStream_t s)
 
 // A velocity set laid out as a Cartesian product with the last axis
 // contiguous: u_k = (x_a, y_b[, z_c]) at k = (a * ny + b) * nz + c.
-int detect_tensor(int D, int nv, const double *u)
+// Returns 1 and the axes when it is one.
+int detect_tensor(int D, int nv, const double *u, int n1d[3], std::vector<double> &axes, std::vector<int> &kidx)
 {
     int n_last = 1;
     while (n_last < nv && u[(size_t)n_last * D + 0] == u[0]) ++n_last;
+    int nx, ny, nz = 1;
+    if (nv % n_last) return 0;
     if (D == 2) {
-        if (nv % n_last) return 0;
-        int na = nv / n_last;
-        for (int a = 0; a < na; ++a)
-            for (int b = 0; b < n_last; ++b) {
-                size_t k = (size_t)a * n_last + b;
-                if (u[k * 2] != u[(size_t)a * n_last * 2] || u[k * 2 + 1] != u[(size_t)b * 2 + 1]) return 0;
-            }
-        return 1;
+        ny = n_last;
+        nx = nv / n_last;
+    } else {
+        while (nz < n_last && u[(size_t)nz * 3 + 1] == u[1]) ++nz;
+        if (n_last % nz) return 0;
+        ny = n_last / nz;
+        nx = nv / n_last;
     }
-    int nz = 1;
-    while (nz < nv && u[(size_t)nz * 3 + 1] == u[1] && u[(size_t)nz * 3] == u[0]) ++nz;
-    if (nv % n_last || n_last % nz) return 0;
-    int ny = n_last / nz, nx = nv / n_last;
+    if (nx > 1023 || ny > 1023 || nz > 1023) return 0;
     for (int a = 0; a < nx; ++a)
         for (int b = 0; b < ny; ++b)
             for (int c = 0; c < nz; ++c) {
-                size_t k = ((size_t)a * ny + b) * nz + c;
-                if (u[k * 3] != u[(size_t)a * n_last * 3] || u[k * 3 + 1] != u[(size_t)b * nz * 3 + 1] ||
-                    u[k * 3 + 2] != u[(size_t)c * 3 + 2])
-                    return 0;
+                const size_t k = ((size_t)a * ny + b) * nz + c;
+                if (u[k * D] != u[(size_t)a * n_last * D]) return 0;
+                if (u[k * D + 1] != u[(size_t)b * nz * D + 1]) return 0;
+                if (D == 3 && u[k * D + 2] != u[(size_t)c * D + 2]) return 0;
             }
+    n1d[0] = nx;
+    n1d[1] = ny;
+    n1d[2] = D == 3 ? nz : 0;
+    axes.clear();
+    for (int a = 0; a < nx; ++a) axes.push_back(u[(size_t)a * n_last * D]);
+    for (int b = 0; b < ny; ++b) axes.push_back(u[(size_t)b * nz * D + 1]);
+    if (D == 3)
+        for (int c = 0; c < nz; ++c) axes.push_back(u[(size_t)c * D + 2]);
+    kidx.resize(nv);
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int c = 0; c < nz; ++c) kidx[((size_t)a * ny + b) * nz + c] = a | (b << 10) | (c << 20);
     return 1;
+}
+
+// Velocities are stored ordered by direction, so the 64 lanes of a wavefront
+// hold nearly parallel velocities and agree on the upwind side of almost
+// every face (only wavefronts straddling a face's tangent line diverge).
+// 2D: by polar angle, then speed.  3D: by polar band, then azimuth
+// (alternating direction band to band), then speed.
+std::vector<int> direction_order(int D, int nv, const double *u)
+{
+    std::vector<int> idx(nv);
+    std::vector<double> k1(nv), k2(nv), k3(nv);
+    const int nb = D == 3 ? std::max(1, (int)std::lround(std::sqrt(nv / 64.0))) : 1;
+    for (int k = 0; k < nv; ++k) {
+        idx[k] = k;
+        const double *v = u + (size_t)k * D;
+        double s2 = 0.0;
+        for (int d = 0; d < D; ++d) s2 += v[d] * v[d];
+        const double az = std::atan2(v[1], v[0]);
+        if (D == 2) {
+            k1[k] = 0.0;
+            k2[k] = az;
+        } else {
+            const double r = std::sqrt(s2);
+            const int band = r > 0.0 ? std::min(nb - 1, (int)(std::acos(std::max(-1.0, std::min(1.0, v[2] / r))) / M_PI * nb)) : 0;
+            k1[k] = band;
+            k2[k] = (band & 1) ? -az : az;
+        }
+        k3[k] = s2;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (k1[a] != k1[b]) return k1[a] < k1[b];
+        if (k2[a] != k2[b]) return k2[a] < k2[b];
+        return k3[a] < k3[b];
+    });
+    return idx;
 }
 
 template <int D>
@@ -230,7 +282,7 @@ int fail(ugks_t *h, const Fail &e)
 void release(ugks_t *h)
 {
     void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
-                    h->cell_dt, h->res, h->err};
+                    h->cell_dt, h->res, h->err, h->u1d, h->kidx};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -279,12 +331,26 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         }
         if (D == 2) create_d<2>(h, mesh, gas);
         else create_d<3>(h, mesh, gas);
-        h->tensor = detect_tensor(D, h->nv, vgrid->u);
+        int n1d[3] = {0, 0, 0};
+        std::vector<double> axes;
+        std::vector<int> kidx;
+        h->tensor = detect_tensor(D, h->nv, vgrid->u, n1d, axes, kidx);
+        // the per-workgroup Gaussian tables must fit in LDS next to the rest
+        if (h->tensor && (size_t)(Dim<3>::MF + 1) * axes.size() * sizeof(double) > 48 * 1024) h->tensor = 0;
 
         const size_t nv = h->nv, nc = h->nc;
-        std::vector<double> uT((size_t)D * nv);
-        for (size_t k = 0; k < nv; ++k)
-            for (int d = 0; d < D; ++d) uT[(size_t)d * nv + k] = vgrid->u[k * D + d];
+        h->perm = direction_order(D, h->nv, vgrid->u);
+        std::vector<double> uT((size_t)D * nv), wP(nv);
+        for (size_t k = 0; k < nv; ++k) {
+            const size_t ku = h->perm[k];
+            for (int d = 0; d < D; ++d) uT[(size_t)d * nv + k] = vgrid->u[ku * D + d];
+            wP[k] = vgrid->w[ku];
+        }
+        if (h->tensor) {
+            std::vector<int> kp(nv);
+            for (size_t k = 0; k < nv; ++k) kp[k] = kidx[h->perm[k]];
+            kidx.swap(kp);
+        }
         h->u = dev_alloc<double>(h, uT.size());
         h->w = dev_alloc<double>(h, nv);
         h->bcp = dev_alloc<double>(h, (size_t)std::max(1, h->nbc) * (D + 2));
@@ -295,6 +361,12 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         h->cell_dt = dev_alloc<double>(h, nc);
         h->res = dev_alloc<double>(h, D + 2);
         h->err = dev_alloc<int>(h, 2);
+        if (h->tensor) {
+            h->u1d = dev_alloc<double>(h, axes.size());
+            h->kidx = dev_alloc<int>(h, kidx.size());
+            upload(h->u1d, axes.data(), sizeof(double) * axes.size(), h->stream);
+            upload(h->kidx, kidx.data(), sizeof(int) * kidx.size(), h->stream);
+        }
         double *prim_d = dev_alloc<double>(h, nc * (D + 2));
         const size_t fbytes = nc * h->ncomp * nv * (h->fstore ? sizeof(float) : sizeof(double));
         for (int b = 0; b < 2; ++b) {
@@ -302,7 +374,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             h->bytes += fbytes;
         }
         upload(h->u, uT.data(), sizeof(double) * uT.size(), h->stream);
-        upload(h->w, vgrid->w, sizeof(double) * nv, h->stream);
+        upload(h->w, wP.data(), sizeof(double) * nv, h->stream);
         if (h->nbc) upload(h->bcp, gas->bc_prim, sizeof(double) * h->nbc * (D + 2), h->stream);
         upload(prim_d, prim0, sizeof(double) * nc * (D + 2), h->stream);
         const int err0[2] = {0, 0x7fffffff};
@@ -329,6 +401,10 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         P.gW = h->gW;
         P.dW2 = h->dW2;
         P.err = h->err;
+        P.u1d = h->u1d;
+        P.kidx = h->kidx;
+        for (int d = 0; d < 3; ++d) P.n1d[d] = h->tensor ? n1d[d] : 0;
+        P.ntab = h->tensor ? (int)axes.size() : 0;
 
         // time step (Alg. 1 line 1), fixed for the run
         hip_check(launch_cfl(P, h->cell_dt, h->stream), "k_cfl launch");
@@ -361,8 +437,17 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
     if (!h) return UGKS_ERR_ARG;
     if (nsteps < 0) return fail(h, Fail{UGKS_ERR_ARG, "nsteps < 0"});
     try {
+        if (h->profiling && h->ev.size() < (size_t)3 * nsteps) {
+            size_t old = h->ev.size();
+            h->ev.resize((size_t)3 * nsteps);
+            for (size_t e = old; e < h->ev.size(); ++e) hip_check(hipEventCreate(&h->ev[e]), "hipEventCreate");
+        }
         for (int s = 0; s < nsteps; ++s) {
-            hip_check(launch_step(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "step launch");
+            if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s], h->stream), "hipEventRecord");
+            hip_check(launch_prologue(h->P, h->stream), "prologue launch");
+            if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s + 1], h->stream), "hipEventRecord");
+            hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
+            if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s + 2], h->stream), "hipEventRecord");
             h->cur ^= 1;
             h->nstep++;
         }
@@ -374,6 +459,15 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
                       "copy residual");
         }
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (h->profiling)
+            for (int s = 0; s < nsteps; ++s) {
+                float a = 0.f, b = 0.f;
+                hip_check(hipEventElapsedTime(&a, h->ev[3 * s], h->ev[3 * s + 1]), "hipEventElapsedTime");
+                hip_check(hipEventElapsedTime(&b, h->ev[3 * s + 1], h->ev[3 * s + 2]), "hipEventElapsedTime");
+                h->prof_ms[0] += b;
+                h->prof_ms[1] += a;
+                h->prof_n++;
+            }
         if (err[0]) return fail(h, Fail{UGKS_ERR_NONPHYSICAL, "non-physical state (rho <= 0, T <= 0 or non-finite) first at cell " + std::to_string(err[1])});
     } catch (const Fail &e) {
         return fail(h, e);
@@ -399,16 +493,19 @@ extern "C" int ugks_get_f(ugks_t *h, double *f_out)
 {
     if (!h || !f_out) return UGKS_ERR_ARG;
     try {
-        const size_t n = (size_t)h->nc * h->ncomp * h->nv;
+        const size_t nv = h->nv, rows = (size_t)h->nc * h->ncomp, n = rows * nv;
+        std::vector<double> tmp(n);
         if (h->fstore == UGKS_F64) {
-            hip_check(hipMemcpyAsync(f_out, h->f[h->cur], sizeof(double) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
+            hip_check(hipMemcpyAsync(tmp.data(), h->f[h->cur], sizeof(double) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         } else {
-            std::vector<float> tmp(n);
-            hip_check(hipMemcpyAsync(tmp.data(), h->f[h->cur], sizeof(float) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
+            std::vector<float> t32(n);
+            hip_check(hipMemcpyAsync(t32.data(), h->f[h->cur], sizeof(float) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-            for (size_t i = 0; i < n; ++i) f_out[i] = tmp[i];
+            for (size_t i = 0; i < n; ++i) tmp[i] = t32[i];
         }
+        for (size_t r = 0; r < rows; ++r)
+            for (size_t k = 0; k < nv; ++k) f_out[r * nv + h->perm[k]] = tmp[r * nv + k];
     } catch (const Fail &e) {
         return fail(h, e);
     }
@@ -419,21 +516,49 @@ extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
 {
     if (!h || !f_in) return UGKS_ERR_ARG;
     try {
-        const size_t n = (size_t)h->nc * h->ncomp * h->nv;
+        const size_t nv = h->nv, rows = (size_t)h->nc * h->ncomp, n = rows * nv;
+        std::vector<double> tmp(n);
+        for (size_t r = 0; r < rows; ++r)
+            for (size_t k = 0; k < nv; ++k) tmp[r * nv + k] = f_in[r * nv + h->perm[k]];
         if (h->fstore == UGKS_F64) {
-            upload(h->f[h->cur], f_in, sizeof(double) * n, h->stream);
+            upload(h->f[h->cur], tmp.data(), sizeof(double) * n, h->stream);
             hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         } else {
-            std::vector<float> tmp(n);
-            for (size_t i = 0; i < n; ++i) tmp[i] = (float)f_in[i];
-            upload(h->f[h->cur], tmp.data(), sizeof(float) * n, h->stream);
+            std::vector<float> t32(n);
+            for (size_t i = 0; i < n; ++i) t32[i] = (float)tmp[i];
+            upload(h->f[h->cur], t32.data(), sizeof(float) * n, h->stream);
             hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         }
     } catch (const Fail &e) {
         return fail(h, e);
     }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_velocity_order(const ugks_t *h, int *perm_out)
+{
+    if (!h || !perm_out) return UGKS_ERR_ARG;
+    std::copy(h->perm.begin(), h->perm.end(), perm_out);
+    return UGKS_OK;
+}
+
+extern "C" int ugks_profile(ugks_t *h, int enable)
+{
+    if (!h) return UGKS_ERR_ARG;
+    h->profiling = enable ? 1 : 0;
+    h->prof_ms[0] = h->prof_ms[1] = 0.0;
+    h->prof_n = 0;
+    return UGKS_OK;
+}
+
+extern "C" int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches)
+{
+    if (!h || !ms_out) return UGKS_ERR_ARG;
+    ms_out[0] = h->prof_ms[0];
+    ms_out[1] = h->prof_ms[1];
+    if (launches) *launches = h->prof_n;
     return UGKS_OK;
 }
 
@@ -449,6 +574,7 @@ extern "C" void ugks_destroy(ugks_t *h)
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     release(h);
     delete h;
 }

@@ -53,6 +53,8 @@ template <int D> struct alignas(16) FaceEq {
     double rho, U[D], lam;
     double pref;          // rho (lam/pi)^{D/2}
     double shk;           // 4 (1 - Pr) lam^2 / (5 rho)
+    double bh;            // M / (2 lam): B = bh H
+    double x4;            // M (M + 2) / (4 lam^2): int xi^4 g dxi = x4 H
     double a[D][NW];      // spatial slopes of g0
     double A[NW];         // time slope of g0
     double q[D];          // interface heat flux
@@ -69,6 +71,12 @@ struct Params {
     void *feq;
     const double *u;   // [dim][nv] (structure of arrays)
     const double *w;   // [nv]
+    // Cartesian velocity grids: 1D axes [nx | ny | nz] and per-velocity axis
+    // indices packed as a | b << 10 | c << 20; ntab = nx + ny + nz, 0 otherwise
+    const double *u1d;
+    const int *kidx;
+    int n1d[3];
+    int ntab;
     const double *bc_prim;  // [n_bc][dim+2]
     double *W, *q;     // [nc][dim+2], [nc][dim]
     double *gW;        // [nc][dim+2][dim] limited gradients of W
@@ -79,7 +87,8 @@ struct Params {
 hipError_t launch_cfl(const Params &p, double *cell_dt, hipStream_t s);
 hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_t s);
 hipError_t launch_moments(const Params &p, const void *f, hipStream_t s);
-hipError_t launch_step(const Params &p, const void *f_in, void *f_out, hipStream_t s);
+hipError_t launch_prologue(const Params &p, hipStream_t s);  // k_cell_grad + k_face_eq
+hipError_t launch_sweep(const Params &p, const void *f_in, void *f_out, hipStream_t s);
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s);
 
 }  // namespace ugx

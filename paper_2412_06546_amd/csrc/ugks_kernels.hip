@@ -124,15 +124,25 @@ __device__ __forceinline__ void equilibrium(const double (&u)[D], const double (
 // ------------------------------------------------------------------------
 // limited least-squares slope of f_k in cell c (Section 3.1, step 2)
 // ------------------------------------------------------------------------
+// Reciprocal to full double precision: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 template <int D, typename FT>
 __device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const FT *__restrict__ f, int nv, int k,
                                               int limiter, double (&fc)[Dim<D>::NC], double (&gr)[Dim<D>::NC][D])
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
     double fmx[NC], fmn[NC];
+    const FT *fcell = f + (size_t)c * NC * nv;  // wave-uniform base of the cell's slab
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-        fc[m] = static_cast<double>(f[((size_t)c * NC + m) * nv + k]);
+        fc[m] = static_cast<double>(fcell[m * nv + k]);
         fmx[m] = fmn[m] = fc[m];
 #pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
@@ -143,63 +153,82 @@ __device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const 
         if (j >= nf) break;
         const int n = g.nb[j];
         if (n < 0) continue;
+        const FT *fnb = f + (size_t)n * NC * nv;
 #pragma unroll
         for (int m = 0; m < NC; ++m) {
-            double fj = static_cast<double>(f[((size_t)n * NC + m) * nv + k]);
-            double df = fj - fc[m];
+            const double fj = static_cast<double>(fnb[m * nv + k]);
+            const double df = fj - fc[m];
 #pragma unroll
-            for (int d = 0; d < D; ++d) gr[m][d] += g.lsq[j][d] * df;
+            for (int d = 0; d < D; ++d) gr[m][d] = fma(g.lsq[j][d], df, gr[m][d]);
             fmx[m] = fmax(fmx[m], fj);
             fmn[m] = fmin(fmn[m], fj);
         }
     }
     if (!limiter) return;
-    // phi = min(1, min_faces phi_f), compared as fractions to avoid one
-    // division per face
+    // phi = min(1, min over faces of the Venkatakrishnan factor), the
+    // fractions compared by cross-multiplication (denominators are positive);
+    // a face with no increment gives num = den and never wins
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
+        const double up = fmx[m] - fc[m], dn = fmn[m] - fc[m];
         double bn = 1.0, bd = 1.0;
 #pragma unroll
         for (int j = 0; j < MF; ++j) {
             if (j >= nf) break;
             double dm = 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) dm += gr[m][d] * g.dvec[j][d];
-            if (dm == 0.0) continue;
-            double dp = dm > 0.0 ? fmx[m] - fc[m] : fmn[m] - fc[m];
-            double num = dp * dp + g.eps2 + 2.0 * dm * dp;
-            double den = dp * dp + 2.0 * dm * dm + dm * dp + g.eps2;
-            if (num * bd < bn * den) {
-                bn = num;
-                bd = den;
-            }
+            for (int d = 0; d < D; ++d) dm = fma(gr[m][d], g.dvec[j][d], dm);
+            const double dp = dm > 0.0 ? up : dn;
+            const double dp2e = fma(dp, dp, g.eps2);
+            const double num = fma(2.0 * dm, dp, dp2e);
+            const double den = fma(dm, fma(2.0, dm, dp), dp2e);
+            const bool take = num * bd < bn * den;
+            bn = take ? num : bn;
+            bd = take ? den : bd;
         }
-        double phi = bn / bd;
+        const double phi = bn * rcp_nr(bd);
 #pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] *= phi;
     }
 }
 
-// Time-integrated interface value of h (and b) at velocity u (Eq. fullSolution
-// integrated over [0, dt]); val is the upwind reconstruction at the face and
-// ug = u . grad of the upwind cell.
+// Shakhov equilibrium f+ = H + H+ (and B + B+) at u, given the reduced
+// Maxwellian value H there (Section 2.2):
+// H+ = shk (c.q)(2 lam c^2 - 2 - D) H, B = M/(2 lam) H,
+// B+ = shk (c.q)(2 lam c^2 - D) B, with shk = 4 (1 - Pr) lam^2 / (5 rho).
 template <int D>
-__device__ __forceinline__ void interface_integral(const FaceEq<D> &e, const double (&u)[D], double u2, double Pr,
+__device__ __forceinline__ void shakhov(const double (&u)[D], const double (&U)[D], double lam, double shk,
+                                        const double (&q)[D], double bh, double H, double &fh, double &fb)
+{
+    constexpr int M = Dim<D>::M;
+    double c2 = 0.0, cq = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double c = u[d] - U[d];
+        c2 = fma(c, c, c2);
+        cq = fma(c, q[d], cq);
+    }
+    const double s = shk * cq, l2 = 2.0 * lam * c2;
+    fh = fma(s * (l2 - 2.0 - D), H, H);
+    if constexpr (M > 0) {
+        const double B = bh * H;  // bh = M / (2 lam)
+        fb = fma(s * (l2 - D), B, B);
+    } else {
+        fb = 0.0;
+    }
+}
+
+// Time-integrated interface value of h (and b) at velocity u (Eq. fullSolution
+// integrated over [0, dt]); val is the upwind reconstruction at the face,
+// ug = u . grad of the upwind cell, H0 the reduced Maxwellian g0 at u.
+template <int D>
+__device__ __forceinline__ void interface_integral(const FaceEq<D> &e, const double (&u)[D], double u2, double H0,
                                                    const double (&val)[Dim<D>::NC], const double (&ug)[Dim<D>::NC],
                                                    double (&I)[Dim<D>::NC])
 {
     constexpr int M = Dim<D>::M, NW = D + 2;
-    double c2 = 0.0, cq = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        double c = u[d] - e.U[d];
-        c2 += c * c;
-        cq += c * e.q[d];
-    }
-    const double lam = e.lam;
-    const double H0 = e.pref * exp(-lam * c2);
-    const double s = e.shk * cq;
-    const double eqH = H0 + s * (2.0 * lam * c2 - 2.0 - D) * H0;
+    double eqH, eqB;
+    shakhov<D>(u, e.U, e.lam, e.shk, e.q, e.bh, H0, eqH, eqB);
     double Pd = 0.0, Ed = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -213,9 +242,8 @@ __device__ __forceinline__ void interface_integral(const FaceEq<D> &e, const dou
 #pragma unroll
     for (int c = 0; c < D; ++c) PA += e.A[1 + c] * u[c];
     if constexpr (M > 0) {
-        const double B0 = (M / (2.0 * lam)) * H0;
-        const double eqB = B0 + s * (2.0 * lam * c2 - D) * B0;
-        const double xi4 = (M * (M + 2) / (4.0 * lam * lam)) * H0;  // int xi^4 g0 dxi
+        const double B0 = e.bh * H0;
+        const double xi4 = e.x4 * H0;  // int xi^4 g0 dxi
         const double gH = Pd * H0 + 0.5 * Ed * B0, gB = Pd * B0 + 0.5 * Ed * xi4;
         const double tH = PA * H0 + 0.5 * e.A[NW - 1] * B0, tB = PA * B0 + 0.5 * e.A[NW - 1] * xi4;
         I[0] = e.c[0] * val[0] + e.c[1] * ug[0] + e.c[2] * eqH + e.c[3] * gH + e.c[4] * tH;
@@ -512,6 +540,8 @@ __global__ __launch_bounds__(128) void k_face_eq(Params p)
         for (int d = 0; d < D; ++d) e.U[d] = U[d];
         e.pref = rho * pow_lam_pi<D>(lam);
         e.shk = 0.0;
+        e.bh = Dim<D>::M / (2.0 * lam);
+        e.x4 = 0.0;
         return;
     }
     // reconstructed states on both sides
@@ -557,6 +587,8 @@ __global__ __launch_bounds__(128) void k_face_eq(Params p)
     for (int d = 0; d < D; ++d) e.U[d] = p0.U[d];
     e.pref = p0.rho * pow_lam_pi<D>(p0.lam);
     e.shk = 4.0 * (1.0 - p.Pr) * p0.lam * p0.lam / (5.0 * p0.rho);
+    e.bh = Dim<D>::M / (2.0 * p0.lam);
+    e.x4 = Dim<D>::M * (Dim<D>::M + 2) / (4.0 * p0.lam * p0.lam);
     // spatial slopes from the averaged limited gradients
     for (int d = 0; d < D; ++d) {
         double Dl[NW];
@@ -575,19 +607,161 @@ __global__ __launch_bounds__(128) void k_face_eq(Params p)
 // ------------------------------------------------------------------------
 // Alg. 1 lines 4-11, fused: the sweep over one cell's velocity slab
 // ------------------------------------------------------------------------
-template <int D, typename FT, int BS, int VPT>
+// Unit-density Gaussian exp(-lam |u_k - U|^2).  On a Cartesian velocity grid
+// it is the product of one-dimensional factors, tabulated in LDS once per
+// workgroup (nx + ny [+ nz] exponentials instead of nx * ny [* nz]).
+template <int D, bool TENSOR> struct Gauss {
+    const double *tab;  // LDS tables, ntab doubles each
+    int ntab;
+    int off1, off2;     // start of the y and z axes inside a table
+    __device__ __forceinline__ double operator()(int t, unsigned kx, const double (&u)[D], double lam,
+                                                 const double *U) const
+    {
+        if constexpr (TENSOR) {
+            const double *tb = tab + t * ntab;
+            double g = tb[kx & 1023u] * tb[off1 + ((kx >> 10) & 1023u)];
+            if constexpr (D == 3) g *= tb[off2 + (kx >> 20)];
+            return g;
+        } else {
+            double c2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const double c = u[d] - U[d];
+                c2 += c * c;
+            }
+            return exp(-lam * c2);
+        }
+    }
+};
+
+// Raw moments of the stage-1 distribution about U^n, from which its heat
+// flux about U^{n+1} follows without a second pass over f:
+// 2D: S0, S_a, S_ab (xx, xy, yy), T_a = sum v_a |v|^2 h, B0, B_a
+// 3D: S0, S_a, S_ab (xx, xy, xz, yy, yz, zz), T_a
+template <int D> struct QMom;
+template <> struct QMom<2> {
+    static constexpr int N = 11;
+    __device__ static __forceinline__ void add(double *m, const double (&v)[2], double w, double h, double b)
+    {
+        const double wh = w * h, v2 = v[0] * v[0] + v[1] * v[1];
+        m[0] += wh;
+        m[1] += wh * v[0];
+        m[2] += wh * v[1];
+        m[3] += wh * v[0] * v[0];
+        m[4] += wh * v[0] * v[1];
+        m[5] += wh * v[1] * v[1];
+        m[6] += wh * v[0] * v2;
+        m[7] += wh * v[1] * v2;
+        m[8] += w * b;
+        m[9] += w * b * v[0];
+        m[10] += w * b * v[1];
+    }
+    __device__ static __forceinline__ void heat_flux(const double *m, const double (&dl)[2], double (&q)[2])
+    {
+        const double S[2][2] = {{m[3], m[4]}, {m[4], m[5]}};
+        const double tr = m[3] + m[5], d2 = dl[0] * dl[0] + dl[1] * dl[1];
+        const double dS = dl[0] * m[1] + dl[1] * m[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const double Sd = S[a][0] * dl[0] + S[a][1] * dl[1];
+            q[a] = 0.5 * (m[6 + a] - 2.0 * Sd + d2 * m[1 + a] - dl[a] * tr + 2.0 * dl[a] * dS - dl[a] * d2 * m[0] +
+                          m[9 + a] - dl[a] * m[8]);
+        }
+    }
+};
+template <> struct QMom<3> {
+    static constexpr int N = 13;
+    __device__ static __forceinline__ void add(double *m, const double (&v)[3], double w, double h, double)
+    {
+        const double wh = w * h, v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        m[0] += wh;
+        m[1] += wh * v[0];
+        m[2] += wh * v[1];
+        m[3] += wh * v[2];
+        m[4] += wh * v[0] * v[0];
+        m[5] += wh * v[0] * v[1];
+        m[6] += wh * v[0] * v[2];
+        m[7] += wh * v[1] * v[1];
+        m[8] += wh * v[1] * v[2];
+        m[9] += wh * v[2] * v[2];
+        m[10] += wh * v[0] * v2;
+        m[11] += wh * v[1] * v2;
+        m[12] += wh * v[2] * v2;
+    }
+    __device__ static __forceinline__ void heat_flux(const double *m, const double (&dl)[3], double (&q)[3])
+    {
+        const double S[3][3] = {{m[4], m[5], m[6]}, {m[5], m[7], m[8]}, {m[6], m[8], m[9]}};
+        const double tr = m[4] + m[7] + m[9], d2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+        const double dS = dl[0] * m[1] + dl[1] * m[2] + dl[2] * m[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double Sd = S[a][0] * dl[0] + S[a][1] * dl[1] + S[a][2] * dl[2];
+            q[a] = 0.5 * (m[10 + a] - 2.0 * Sd + d2 * m[1 + a] - dl[a] * tr + 2.0 * dl[a] * dS - dl[a] * d2 * m[0]);
+        }
+    }
+};
+
+// Net outflow S u_n dt rho_w H_w (and the b part) of the particles the
+// wall faces of cell gi send back at velocity k (u_n <= 0).  Returns false
+// when no wall face of the cell reflects at this velocity.
+template <int D, bool TENSOR>
+__device__ __forceinline__ bool wall_reflected(const CellGeo<D> &gi, const FaceGeo<D> *fg, const FaceEq<D> *fe,
+                                               const Gauss<D, TENSOR> gauss, int nf, int k, unsigned kx,
+                                               const double (&u)[D], double dt, const double (&rho_w)[Dim<D>::MF],
+                                               double (&out)[Dim<D>::NC])
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M;
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MF; ++j) {
+        if (j >= nf) break;
+        const FaceGeo<D> &F = fg[gi.face[j]];
+        if (F.bc != 3) continue;
+        double un = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+        if (un > 0.0) continue;
+        const FaceEq<D> &e = fe[gi.face[j]];
+        const double Hw = rho_w[j] * e.pref * gauss(j, kx, u, e.lam, e.U);
+        const double sa = F.area * un * dt;
+        out[0] += sa * Hw;
+        if constexpr (NC > 1) out[1] += sa * e.bh * Hw;
+        any = true;
+    }
+    (void)k;
+    return any;
+}
+
+// One workgroup per cell; threads stride over the cell's velocities.
+//   pass 1: for each velocity, limited slopes (own cell, and the upwind
+//           neighbour where it is upwind), the time-integrated flux through
+//           every face, and the stage-1 value (without the wall's reflected
+//           particles) -> written to f_out; moments accumulated on the fly;
+//   wall:   reduction of the incident and unit-density reflected mass fluxes
+//           -> wall density; the reflected particles' contribution to the
+//           moments;
+//   macro:  workgroup reduction -> W^{n+1}, tau^{n+1}, q^{n+1};
+//   pass 2: each thread re-reads what it wrote, adds the reflected
+//           particles, applies stage 2 and writes f^{n+1}.
+template <int D, typename FT, int BS, bool TENSOR>
 __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
-    const int i = blockIdx.x;
-    const int tid = threadIdx.x;
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2, NQ = QMom<D>::N;
+    constexpr int NT = MF + 1;  // Gaussian tables: one per face slot, one for the cell
+    extern __shared__ double smem[];
+    const int i = blockIdx.x, tid = threadIdx.x;
     const CellGeo<D> *cg = static_cast<const CellGeo<D> *>(p.cgeo);
     const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
     const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
     const CellGeo<D> &gi = cg[i];
     const int nv = p.nv, nf = gi.nf;
     const double dt = p.dt, Pr = p.Pr;
-    __shared__ double lds[(BS / 64) * (2 * MF > NW ? 2 * MF : NW)];
+    const int ntab = TENSOR ? p.ntab : 0;
+    double *red = smem + NT * ntab;
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    const size_t base = (size_t)i * NC * nv;
 
     // state at t^n
     double Wn[NW];
@@ -601,232 +775,228 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
     const double pref_n = pn.rho * pow_lam_pi<D>(pn.lam);
     const double shk_n = 4.0 * (1.0 - Pr) * pn.lam * pn.lam / (5.0 * pn.rho);
     const double hdt_tau = 0.5 * dt / tau_n;
+    const double bh_n = Dim<D>::M / (2.0 * pn.lam);
 
     int has_wall = 0;
     for (int j = 0; j < nf; ++j) has_wall |= (fg[gi.face[j]].bc == 3);
 
-    double acc[VPT][NC];
-    double mom[NW];
+    if constexpr (TENSOR) {
+        // one-dimensional Gaussian factors of every face's Maxwellian and of f+^n
+        for (int t = tid; t < NT * ntab; t += BS) {
+            const int which = t / ntab, idx = t - which * ntab;
+            const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+            double lam, Ud;
+            if (which < nf) {
+                const FaceEq<D> &e = fe[gi.face[which]];
+                lam = e.lam;
+                Ud = e.U[ax];
+            } else {
+                lam = pn.lam;
+                Ud = pn.U[0];
+                if (ax == 1) Ud = pn.U[1];
+                if (D == 3 && ax == 2) Ud = pn.U[D - 1];
+            }
+            const double c = p.u1d[idx] - Ud;
+            smem[t] = exp(-lam * c * c);
+        }
+        __syncthreads();
+    }
+
+    double mom[NW + NQ];
     double wsum[2 * MF];  // per slot: incident mass flux, reflected unit-density flux
 #pragma unroll
-    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+    for (int m = 0; m < NW + NQ; ++m) mom[m] = 0.0;
 #pragma unroll
     for (int j = 0; j < 2 * MF; ++j) wsum[j] = 0.0;
 
+    for (int k = tid; k < nv; k += BS) {
+        double u[D], u2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < VPT; ++s) {
-        const int k = s * BS + tid;
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 += u[d] * u[d];
+        }
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        const double wk = p.w[k];
+        double fi[NC], gri[NC][D];
+        limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+        double out[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[s][c] = 0.0;
-        if (s * BS >= nv) continue;
-        if (k < nv) {
-            double u[D], u2 = 0.0;
+        for (int c = 0; c < NC; ++c) out[c] = 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                u[d] = p.u[d * nv + k];
-                u2 += u[d] * u[d];
-            }
-            const double wk = p.w[k];
-            double fi[NC], gri[NC][D];
-            limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
-            double out[NC];
+        for (int j = 0; j < MF; ++j) {
+            if (j >= nf) break;
+            const int f = gi.face[j];
+            const FaceGeo<D> &F = fg[f];
+            const FaceEq<D> &e = fe[f];
+            double un = 0.0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) out[c] = 0.0;
-#pragma unroll
-            for (int j = 0; j < MF; ++j) {
-                if (j >= nf) break;
-                const int f = gi.face[j];
-                const FaceGeo<D> &F = fg[f];
-                double un = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
-                double I[NC];
-                if (F.bc == 0) {
-                    const bool self_up = (un > 0.0) == (gi.side[j] == 0);
-                    double val[NC], ug[NC];
-                    if (self_up) {
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) {
-                            val[c] = fi[c];
-                            ug[c] = 0.0;
-#pragma unroll
-                            for (int d = 0; d < D; ++d) {
-                                val[c] += gri[c][d] * gi.dvec[j][d];
-                                ug[c] += u[d] * gri[c][d];
-                            }
-                        }
-                    } else {
-                        const int n = gi.nb[j];
-                        const CellGeo<D> &gn = cg[n];
-                        const int bj = gi.back[j];
-                        double fn[NC], grn[NC][D];
-                        limited_slope<D, FT>(gn, n, fin, nv, k, p.limiter, fn, grn);
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) {
-                            val[c] = fn[c];
-                            ug[c] = 0.0;
-#pragma unroll
-                            for (int d = 0; d < D; ++d) {
-                                val[c] += grn[c][d] * gn.dvec[bj][d];
-                                ug[c] += u[d] * grn[c][d];
-                            }
-                        }
-                    }
-                    interface_integral<D>(fe[f], u, u2, Pr, val, ug, I);
-                } else if (un > 0.0) {
-                    // outgoing through a wall or far-field face: free transport
+            for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+            double I[NC];
+            if (F.bc == 0) {
+                const bool self_up = (un > 0.0) == (gi.side[j] == 0);
+                double val[NC], ug[NC];
+                if (self_up) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        double v = fi[c], ug = 0.0;
+                        val[c] = fi[c];
+                        ug[c] = 0.0;
 #pragma unroll
                         for (int d = 0; d < D; ++d) {
-                            v += gri[c][d] * gi.dvec[j][d];
-                            ug += u[d] * gri[c][d];
+                            val[c] += gri[c][d] * gi.dvec[j][d];
+                            ug[c] += u[d] * gri[c][d];
                         }
-                        I[c] = dt * v - 0.5 * dt * dt * ug;
                     }
-                    if (F.bc == 3) wsum[2 * j] += wk * un * I[0];
                 } else {
-                    const FaceEq<D> &e = fe[f];
-                    double c2 = 0.0;
+                    const int n = gi.nb[j];
+                    const CellGeo<D> &gn = cg[n];
+                    const int bj = gi.back[j];
+                    double fn[NC], grn[NC][D];
+                    limited_slope<D, FT>(gn, n, fin, nv, k, p.limiter, fn, grn);
 #pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        double cc = u[d] - e.U[d];
-                        c2 += cc * cc;
-                    }
-                    const double H = e.pref * exp(-e.lam * c2);
-                    if (F.bc == 3) {
-                        // reflected part waits for the wall density
-                        wsum[2 * j + 1] += wk * un * dt * H;
+                    for (int c = 0; c < NC; ++c) {
+                        val[c] = fn[c];
+                        ug[c] = 0.0;
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) I[c] = 0.0;
-                    } else {
-                        I[0] = dt * H;
-                        if constexpr (NC > 1) I[1] = dt * (M / (2.0 * e.lam)) * H;
+                        for (int d = 0; d < D; ++d) {
+                            val[c] += grn[c][d] * gn.dvec[bj][d];
+                            ug[c] += u[d] * grn[c][d];
+                        }
                     }
                 }
-                const double sa = (gi.side[j] ? -F.area : F.area) * un;
+                const double H0 = e.pref * gauss(j, kx, u, e.lam, e.U);
+                interface_integral<D>(e, u, u2, H0, val, ug, I);
+            } else if (un > 0.0) {
+                // outgoing through a wall or far-field face: free transport
 #pragma unroll
-                for (int c = 0; c < NC; ++c) out[c] += sa * I[c];
+                for (int c = 0; c < NC; ++c) {
+                    double v = fi[c], ug = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        v += gri[c][d] * gi.dvec[j][d];
+                        ug += u[d] * gri[c][d];
+                    }
+                    I[c] = dt * v - 0.5 * dt * dt * ug;
+                }
+                if (F.bc == 3) wsum[2 * j] += wk * un * I[0];
+            } else {
+                const double H = e.pref * gauss(j, kx, u, e.lam, e.U);
+                if (F.bc == 3) {
+                    // reflected part waits for the wall density
+                    wsum[2 * j + 1] += wk * un * dt * H;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) I[c] = 0.0;
+                } else {
+                    I[0] = dt * H;
+                    if constexpr (NC > 1) I[1] = dt * e.bh * H;
+                }
             }
-            // Eq. microS1 with the source at t^n
-            double fpn[NC];
-            {
-                double H, B;
-                equilibrium<D>(u, pn.U, pn.lam, pref_n, shk_n, qn, H, B);
-                fpn[0] = H;
-                if constexpr (NC > 1) fpn[1] = B;
-            }
+            const double sa = (gi.side[j] ? -F.area : F.area) * un;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[s][c] = fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]);
-            // moments of the net outflow (Eq. macroscopicFlux summed over faces)
-            mom[0] += wk * out[0];
-#pragma unroll
-            for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
-            mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
+            for (int c = 0; c < NC; ++c) out[c] += sa * I[c];
         }
+        // Eq. microS1 with the source at t^n
+        double fpn[2];
+        {
+            const double H = pref_n * gauss(MF, kx, u, pn.lam, pn.U);
+            shakhov<D>(u, pn.U, pn.lam, shk_n, qn, bh_n, H, fpn[0], fpn[1]);
+        }
+        double ft[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            ft[c] = fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]);
+            fout[base + (size_t)c * nv + k] = static_cast<FT>(ft[c]);
+        }
+        // moments of the net outflow (Eq. macroscopicFlux summed over faces)
+        mom[0] += wk * out[0];
+#pragma unroll
+        for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
+        mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
+        double v[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[d] = u[d] - pn.U[d];
+        QMom<D>::add(mom + NW, v, wk, ft[0], NC > 1 ? ft[NC - 1] : 0.0);
     }
 
-    // Alg. 1 line 9: wall density from zero net mass flux, then the reflected flux
+    // Alg. 1 line 9: wall density from zero net mass flux
+    double rho_w[MF];
     if (has_wall) {
-        block_reduce<BS>(wsum, lds, OpAdd{});
+        block_reduce<BS>(wsum, red, OpAdd{});
 #pragma unroll
-        for (int s = 0; s < VPT; ++s) {
-            const int k = s * BS + tid;
-            if (s * BS >= nv) continue;
-            if (k >= nv) continue;
+        for (int j = 0; j < MF; ++j) rho_w[j] = (j < nf && wsum[2 * j + 1] != 0.0) ? -wsum[2 * j] / wsum[2 * j + 1] : 0.0;
+        for (int k = tid; k < nv; k += BS) {
             double u[D], u2 = 0.0;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 u[d] = p.u[d * nv + k];
                 u2 += u[d] * u[d];
             }
+            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
             const double wk = p.w[k];
             double out[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) out[c] = 0.0;
-#pragma unroll
-            for (int j = 0; j < MF; ++j) {
-                if (j >= nf) break;
-                const int f = gi.face[j];
-                const FaceGeo<D> &F = fg[f];
-                if (F.bc != 3) continue;
-                double un = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
-                if (un > 0.0) continue;
-                const FaceEq<D> &e = fe[f];
-                const double rho_w = -wsum[2 * j] / wsum[2 * j + 1];
-                double c2 = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    double cc = u[d] - e.U[d];
-                    c2 += cc * cc;
-                }
-                const double Hw = rho_w * e.pref * exp(-e.lam * c2);
-                const double sa = F.area * un * dt;
-                out[0] += sa * Hw;
-                if constexpr (NC > 1) out[1] += sa * (M / (2.0 * e.lam)) * Hw;
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[s][c] -= out[c] * gi.inv_vol;
+            if (!wall_reflected<D, TENSOR>(gi, fg, fe, gauss, nf, k, kx, u, dt, rho_w, out)) continue;
             mom[0] += wk * out[0];
 #pragma unroll
             for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
             mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
+            double v[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) v[d] = u[d] - pn.U[d];
+            QMom<D>::add(mom + NW, v, wk, -out[0] * gi.inv_vol, NC > 1 ? -out[NC - 1] * gi.inv_vol : 0.0);
         }
     }
 
-    // Alg. 1 line 10: Eq. macroscopicUpdata
-    block_reduce<BS>(mom, lds, OpAdd{});
+    // Alg. 1 line 10: Eq. macroscopicUpdata, then tau and q at t^{n+1}
+    block_reduce<BS>(mom, red, OpAdd{});
     double W1[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) W1[m] = Wn[m] - mom[m] * gi.inv_vol;
     const Prim<D> p1 = to_prim<D>(W1);
     const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
-
-    // heat flux of the stage-1 distribution about U^{n+1}
-    double qt[D];
+    double dl[D], qt[D], q1[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) qt[d] = 0.0;
-#pragma unroll
-    for (int s = 0; s < VPT; ++s) {
-        const int k = s * BS + tid;
-        if (s * BS >= nv) continue;
-        if (k >= nv) continue;
-        double c[D], c2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            c[d] = p.u[d * nv + k] - p1.U[d];
-            c2 += c[d] * c[d];
-        }
-        const double wt = 0.5 * p.w[k] * (c2 * acc[s][0] + (NC > 1 ? acc[s][NC - 1] : 0.0));
-#pragma unroll
-        for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
-    }
-    block_reduce<BS>(qt, lds, OpAdd{});
-    double q1[D];
+    for (int d = 0; d < D; ++d) dl[d] = p1.U[d] - pn.U[d];
+    QMom<D>::heat_flux(mom + NW, dl, qt);
 #pragma unroll
     for (int d = 0; d < D; ++d) q1[d] = qt[d] / (1.0 + Pr * dt / (2.0 * tau1));
+
+    if constexpr (TENSOR) {
+        // the cell's table now holds the factors of f+^{n+1}
+        for (int idx = tid; idx < ntab; idx += BS) {
+            const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+            double Ud = p1.U[0];
+            if (ax == 1) Ud = p1.U[1];
+            if (D == 3 && ax == 2) Ud = p1.U[D - 1];
+            const double c = p.u1d[idx] - Ud;
+            smem[MF * ntab + idx] = exp(-p1.lam * c * c);
+        }
+        __syncthreads();
+    }
 
     // Alg. 1 line 11: Eq. microS2
     const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
     const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
     const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
-#pragma unroll
-    for (int s = 0; s < VPT; ++s) {
-        const int k = s * BS + tid;
-        if (s * BS >= nv) continue;
-        if (k >= nv) continue;
+    const double bh_1 = Dim<D>::M / (2.0 * p1.lam);
+    for (int k = tid; k < nv; k += BS) {
         double u[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) u[d] = p.u[d * nv + k];
-        double H, B;
-        equilibrium<D>(u, p1.U, p1.lam, pref_1, shk_1, q1, H, B);
-        const double fp[2] = {H, B};
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double ft[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            fout[((size_t)i * NC + c) * nv + k] = static_cast<FT>((acc[s][c] + a1 * fp[c]) * inv1);
+        for (int c = 0; c < NC; ++c) ft[c] = static_cast<double>(fout[base + (size_t)c * nv + k]);
+        if (has_wall) {
+            double out[NC];
+            if (wall_reflected<D, TENSOR>(gi, fg, fe, gauss, nf, k, kx, u, dt, rho_w, out))
+#pragma unroll
+                for (int c = 0; c < NC; ++c) ft[c] -= out[c] * gi.inv_vol;
+        }
+        double fp[2];
+        const double H = pref_1 * gauss(MF, kx, u, p1.lam, p1.U);
+        shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fout[base + (size_t)c * nv + k] = static_cast<FT>((ft[c] + a1 * fp[c]) * inv1);
     }
     if (tid == 0) {
         bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
@@ -900,32 +1070,37 @@ hipError_t launch_moments(const Params &p, const void *f, hipStream_t s)
     return p.fstore ? moments_d<3, float>(p, f, s) : moments_d<3, double>(p, f, s);
 }
 
-template <int D, typename FT, int BS, int VPT>
-void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_sweep<D, FT, BS, VPT>), dim3(p.nc), dim3(BS), 0, s, p, static_cast<const FT *>(fi),
-                       static_cast<FT *>(fo));
-}
-
-template <int D, typename FT> hipError_t step_d(const Params &p, const void *fi, void *fo, hipStream_t s)
+template <int D> hipError_t prologue_d(const Params &p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cell_grad<D>, dim3((p.nc + 255) / 256), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_face_eq<D>, dim3((p.nf + 127) / 128), dim3(128), 0, s, p);
-    const int nv = p.nv;
-    if (nv <= 256) sweep_launch<D, FT, 256, 1>(p, fi, fo, s);
-    else if (nv <= 512) sweep_launch<D, FT, 256, 2>(p, fi, fo, s);
-    else if (nv <= 1024) sweep_launch<D, FT, 256, 4>(p, fi, fo, s);
-    else if (nv <= 2048) sweep_launch<D, FT, 256, 8>(p, fi, fo, s);
-    else if (nv <= 4096) sweep_launch<D, FT, 256, 16>(p, fi, fo, s);
-    else if (nv <= 8192) sweep_launch<D, FT, 512, 16>(p, fi, fo, s);
-    else if (nv <= 16384) sweep_launch<D, FT, 1024, 16>(p, fi, fo, s);
-    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
-hipError_t launch_step(const Params &p, const void *fi, void *fo, hipStream_t s)
+hipError_t launch_prologue(const Params &p, hipStream_t s)
 {
-    if (p.dim == 2) return p.fstore ? step_d<2, float>(p, fi, fo, s) : step_d<2, double>(p, fi, fo, s);
-    return p.fstore ? step_d<3, float>(p, fi, fo, s) : step_d<3, double>(p, fi, fo, s);
+    return p.dim == 2 ? prologue_d<2>(p, s) : prologue_d<3>(p, s);
+}
+
+template <int D, typename FT, int BS, bool TENSOR>
+void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
+{
+    constexpr int NW = D + 2, NQ = QMom<D>::N, MF = Dim<D>::MF;
+    constexpr int NRED = (NW + NQ > 2 * MF) ? NW + NQ : 2 * MF;
+    const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (TENSOR ? p.ntab : 0) + (BS / 64) * NRED);
+    hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR>), dim3(p.nc), dim3(BS), lds, s, p, static_cast<const FT *>(fi),
+                       static_cast<FT *>(fo));
+}
+
+template <int D, typename FT> hipError_t sweep_d(const Params &p, const void *fi, void *fo, hipStream_t s)
+{
+    if (p.ntab > 0) sweep_launch<D, FT, 256, true>(p, fi, fo, s);
+    else sweep_launch<D, FT, 256, false>(p, fi, fo, s);
+    return hipGetLastError();
+}
+hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s)
+{
+    if (p.dim == 2) return p.fstore ? sweep_d<2, float>(p, fi, fo, s) : sweep_d<2, double>(p, fi, fo, s);
+    return p.fstore ? sweep_d<3, float>(p, fi, fo, s) : sweep_d<3, double>(p, fi, fo, s);
 }
 
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s)

@@ -79,6 +79,12 @@ def load_library(path: str = LIB_PATH):
     L.ugks_footprint_bytes.argtypes = [C.c_void_p]
     L.ugks_is_tensor_grid.restype = C.c_int
     L.ugks_is_tensor_grid.argtypes = [C.c_void_p]
+    L.ugks_profile.restype = C.c_int
+    L.ugks_profile.argtypes = [C.c_void_p, C.c_int]
+    L.ugks_profile_read.restype = C.c_int
+    L.ugks_profile_read.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_long)]
+    L.ugks_velocity_order.restype = C.c_int
+    L.ugks_velocity_order.argtypes = [C.c_void_p, _ip]
     L.ugks_device_f.restype = C.c_void_p
     L.ugks_device_f.argtypes = [C.c_void_p]
     L.ugks_destroy.restype = None
@@ -187,6 +193,22 @@ class Solver:
         f = np.zeros((self.nc, self.ncomp, self.nv))
         _check(self._L, self._h, self._L.ugks_get_f(self._h, f.ctypes.data_as(_dp)))
         return f
+
+    def velocity_order(self):
+        """Stored velocity position -> caller's velocity index."""
+        perm = np.zeros(self.nv, dtype=np.int32)
+        _check(self._L, self._h, self._L.ugks_velocity_order(self._h, perm.ctypes.data_as(_ip)))
+        return perm
+
+    def profile(self, enable: bool = True):
+        _check(self._L, self._h, self._L.ugks_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(ms in the sweep kernel, ms in the prologue kernels, steps timed)."""
+        ms = np.zeros(2)
+        n = C.c_long(0)
+        _check(self._L, self._h, self._L.ugks_profile_read(self._h, ms.ctypes.data_as(_dp), C.byref(n)))
+        return float(ms[0]), float(ms[1]), int(n.value)
 
     def set_f(self, f):
         a = np.ascontiguousarray(f, dtype=np.float64)
