@@ -340,3 +340,173 @@ def n_comp(dim: int) -> int:
     (one internal velocity component), h only in 3D (no internal component
     for a monatomic gas, so b is identically zero)."""
     return 2 if dim == 2 else 1
+
+
+# --------------------------------------------------------------------------
+# 3D polyhedral meshes
+# --------------------------------------------------------------------------
+def _poly_area_centroid(P):
+    """Area vector (right-hand rule over the vertex order) and centroid of a
+    planar polygon in 3D, by a fan of triangles."""
+    a = np.zeros(3)
+    c = np.zeros(3)
+    for t in range(1, len(P) - 1):
+        at = 0.5 * np.cross(P[t] - P[0], P[t + 1] - P[0])
+        w = np.linalg.norm(at)
+        a += at
+        c += w * (P[0] + P[t] + P[t + 1]) / 3.0
+    return a, c / max(np.linalg.norm(a), 1e-300)
+
+
+def build_mesh_3d(cells, classify_boundary=None):
+    """Assemble face data from polyhedra.
+
+    cells: list of polyhedra; each is a list of faces, each face a list of
+    vertices (vid, x, y, z) ordered counter-clockwise seen from outside the
+    cell; vid identifies the vertex across periodic images and (x, y, z) is
+    its position in that cell's own frame.
+    """
+    nc = len(cells)
+    vol = np.zeros(nc)
+    cen = np.zeros((nc, 3))
+    faces = {}
+    for c, poly in enumerate(cells):
+        pts = np.array([[v[1], v[2], v[3]] for f in poly for v in f])
+        ref = pts.mean(axis=0)
+        V = 0.0
+        C = np.zeros(3)
+        for f in poly:
+            P = np.array([[v[1], v[2], v[3]] for v in f])
+            for t in range(1, len(P) - 1):
+                tv = np.dot(P[0] - ref, np.cross(P[t] - ref, P[t + 1] - ref)) / 6.0
+                V += tv
+                C += tv * (ref + P[0] + P[t] + P[t + 1]) / 4.0
+            key = tuple(sorted(v[0] for v in f))
+            faces.setdefault(key, []).append((c, P))
+        if V <= 0:
+            raise ValueError(f"cell {c} has non-positive volume (faces not outward)")
+        vol[c], cen[c] = V, C / V
+    fc, fn, fa, fx, fs, fbc, fid = [], [], [], [], [], [], []
+    for key in sorted(faces, key=lambda k: tuple(sorted(e[0] for e in faces[k])) + k):
+        ent = sorted(faces[key], key=lambda e: e[0])
+        c0, P0 = ent[0]
+        av, xc = _poly_area_centroid(P0)
+        area = float(np.linalg.norm(av))
+        normal = av / area
+        if len(ent) == 2:
+            c1, P1 = ent[1]
+            _, x1 = _poly_area_centroid(P1)
+            shift = xc - x1
+            fc.append((c0, c1)); fbc.append(BC_INTERIOR); fid.append(0)
+        elif len(ent) == 1:
+            shift = np.zeros(3)
+            if classify_boundary is None:
+                raise ValueError("boundary face in a mesh declared closed")
+            bc, bid = classify_boundary(xc, normal)
+            fc.append((c0, -1)); fbc.append(bc); fid.append(bid)
+        else:
+            raise ValueError("face shared by more than two cells")
+        fn.append(normal); fa.append(area); fx.append(xc); fs.append(shift)
+    return dict(dim=3, cell_volume=vol, cell_centroid=cen,
+                face_cells=np.array(fc, dtype=np.int32).reshape(-1, 2),
+                face_normal=np.array(fn).reshape(-1, 3), face_area=np.array(fa),
+                face_centroid=np.array(fx).reshape(-1, 3), face_shift=np.array(fs).reshape(-1, 3),
+                face_bc=np.array(fbc, dtype=np.int32), face_bc_id=np.array(fid, dtype=np.int32))
+
+
+_HEX_FACES = [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (2, 3, 7, 6), (0, 4, 7, 3), (1, 2, 6, 5)]
+_CUBE = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+
+
+def _tet_faces(v):
+    """Four outward-ordered triangles of the tetrahedron v[0..3]."""
+    P = [np.array(x[1:]) for x in v]
+    faces = []
+    for skip in range(4):
+        tri = [v[j] for j in range(4) if j != skip]
+        a, b, c = (np.array(t[1:]) for t in tri)
+        if np.dot(np.cross(b - a, c - a), a - P[skip]) < 0:
+            tri = [tri[0], tri[2], tri[1]]
+        faces.append(tri)
+    return faces
+
+
+def box_mesh_3d(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, kind="hex", periodic=(True, True, True),
+                classify_boundary=None):
+    """Box of nx*ny*nz cubes: hexahedra, 6 tetrahedra per cube (Kuhn split
+    along the main diagonal, conforming between cubes), or 2 triangular
+    prisms per cube.  Periodic along the flagged axes."""
+    n = (nx, ny, nz)
+    h = (lx / nx, ly / ny, lz / nz)
+
+    def v(i, j, k):
+        idx = [i, j, k]
+        vid = 0
+        for d in range(3):
+            m = n[d] if periodic[d] else n[d] + 1
+            vid = vid * m + (idx[d] % n[d] if periodic[d] else idx[d])
+        return (vid, i * h[0], j * h[1], k * h[2])
+
+    cells = []
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                cv = [v(i + a, j + b, k + c) for (a, b, c) in _CUBE]
+                if kind == "hex":
+                    cells.append([[cv[q] for q in f] for f in _HEX_FACES])
+                elif kind == "tet":
+                    import itertools
+                    for perm in itertools.permutations(range(3)):
+                        p = [0, 0, 0]
+                        path = [tuple(p)]
+                        for ax in perm:
+                            p[ax] += 1
+                            path.append(tuple(p))
+                        tv = [v(i + a, j + b, k + c) for (a, b, c) in path]
+                        cells.append(_tet_faces(tv))
+                elif kind == "prism":
+                    for tri in ((0, 1, 2), (0, 2, 3)):
+                        bot = [cv[t] for t in tri]
+                        top = [cv[t + 4] for t in tri]
+                        cells.append([[bot[0], bot[2], bot[1]], [top[0], top[1], top[2]],
+                                      [bot[0], bot[1], top[1], top[0]], [bot[1], bot[2], top[2], top[1]],
+                                      [bot[2], bot[0], top[0], top[2]]])
+                else:
+                    raise ValueError(kind)
+    return build_mesh_3d(cells, classify_boundary)
+
+
+def case_box_wave_3d(n=3, kind="tet", nv=8, half_width=5.0, kn=0.1, Pr=2.0 / 3.0, omega=0.81, amp=0.1,
+                     limiter=1):
+    """3D periodic box [0,1]^3 of n^3 cubes (hex, tet or prism cells) with a
+    density/temperature wave and a drift; Cartesian nv^3 velocity grid."""
+    mesh = box_mesh_3d(n, n, n, kind=kind)
+    vg = tensor_vgrid(nv, half_width, 3)
+    gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 1.0), limiter=limiter, dim=3)
+    x = mesh["cell_centroid"]
+    prim0 = np.zeros((len(x), 5))
+    prim0[:, 0] = 1.0 + amp * np.sin(2 * math.pi * x[:, 0]) * np.cos(2 * math.pi * x[:, 2])
+    prim0[:, 1] = 0.1
+    prim0[:, 2] = -0.05 * np.sin(2 * math.pi * x[:, 1])
+    prim0[:, 3] = 0.05
+    prim0[:, 4] = 1.0 + 0.5 * amp * np.cos(2 * math.pi * x[:, 1])
+    return dict(name=f"box3d_{kind}_{len(x)}_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+
+
+def case_channel_3d(n=3, kind="hex", nv=8, half_width=5.0, kn=0.1, Pr=2.0 / 3.0, omega=0.81, t_wall=1.2,
+                    u_wall=0.3):
+    """3D box periodic in x and y between two isothermal walls at z = 0 and
+    z = 1; the top wall slides in x (moving-wall Couette start)."""
+    def classify(xf, nrm):
+        return (BC_WALL, 1) if xf[2] > 0.5 else (BC_WALL, 2)
+    mesh = box_mesh_3d(n, n, n, kind=kind, periodic=(True, True, False), classify_boundary=classify)
+    vg = tensor_vgrid(nv, half_width, 3)
+    bc = np.array([[1.0, 0.0, 0.0, 0.0, 1.0],
+                   [1.0, u_wall, 0.0, 0.0, t_wall],
+                   [1.0, 0.0, 0.0, 0.0, 1.0]])
+    gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 1.0), bc_prim=bc, dim=3)
+    x = mesh["cell_centroid"]
+    prim0 = np.zeros((len(x), 5))
+    prim0[:, 0] = 1.0 + 0.05 * np.sin(2 * math.pi * x[:, 0])
+    prim0[:, 4] = 1.0
+    return dict(name=f"channel3d_{kind}_{len(x)}_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)

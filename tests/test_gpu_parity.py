@@ -258,3 +258,60 @@ def test_full_size_cylinder_fp64():
     idx = np.array([0, 1, 199, 200, 5000, 12345, 19999])
     fg, fo = s.f()[idx], o.f()[idx]
     assert f_rel_err(fg, fo) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["tet", "hex", "prism"])
+def test_3d_periodic_fp64(kind):
+    """3D cells (4, 6 and 5 faces), 9^3 = 729 velocities: two full blocks of
+    256 lanes and a ragged tail."""
+    ugks = _gpu()
+    c = cases.case_box_wave_3d(kind=kind, nv=9)
+    _say(f"case {c['name']}: fp64, 15 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert s.tensor_grid and s.ncomp == 1
+    assert s.dt == pytest.approx(o.dt, rel=1e-15)
+    s.step(15)
+    o.step(15)
+    _compare(s, o)
+
+
+@pytest.mark.parametrize("kind", ["hex", "prism"])
+def test_3d_channel_sliding_wall_fp64(kind):
+    ugks = _gpu()
+    c = cases.case_channel_3d(kind=kind, nv=9)
+    _say(f"case {c['name']}: fp64, 15 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    s.step(15)
+    o.step(15)
+    _compare(s, o)
+
+
+def test_3d_unstructured_velocity_set_fp64():
+    """A velocity point set that is not a Cartesian product (points of a
+    Cartesian grid kept inside a ball, weights = cell volumes): the direct
+    exponential path."""
+    ugks = _gpu()
+    c = cases.case_box_wave_3d(kind="tet", nv=12, half_width=5.0)
+    u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+    keep = (u ** 2).sum(1) <= 5.0 ** 2
+    c["vgrid"] = dict(dim=3, u=np.ascontiguousarray(u[keep]), w=np.ascontiguousarray(w[keep]))
+    _say(f"case {c['name']} ball of {keep.sum()} velocities: fp64, 10 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert not s.tensor_grid
+    s.step(10)
+    o.step(10)
+    _compare(s, o)
+
+
+def test_2d_unstructured_velocity_set_fp64():
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+    keep = (u ** 2).sum(1) <= 14.0 ** 2
+    c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(u[keep]), w=np.ascontiguousarray(w[keep]))
+    _say(f"case {c['name']} disc of {keep.sum()} velocities: fp64, 20 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert not s.tensor_grid
+    s.step(20)
+    o.step(20)
+    _compare(s, o)

@@ -529,3 +529,59 @@ def test_mirror_symmetry():
     exp = Wa[src].copy()
     exp[:, 1] = -Wa[src, 1]
     np.testing.assert_allclose(Wb, exp, rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# 3D: the same invariants on tetrahedra, hexahedra and prisms
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["tet", "hex", "prism"])
+def test_3d_conservation_and_uniform_state(kind):
+    c = cases.case_box_wave_3d(kind=kind)
+    o = oracle.Oracle(c)
+    vol = c["mesh"]["cell_volume"]
+    W0, _ = o.macros()
+    o.step(8)
+    W, _ = o.macros()
+    d = (W * vol[:, None]).sum(0) - (W0 * vol[:, None]).sum(0)
+    assert np.abs(d).max() < 1e-13 * (W0[:, 0] * vol).sum()
+    assert np.abs(W - W0).max() > 1e-4
+    u = cases.case_box_wave_3d(kind=kind, amp=0.0)
+    u["prim0"][:, 1:4] = [0.2, -0.1, 0.3]
+    o = oracle.Oracle(u)
+    W0, _ = o.macros()
+    o.step(5)
+    W, _ = o.macros()
+    np.testing.assert_allclose(W, W0, rtol=1e-14, atol=1e-15)
+
+
+def test_3d_free_transport_of_linear_data_is_exact():
+    mesh = cases.box_mesh_3d(6, 6, 6, kind="tet")
+    nc = len(mesh["cell_volume"])
+    vg = cases.tensor_vgrid(4, 1.5, 3)
+    gas = cases.gas_params(1.0, 0.5, 1e30, limiter=0, dim=3)
+    prim0 = np.tile([1.0, 0.0, 0.0, 0.0, 1.0], (nc, 1))
+    o = oracle.Oracle(dict(mesh=mesh, vgrid=vg, gas=gas, prim0=prim0))
+    u, x = vg["u"], mesh["cell_centroid"]
+    A = 2.0 + 0.1 * np.arange(len(u)) / len(u)
+    B = np.array([0.3, -0.2, 0.25])
+    f = A[None, None, :] + ((x - 0.5) @ B)[:, None, None]
+    o.set_f(f)
+    o.step(1)
+    g = o.f()
+    inner = [i for i in range(nc) if np.all(np.abs(x[i] - 0.5) < 0.17)]
+    assert len(inner) > 10
+    ex = A[None, :] + ((x[inner] - 0.5) @ B)[:, None] - o.dt * (u @ B)[None, :]
+    np.testing.assert_allclose(g[inner, 0, :], ex, rtol=1e-13)
+
+
+def test_3d_channel_with_sliding_wall_conserves_mass():
+    c = cases.case_channel_3d(kind="prism")
+    o = oracle.Oracle(c)
+    vol = c["mesh"]["cell_volume"]
+    m0 = (o.macros()[0][:, 0] * vol).sum()
+    o.step(10)
+    W, _ = o.macros()
+    assert abs((W[:, 0] * vol).sum() - m0) < 1e-14 * m0
+    # the sliding wall drags the gas along x near the top
+    top = c["mesh"]["cell_centroid"][:, 2] > 0.6
+    assert W[top, 1].mean() > 0.0
