@@ -634,121 +634,21 @@ template <int D, bool TENSOR> struct Gauss {
     }
 };
 
-// Raw moments of the stage-1 distribution about U^n, from which its heat
-// flux about U^{n+1} follows without a second pass over f:
-// 2D: S0, S_a, S_ab (xx, xy, yy), T_a = sum v_a |v|^2 h, B0, B_a
-// 3D: S0, S_a, S_ab (xx, xy, xz, yy, yz, zz), T_a
-template <int D> struct QMom;
-template <> struct QMom<2> {
-    static constexpr int N = 11;
-    __device__ static __forceinline__ void add(double *m, const double (&v)[2], double w, double h, double b)
-    {
-        const double wh = w * h, v2 = v[0] * v[0] + v[1] * v[1];
-        m[0] += wh;
-        m[1] += wh * v[0];
-        m[2] += wh * v[1];
-        m[3] += wh * v[0] * v[0];
-        m[4] += wh * v[0] * v[1];
-        m[5] += wh * v[1] * v[1];
-        m[6] += wh * v[0] * v2;
-        m[7] += wh * v[1] * v2;
-        m[8] += w * b;
-        m[9] += w * b * v[0];
-        m[10] += w * b * v[1];
-    }
-    __device__ static __forceinline__ void heat_flux(const double *m, const double (&dl)[2], double (&q)[2])
-    {
-        const double S[2][2] = {{m[3], m[4]}, {m[4], m[5]}};
-        const double tr = m[3] + m[5], d2 = dl[0] * dl[0] + dl[1] * dl[1];
-        const double dS = dl[0] * m[1] + dl[1] * m[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const double Sd = S[a][0] * dl[0] + S[a][1] * dl[1];
-            q[a] = 0.5 * (m[6 + a] - 2.0 * Sd + d2 * m[1 + a] - dl[a] * tr + 2.0 * dl[a] * dS - dl[a] * d2 * m[0] +
-                          m[9 + a] - dl[a] * m[8]);
-        }
-    }
-};
-template <> struct QMom<3> {
-    static constexpr int N = 13;
-    __device__ static __forceinline__ void add(double *m, const double (&v)[3], double w, double h, double)
-    {
-        const double wh = w * h, v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-        m[0] += wh;
-        m[1] += wh * v[0];
-        m[2] += wh * v[1];
-        m[3] += wh * v[2];
-        m[4] += wh * v[0] * v[0];
-        m[5] += wh * v[0] * v[1];
-        m[6] += wh * v[0] * v[2];
-        m[7] += wh * v[1] * v[1];
-        m[8] += wh * v[1] * v[2];
-        m[9] += wh * v[2] * v[2];
-        m[10] += wh * v[0] * v2;
-        m[11] += wh * v[1] * v2;
-        m[12] += wh * v[2] * v2;
-    }
-    __device__ static __forceinline__ void heat_flux(const double *m, const double (&dl)[3], double (&q)[3])
-    {
-        const double S[3][3] = {{m[4], m[5], m[6]}, {m[5], m[7], m[8]}, {m[6], m[8], m[9]}};
-        const double tr = m[4] + m[7] + m[9], d2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-        const double dS = dl[0] * m[1] + dl[1] * m[2] + dl[2] * m[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double Sd = S[a][0] * dl[0] + S[a][1] * dl[1] + S[a][2] * dl[2];
-            q[a] = 0.5 * (m[10 + a] - 2.0 * Sd + d2 * m[1 + a] - dl[a] * tr + 2.0 * dl[a] * dS - dl[a] * d2 * m[0]);
-        }
-    }
-};
-
-// Net outflow S u_n dt rho_w H_w (and the b part) of the particles the
-// wall faces of cell gi send back at velocity k (u_n <= 0).  Returns false
-// when no wall face of the cell reflects at this velocity.
-template <int D, bool TENSOR>
-__device__ __forceinline__ bool wall_reflected(const CellGeo<D> &gi, const FaceGeo<D> *fg, const FaceEq<D> *fe,
-                                               const Gauss<D, TENSOR> gauss, int nf, int k, unsigned kx,
-                                               const double (&u)[D], double dt, const double (&rho_w)[Dim<D>::MF],
-                                               double (&out)[Dim<D>::NC])
-{
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M;
-    bool any = false;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) out[c] = 0.0;
-#pragma unroll
-    for (int j = 0; j < MF; ++j) {
-        if (j >= nf) break;
-        const FaceGeo<D> &F = fg[gi.face[j]];
-        if (F.bc != 3) continue;
-        double un = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
-        if (un > 0.0) continue;
-        const FaceEq<D> &e = fe[gi.face[j]];
-        const double Hw = rho_w[j] * e.pref * gauss(j, kx, u, e.lam, e.U);
-        const double sa = F.area * un * dt;
-        out[0] += sa * Hw;
-        if constexpr (NC > 1) out[1] += sa * e.bh * Hw;
-        any = true;
-    }
-    (void)k;
-    return any;
-}
-
 // One workgroup per cell; threads stride over the cell's velocities.
+//   wall:   (wall cells only) incident and unit-density reflected mass fluxes
+//           summed over velocities -> wall density;
 //   pass 1: for each velocity, limited slopes (own cell, and the upwind
 //           neighbour where it is upwind), the time-integrated flux through
-//           every face, and the stage-1 value (without the wall's reflected
-//           particles) -> written to f_out; moments accumulated on the fly;
-//   wall:   reduction of the incident and unit-density reflected mass fluxes
-//           -> wall density; the reflected particles' contribution to the
-//           moments;
-//   macro:  workgroup reduction -> W^{n+1}, tau^{n+1}, q^{n+1};
-//   pass 2: each thread re-reads what it wrote, adds the reflected
-//           particles, applies stage 2 and writes f^{n+1}.
+//           every face, the stage-1 value -> written to f_out; moments of the
+//           net outflow accumulated on the fly;
+//   macro:  workgroup reduction -> W^{n+1}, tau^{n+1};
+//   heat:   each thread re-reads its stage-1 values -> q^{n+1};
+//   pass 2: each thread re-reads its stage-1 values, applies stage 2 and
+//           writes f^{n+1}.
 template <int D, typename FT, int BS, bool TENSOR>
 __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2, NQ = QMom<D>::N;
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
     constexpr int NT = MF + 1;  // Gaussian tables: one per face slot, one for the cell
     extern __shared__ double smem[];
     const int i = blockIdx.x, tid = threadIdx.x;
@@ -789,7 +689,9 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             if (which < nf) {
                 const FaceEq<D> &e = fe[gi.face[which]];
                 lam = e.lam;
-                Ud = e.U[ax];
+                Ud = e.U[0];
+                if (ax == 1) Ud = e.U[1];
+                if (D == 3 && ax == 2) Ud = e.U[D - 1];
             } else {
                 lam = pn.lam;
                 Ud = pn.U[0];
@@ -799,16 +701,61 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             const double c = p.u1d[idx] - Ud;
             smem[t] = exp(-lam * c * c);
         }
-        __syncthreads();
+    }
+    __syncthreads();
+
+    // Alg. 1 line 9 (wall density) first, for wall cells only: the incident
+    // particles' mass flux and the unit-density reflected flux, summed over
+    // velocities; rho_w makes the net mass flux through the wall vanish
+    // (Eq. maxWalldes).  Knowing rho_w up front, the sweep below adds the
+    // reflected particles directly.
+    double rho_w[MF];
+#pragma unroll
+    for (int j = 0; j < MF; ++j) rho_w[j] = 0.0;
+    if (has_wall) {
+        double wsum[2 * MF];
+#pragma unroll
+        for (int j = 0; j < 2 * MF; ++j) wsum[j] = 0.0;
+        for (int k = tid; k < nv; k += BS) {
+            double u[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) u[d] = p.u[d * nv + k];
+            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+            const double wk = p.w[k];
+            double fi[NC], gri[NC][D];
+            limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+#pragma unroll
+            for (int j = 0; j < MF; ++j) {
+                if (j >= nf) break;
+                const FaceGeo<D> &F = fg[gi.face[j]];
+                if (F.bc != 3) continue;
+                double un = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+                if (un > 0.0) {
+                    double v = fi[0], ug = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        v += gri[0][d] * gi.dvec[j][d];
+                        ug += u[d] * gri[0][d];
+                    }
+                    wsum[2 * j] += wk * un * (dt * v - 0.5 * dt * dt * ug);
+                } else {
+                    const FaceEq<D> &e = fe[gi.face[j]];
+                    wsum[2 * j + 1] += wk * un * dt * e.pref * gauss(j, kx, u, e.lam, e.U);
+                }
+            }
+        }
+        block_reduce<BS>(wsum, red, OpAdd{});
+#pragma unroll
+        for (int j = 0; j < MF; ++j) rho_w[j] = (j < nf && wsum[2 * j + 1] != 0.0) ? -wsum[2 * j] / wsum[2 * j + 1] : 0.0;
     }
 
-    double mom[NW + NQ];
-    double wsum[2 * MF];  // per slot: incident mass flux, reflected unit-density flux
+    // Alg. 1 lines 4-8: per velocity, limited slopes, interface fluxes,
+    // stage 1; the moments of the net outflow give W^{n+1}
+    double mom[NW];
 #pragma unroll
-    for (int m = 0; m < NW + NQ; ++m) mom[m] = 0.0;
-#pragma unroll
-    for (int j = 0; j < 2 * MF; ++j) wsum[j] = 0.0;
-
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
     for (int k = tid; k < nv; k += BS) {
         double u[D], u2 = 0.0;
 #pragma unroll
@@ -817,7 +764,6 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             u2 += u[d] * u[d];
         }
         const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-        const double wk = p.w[k];
         double fi[NC], gri[NC][D];
         limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
         double out[NC];
@@ -878,18 +824,11 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
                     }
                     I[c] = dt * v - 0.5 * dt * dt * ug;
                 }
-                if (F.bc == 3) wsum[2 * j] += wk * un * I[0];
             } else {
-                const double H = e.pref * gauss(j, kx, u, e.lam, e.U);
-                if (F.bc == 3) {
-                    // reflected part waits for the wall density
-                    wsum[2 * j + 1] += wk * un * dt * H;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) I[c] = 0.0;
-                } else {
-                    I[0] = dt * H;
-                    if constexpr (NC > 1) I[1] = dt * e.bh * H;
-                }
+                // incoming from the wall (density rho_w) or the ghost Maxwellian
+                const double H = (F.bc == 3 ? rho_w[j] : 1.0) * e.pref * gauss(j, kx, u, e.lam, e.U);
+                I[0] = dt * H;
+                if constexpr (NC > 1) I[1] = dt * e.bh * H;
             }
             const double sa = (gi.side[j] ? -F.area : F.area) * un;
 #pragma unroll
@@ -901,62 +840,46 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             const double H = pref_n * gauss(MF, kx, u, pn.lam, pn.U);
             shakhov<D>(u, pn.U, pn.lam, shk_n, qn, bh_n, H, fpn[0], fpn[1]);
         }
-        double ft[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            ft[c] = fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]);
-            fout[base + (size_t)c * nv + k] = static_cast<FT>(ft[c]);
-        }
+        for (int c = 0; c < NC; ++c)
+            fout[base + (size_t)c * nv + k] =
+                static_cast<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
         // moments of the net outflow (Eq. macroscopicFlux summed over faces)
+        const double wk = p.w[k];
         mom[0] += wk * out[0];
 #pragma unroll
         for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
         mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
-        double v[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) v[d] = u[d] - pn.U[d];
-        QMom<D>::add(mom + NW, v, wk, ft[0], NC > 1 ? ft[NC - 1] : 0.0);
     }
 
-    // Alg. 1 line 9: wall density from zero net mass flux
-    double rho_w[MF];
-    if (has_wall) {
-        block_reduce<BS>(wsum, red, OpAdd{});
-#pragma unroll
-        for (int j = 0; j < MF; ++j) rho_w[j] = (j < nf && wsum[2 * j + 1] != 0.0) ? -wsum[2 * j] / wsum[2 * j + 1] : 0.0;
-        for (int k = tid; k < nv; k += BS) {
-            double u[D], u2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                u[d] = p.u[d * nv + k];
-                u2 += u[d] * u[d];
-            }
-            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-            const double wk = p.w[k];
-            double out[NC];
-            if (!wall_reflected<D, TENSOR>(gi, fg, fe, gauss, nf, k, kx, u, dt, rho_w, out)) continue;
-            mom[0] += wk * out[0];
-#pragma unroll
-            for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
-            mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
-            double v[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) v[d] = u[d] - pn.U[d];
-            QMom<D>::add(mom + NW, v, wk, -out[0] * gi.inv_vol, NC > 1 ? -out[NC - 1] * gi.inv_vol : 0.0);
-        }
-    }
-
-    // Alg. 1 line 10: Eq. macroscopicUpdata, then tau and q at t^{n+1}
+    // Alg. 1 line 10: Eq. macroscopicUpdata, then tau at t^{n+1}
     block_reduce<BS>(mom, red, OpAdd{});
     double W1[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) W1[m] = Wn[m] - mom[m] * gi.inv_vol;
     const Prim<D> p1 = to_prim<D>(W1);
     const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
-    double dl[D], qt[D], q1[D];
+
+    // heat flux of the stage-1 distribution about U^{n+1} (each thread
+    // re-reads the values it wrote)
+    double qt[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) dl[d] = p1.U[d] - pn.U[d];
-    QMom<D>::heat_flux(mom + NW, dl, qt);
+    for (int d = 0; d < D; ++d) qt[d] = 0.0;
+    for (int k = tid; k < nv; k += BS) {
+        double c[D], c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            c[d] = p.u[d * nv + k] - p1.U[d];
+            c2 += c[d] * c[d];
+        }
+        const double h = static_cast<double>(fout[base + k]);
+        const double b = NC > 1 ? static_cast<double>(fout[base + (size_t)(NC - 1) * nv + k]) : 0.0;
+        const double wt = 0.5 * p.w[k] * (c2 * h + b);
+#pragma unroll
+        for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
+    }
+    block_reduce<BS>(qt, red, OpAdd{});
+    double q1[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) q1[d] = qt[d] / (1.0 + Pr * dt / (2.0 * tau1));
 
@@ -983,20 +906,14 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
 #pragma unroll
         for (int d = 0; d < D; ++d) u[d] = p.u[d * nv + k];
         const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-        double ft[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) ft[c] = static_cast<double>(fout[base + (size_t)c * nv + k]);
-        if (has_wall) {
-            double out[NC];
-            if (wall_reflected<D, TENSOR>(gi, fg, fe, gauss, nf, k, kx, u, dt, rho_w, out))
-#pragma unroll
-                for (int c = 0; c < NC; ++c) ft[c] -= out[c] * gi.inv_vol;
-        }
         double fp[2];
         const double H = pref_1 * gauss(MF, kx, u, p1.lam, p1.U);
         shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) fout[base + (size_t)c * nv + k] = static_cast<FT>((ft[c] + a1 * fp[c]) * inv1);
+        for (int c = 0; c < NC; ++c) {
+            const size_t o = base + (size_t)c * nv + k;
+            fout[o] = static_cast<FT>((static_cast<double>(fout[o]) + a1 * fp[c]) * inv1);
+        }
     }
     if (tid == 0) {
         bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
@@ -1084,8 +1001,8 @@ hipError_t launch_prologue(const Params &p, hipStream_t s)
 template <int D, typename FT, int BS, bool TENSOR>
 void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
 {
-    constexpr int NW = D + 2, NQ = QMom<D>::N, MF = Dim<D>::MF;
-    constexpr int NRED = (NW + NQ > 2 * MF) ? NW + NQ : 2 * MF;
+    constexpr int NW = D + 2, MF = Dim<D>::MF;
+    constexpr int NRED = (NW > 2 * MF) ? NW : 2 * MF;
     const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (TENSOR ? p.ntab : 0) + (BS / 64) * NRED);
     hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR>), dim3(p.nc), dim3(BS), lds, s, p, static_cast<const FT *>(fi),
                        static_cast<FT *>(fo));
