@@ -645,13 +645,26 @@ template <int D, bool TENSOR> struct Gauss {
 //   heat:   each thread re-reads its stage-1 values -> q^{n+1};
 //   pass 2: each thread re-reads its stage-1 values, applies stage 2 and
 //           writes f^{n+1}.
+#ifndef UGKS_XCDS
+#define UGKS_XCDS 8  // accelerator complex dies of an MI355X
+#endif
+#ifndef UGKS_XCD_RUN
+#define UGKS_XCD_RUN 32
+#endif
 template <int D, typename FT, int BS, bool TENSOR>
 __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
     constexpr int NT = MF + 1;  // Gaussian tables: one per face slot, one for the cell
     extern __shared__ double smem[];
-    const int i = blockIdx.x, tid = threadIdx.x;
+    // Workgroups are dealt to the XCDs round-robin; hand each XCD runs of
+    // UGKS_XCD_RUN consecutive cells, so that mesh neighbours (whose slabs
+    // every workgroup re-reads) mostly meet in the same L2 while the runs,
+    // interleaved over the XCDs, keep the load balanced.
+    const int t = blockIdx.x / UGKS_XCDS;
+    const int i = ((t / UGKS_XCD_RUN) * UGKS_XCDS + blockIdx.x % UGKS_XCDS) * UGKS_XCD_RUN + t % UGKS_XCD_RUN;
+    if (i >= p.nc) return;
+    const int tid = threadIdx.x;
     const CellGeo<D> *cg = static_cast<const CellGeo<D> *>(p.cgeo);
     const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
     const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
@@ -1004,7 +1017,9 @@ void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
     constexpr int NW = D + 2, MF = Dim<D>::MF;
     constexpr int NRED = (NW > 2 * MF) ? NW : 2 * MF;
     const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (TENSOR ? p.ntab : 0) + (BS / 64) * NRED);
-    hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR>), dim3(p.nc), dim3(BS), lds, s, p, static_cast<const FT *>(fi),
+    constexpr int span = UGKS_XCDS * UGKS_XCD_RUN;
+    const unsigned grid = (unsigned)(((p.nc + span - 1) / span) * span);
+    hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR>), dim3(grid), dim3(BS), lds, s, p, static_cast<const FT *>(fi),
                        static_cast<FT *>(fo));
 }
 
