@@ -118,6 +118,22 @@ int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_g
  * lost positivity or finiteness (checked once at the end of the call). */
 int ugks_step(ugks_t *h, int nsteps, double *residual_out);
 
+/* Asynchronous stepping, for serving several cases at once on different
+ * streams.  ugks_step_async enqueues nsteps steps (as ugks_step) plus the
+ * copies of the non-physical flag and of the last step's residual into
+ * handle-owned pinned host memory, and returns without waiting.  Only one
+ * batch may be outstanding per handle (UGKS_ERR_STATE otherwise).
+ * ugks_poll sets *done = 0 while the batch runs; once it has finished it
+ * sets *done = 1, writes residual_out (nullable, [dim+2]) and returns
+ * UGKS_ERR_NONPHYSICAL if a cell lost positivity or finiteness. */
+int ugks_step_async(ugks_t *h, int nsteps);
+int ugks_poll(ugks_t *h, int *done, double *residual_out);
+
+/* Device bytes ugks_create would allocate for these inputs (host-side
+ * computation, no GPU needed): admission control against an HBM budget.
+ * Returns 0 for invalid arguments. */
+size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas);
+
 /* Copy the conservative variables W [n_cells][dim+2] = (rho, rho U, rho E)
  * and the heat flux q [n_cells][dim] (nullable) to host memory. */
 int ugks_macros(ugks_t *h, double *W_out, double *q_out);

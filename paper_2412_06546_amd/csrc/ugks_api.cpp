@@ -36,6 +36,12 @@ struct ugks {
     double prof_ms[2] = {0.0, 0.0};
     long prof_n = 0;
     std::vector<int> perm;  // internal velocity index -> caller's index
+    // asynchronous stepping: pinned copies of the error flag and residual,
+    // and an event marking the end of the last enqueued steps
+    int *h_err = nullptr;
+    double *h_res = nullptr;
+    hipEvent_t done_ev = nullptr;
+    int pending = 0;
 };
 
 static std::string g_create_error;
@@ -272,6 +278,22 @@ template <int D> void create_d(ugks_t *h, const ugks_mesh_t *m, const ugks_gas_t
     hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
 }
 
+// Device bytes a handle owns once created (the same sizes ugks_create
+// allocates; the temporary initial-state buffer is not counted).
+template <typename T> size_t nbytes(size_t n) { return sizeof(T) * (n ? n : 1); }
+size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab)
+{
+    const size_t NW = D + 2, ncomp = D == 2 ? 2 : 1;
+    size_t b = D == 2 ? nbytes<CellGeo<2>>(nc) + nbytes<FaceGeo<2>>(nf) + nbytes<FaceEq<2>>(nf)
+                      : nbytes<CellGeo<3>>(nc) + nbytes<FaceGeo<3>>(nf) + nbytes<FaceEq<3>>(nf);
+    b += nbytes<double>(D * nv) + nbytes<double>(nv) + nbytes<double>((size_t)std::max(1, nbc) * NW);
+    b += nbytes<double>(nc * NW) + nbytes<double>(nc * D) + nbytes<double>(nc * NW * D) + nbytes<double>(nc * NW);
+    b += nbytes<double>(nc) + nbytes<double>(NW) + nbytes<int>(2);
+    if (ntab) b += nbytes<double>(ntab) + nbytes<int>(nv);
+    b += 2 * nc * ncomp * nv * (fstore ? sizeof(float) : sizeof(double));
+    return b;
+}
+
 int fail(ugks_t *h, const Fail &e)
 {
     if (h) h->msg = e.msg;
@@ -281,6 +303,9 @@ int fail(ugks_t *h, const Fail &e)
 
 void release(ugks_t *h)
 {
+    if (h->h_err) (void)hipHostFree(h->h_err);
+    if (h->h_res) (void)hipHostFree(h->h_res);
+    if (h->done_ev) (void)hipEventDestroy(h->done_ev);
     void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
                     h->cell_dt, h->res, h->err, h->u1d, h->kidx};
     for (void *p : ptrs)
@@ -473,6 +498,73 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
         return fail(h, e);
     }
     return UGKS_OK;
+}
+
+extern "C" int ugks_step_async(ugks_t *h, int nsteps)
+{
+    if (!h) return UGKS_ERR_ARG;
+    if (nsteps <= 0) return fail(h, Fail{UGKS_ERR_ARG, "nsteps must be positive"});
+    if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "previous asynchronous steps not yet polled to completion"});
+    try {
+        if (!h->h_err) {
+            hip_check(hipHostMalloc((void **)&h->h_err, 2 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+            hip_check(hipHostMalloc((void **)&h->h_res, (h->dim + 2) * sizeof(double), hipHostMallocDefault),
+                      "hipHostMalloc");
+            hip_check(hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming), "hipEventCreate");
+        }
+        for (int s = 0; s < nsteps; ++s) {
+            hip_check(launch_prologue(h->P, h->stream), "prologue launch");
+            hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
+            h->cur ^= 1;
+            h->nstep++;
+        }
+        hip_check(launch_residual(h->P, h->res, h->stream), "residual launch");
+        hip_check(hipMemcpyAsync(h->h_err, h->err, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy flag");
+        hip_check(hipMemcpyAsync(h->h_res, h->res, (h->dim + 2) * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                  "copy residual");
+        hip_check(hipEventRecord(h->done_ev, h->stream), "hipEventRecord");
+        h->pending = 1;
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_poll(ugks_t *h, int *done, double *residual_out)
+{
+    if (!h || !done) return UGKS_ERR_ARG;
+    if (!h->pending) {
+        *done = 1;
+        return UGKS_OK;
+    }
+    const hipError_t q = hipEventQuery(h->done_ev);
+    if (q == hipErrorNotReady) {
+        *done = 0;
+        return UGKS_OK;
+    }
+    h->pending = 0;
+    *done = 1;
+    if (q != hipSuccess) return fail(h, Fail{UGKS_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q)});
+    if (residual_out)
+        for (int m = 0; m < h->dim + 2; ++m) residual_out[m] = h->h_res[m];
+    if (h->h_err[0])
+        return fail(h, Fail{UGKS_ERR_NONPHYSICAL,
+                            "non-physical state (rho <= 0, T <= 0 or non-finite) first at cell " + std::to_string(h->h_err[1])});
+    return UGKS_OK;
+}
+
+extern "C" size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas)
+{
+    if (!mesh || !vgrid || !gas || (mesh->dim != 2 && mesh->dim != 3) || vgrid->dim != mesh->dim || !vgrid->u)
+        return 0;
+    int n1d[3];
+    std::vector<double> axes;
+    std::vector<int> kidx;
+    size_t ntab = 0;
+    if (detect_tensor(mesh->dim, vgrid->n_vel, vgrid->u, n1d, axes, kidx) &&
+        (size_t)(Dim<3>::MF + 1) * axes.size() * sizeof(double) <= 48 * 1024)
+        ntab = axes.size();
+    return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab);
 }
 
 extern "C" int ugks_macros(ugks_t *h, double *W_out, double *q_out)

@@ -1,0 +1,212 @@
+"""Continuous batching of independent flow cases on one GPU.
+
+Requests (a case, an arrival time, a residual tolerance and a step cap)
+arrive over time.  A request is admitted, in arrival order, as soon as a slot
+is free and its device footprint (ugks_footprint_estimate, the bytes
+ugks_create will allocate) fits in what is left of the HBM budget.  Every
+admitted case owns a HIP stream; the server keeps a batch of steps enqueued
+on each (ugks_step_async), so the kernels of all active cases overlap on the
+device, polls them without blocking (ugks_poll), retires a case when its
+residual -- the L2 change of W over one step, relative to that of its first
+step -- falls below the tolerance or the step cap is reached, frees its
+memory and admits the next.  Each case's computation is independent of the
+others (own buffers, own stream, deterministic kernels), so its result in the
+mix equals its result alone.
+
+The backend is pluggable so that the scheduling logic can be exercised
+without a GPU (tests use a fake backend); GpuBackend is the product path.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    case: dict
+    arrival: float = 0.0       # seconds after the server starts
+    tol: float = 1e-6          # stop when max_m res_m / res_m(first step) <= tol
+    max_steps: int = 1000      # step cap
+    fstore: str = "f64"
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    steps: int = 0
+    converged: bool = False
+    residual: float = float("nan")
+    footprint: int = 0
+    updates: int = 0           # cell-velocity updates performed
+    W: Optional[np.ndarray] = None
+    q: Optional[np.ndarray] = None
+    error: str = ""
+
+    @property
+    def time_to_result(self) -> float:
+        return self.finished - self.arrival
+
+
+class GpuBackend:
+    """Runs each admitted case through the HIP library on its own stream."""
+
+    def __init__(self):
+        import torch
+        from . import ugks
+        if not torch.cuda.is_available():
+            raise RuntimeError("GpuBackend needs the GPU")
+        self._torch, self._ugks = torch, ugks
+
+    def footprint(self, req: Request) -> int:
+        return self._ugks.footprint_estimate(req.case, req.fstore)
+
+    def start(self, req: Request):
+        import ctypes
+        stream = self._torch.cuda.Stream()  # default priority
+        s = self._ugks.Solver(req.case, fstore=req.fstore, stream=ctypes.c_void_p(stream.cuda_stream))
+        s._serve_stream = stream            # keep the stream alive with the solver
+        return s
+
+
+class Server:
+    def __init__(self, budget_bytes: int, max_active: int = 16, chunk: int = 10, backend=None,
+                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = lambda: time.sleep(1e-4)):
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.chunk = int(chunk)
+        self.backend = backend if backend is not None else GpuBackend()
+        self.clock = clock
+        self.idle = idle
+        self.peak_used = 0
+        self.log: List[tuple] = []   # (time, event, rid, bytes in use)
+
+    def run(self, requests: List[Request]) -> List[Result]:
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        results = {r.rid: Result(r.rid, r.arrival) for r in requests}
+        active = {}  # rid -> [request, solver, footprint, first residual, steps queued]
+        used = 0
+        t0 = self.clock()
+        while pending or active:
+            now = self.clock() - t0
+            progressed = False
+            # admission: arrival order, while a slot is free and the footprint fits
+            while pending and pending[0].arrival <= now and len(active) < self.max_active:
+                req = pending[0]
+                res = results[req.rid]
+                fp = self.backend.footprint(req)
+                res.footprint = fp
+                if fp <= 0 or fp > self.budget:
+                    pending.pop(0)
+                    res.error = f"footprint {fp} B exceeds the budget of {self.budget} B"
+                    res.finished = now
+                    progressed = True
+                    continue
+                if used + fp > self.budget:
+                    break
+                pending.pop(0)
+                try:
+                    solver = self.backend.start(req)
+                    solver.step_async(1)   # the first step's residual normalises the rest
+                except Exception as exc:   # creation failure is reported, not fatal
+                    res.error = str(exc)
+                    res.finished = self.clock() - t0
+                    progressed = True
+                    continue
+                used += fp
+                self.peak_used = max(self.peak_used, used)
+                res.admitted = now
+                active[req.rid] = [req, solver, fp, None, 1]
+                self.log.append((now, "admit", req.rid, used))
+                progressed = True
+            # progress of the active cases
+            for rid in list(active):
+                req, solver, fp, r0, queued = active[rid]
+                res = results[rid]
+                try:
+                    r = solver.poll()
+                except Exception as exc:
+                    r, res.error = None, str(exc)
+                if r is None and not res.error:
+                    continue
+                progressed = True
+                res.steps = queued
+                done = bool(res.error)
+                if not done:
+                    if r0 is None:
+                        r0 = np.where(r > 0, r, 1.0)
+                        active[rid][3] = r0
+                    res.residual = float(np.max(r / r0))
+                    res.converged = res.residual <= req.tol
+                    done = res.converged or queued >= req.max_steps
+                if done:
+                    if not res.error:
+                        res.W, res.q = solver.macros()
+                    res.updates = res.steps * solver.nc * solver.nv
+                    solver.close()
+                    del active[rid]
+                    used -= fp
+                    res.finished = self.clock() - t0
+                    self.log.append((res.finished, "retire", rid, used))
+                else:
+                    n = min(self.chunk, req.max_steps - queued)
+                    solver.step_async(n)
+                    active[rid][4] = queued + n
+            if not progressed:
+                self.idle()
+        return [results[r.rid] for r in requests]
+
+    @staticmethod
+    def summary(results: List[Result]) -> dict:
+        ok = [r for r in results if not r.error]
+        t = np.array([r.time_to_result for r in ok]) if ok else np.zeros(1)
+        span = max((r.finished for r in ok), default=0.0) - min((r.arrival for r in ok), default=0.0)
+        ups = sum(r.updates for r in ok)
+        return {
+            "cases": len(results),
+            "completed": len(ok),
+            "converged": sum(r.converged for r in ok),
+            "capped": sum((not r.converged) for r in ok),
+            "rejected_or_failed": len(results) - len(ok),
+            "p50_time_to_result_s": float(np.percentile(t, 50)),
+            "p99_time_to_result_s": float(np.percentile(t, 99)),
+            "makespan_s": float(span),
+            "updates_per_s": float(ups / span) if span > 0 else 0.0,
+        }
+
+
+def poisson_stream(n_cases: int = 128, rate: float = 4.0, seed: int = 0, n_cells=(2000, 50000), n_1d=(20, 64),
+                   ma=(0.5, 6.0), kn=(1e-3, 1.0), tol: float = 1e-6, max_steps: int = 1000, fstore: str = "f32"):
+    """Requests of the serving workload: Poisson arrivals (rate per second),
+    cylinder cases with N_c log-uniform in n_cells (all triangles), N_1D x N_1D
+    velocity grids with N_1D uniform, Ma uniform, Kn log-uniform; velocity
+    half-width max(6, 0.4 U_inf + 6 sqrt(R T_s)) around 0 (the paper's sizing
+    rule for its cylinder velocity mesh, Section 4.1)."""
+    import math
+    from . import cases
+    rng = cases.SplitMix64(seed)
+    t = 0.0
+    out = []
+    for rid in range(n_cases):
+        t += -math.log(1.0 - rng.uniform()) / rate
+        nc_target = math.exp(math.log(n_cells[0]) + rng.uniform() * (math.log(n_cells[1]) - math.log(n_cells[0])))
+        n1 = int(n_1d[0] + rng.uniform() * (n_1d[1] - n_1d[0] + 1))
+        m = ma[0] + rng.uniform() * (ma[1] - ma[0])
+        k = math.exp(math.log(kn[0]) + rng.uniform() * (math.log(kn[1]) - math.log(kn[0])))
+        # all-triangle O-grid: n_theta x n_r quads, each cut in two
+        n_r = max(4, int(round(math.sqrt(nc_target / 8.0))))
+        n_theta = max(8, int(round(nc_target / (2 * n_r))))
+        T_s = 1.0 + m * m / 3.0
+        u_inf = m * cases.sound_speed(1.0)
+        half = max(6.0, 0.4 * u_inf + 6.0 * math.sqrt(cases.R_GAS * T_s))
+        case = cases.case_cylinder(n_theta=n_theta, n_r=n_r, n_tri_rings=n_r, nv=n1, half_width=half, ma=m, kn=k,
+                                   h_first=0.02, seed=seed + rid)
+        out.append(Request(rid, case, arrival=t, tol=tol, max_steps=max_steps, fstore=fstore))
+    return out

@@ -63,6 +63,12 @@ def load_library(path: str = LIB_PATH):
                               C.c_void_p, C.POINTER(C.c_void_p)]
     L.ugks_step.restype = C.c_int
     L.ugks_step.argtypes = [C.c_void_p, C.c_int, _dp]
+    L.ugks_step_async.restype = C.c_int
+    L.ugks_step_async.argtypes = [C.c_void_p, C.c_int]
+    L.ugks_poll.restype = C.c_int
+    L.ugks_poll.argtypes = [C.c_void_p, C.POINTER(C.c_int), _dp]
+    L.ugks_footprint_estimate.restype = C.c_size_t
+    L.ugks_footprint_estimate.argtypes = [C.POINTER(ugks_mesh_t), C.POINTER(ugks_vgrid_t), C.POINTER(ugks_gas_t)]
     L.ugks_macros.restype = C.c_int
     L.ugks_macros.argtypes = [C.c_void_p, _dp, _dp]
     L.ugks_get_f.restype = C.c_int
@@ -111,44 +117,59 @@ def current_stream_handle():
     return None
 
 
+def _structs(case, fstore, keep):
+    """ugks_mesh_t, ugks_vgrid_t, ugks_gas_t and prim0 for a case dict; the
+    numpy buffers they point to are appended to keep."""
+    m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
+    dim = int(m["dim"])
+
+    def d(x):
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(_dp)
+
+    def i(x):
+        a = np.ascontiguousarray(x, dtype=np.int32)
+        keep.append(a)
+        return a.ctypes.data_as(_ip)
+
+    mesh = ugks_mesh_t(dim, len(m["cell_volume"]), len(m["face_area"]), d(m["cell_volume"]), d(m["cell_centroid"]),
+                       i(m["face_cells"]), d(m["face_normal"]), d(m["face_area"]), d(m["face_centroid"]),
+                       d(m["face_shift"]) if m.get("face_shift") is not None else None,
+                       i(m["face_bc"]), i(m["face_bc_id"]))
+    vgrid = ugks_vgrid_t(dim, len(vg["w"]), d(vg["u"]), d(vg["w"]))
+    bc = np.asarray(gas["bc_prim"], dtype=np.float64)
+    g = ugks_gas_t(gas["Pr"], gas["omega"], gas["mu_ref"], gas["cfl"], gas["dt_override"], gas["limiter_k"],
+                   int(gas["limiter"]), UGKS_F32 if fstore == "f32" else UGKS_F64, bc.shape[0], d(bc))
+    return mesh, vgrid, g, d(case["prim0"])
+
+
+def footprint_estimate(case, fstore: str = "f64") -> int:
+    """Device bytes ugks_create would allocate for this case (host only)."""
+    L = load_library()
+    keep = []
+    mesh, vgrid, g, _ = _structs(case, fstore, keep)
+    return int(L.ugks_footprint_estimate(C.byref(mesh), C.byref(vgrid), C.byref(g)))
+
+
 class Solver:
     """A flow case on the GPU: ugks_create ... ugks_destroy."""
 
     def __init__(self, case, fstore: str = "f64", stream=None):
         L = self._L = load_library()
-        m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
-        self.dim = int(m["dim"])
-        self.nc = len(m["cell_volume"])
-        self.nv = len(vg["w"])
-        keep = self._keep = []
-
-        def d(x):
-            a = np.ascontiguousarray(x, dtype=np.float64)
-            keep.append(a)
-            return a.ctypes.data_as(_dp)
-
-        def i(x):
-            a = np.ascontiguousarray(x, dtype=np.int32)
-            keep.append(a)
-            return a.ctypes.data_as(_ip)
-
-        mesh = ugks_mesh_t(self.dim, self.nc, len(m["face_area"]), d(m["cell_volume"]), d(m["cell_centroid"]),
-                           i(m["face_cells"]), d(m["face_normal"]), d(m["face_area"]), d(m["face_centroid"]),
-                           d(m["face_shift"]) if m.get("face_shift") is not None else None,
-                           i(m["face_bc"]), i(m["face_bc_id"]))
-        vgrid = ugks_vgrid_t(self.dim, self.nv, d(vg["u"]), d(vg["w"]))
-        bc = np.asarray(gas["bc_prim"], dtype=np.float64)
-        g = ugks_gas_t(gas["Pr"], gas["omega"], gas["mu_ref"], gas["cfl"], gas["dt_override"], gas["limiter_k"],
-                       int(gas["limiter"]), UGKS_F32 if fstore == "f32" else UGKS_F64, bc.shape[0], d(bc))
+        self.dim = int(case["mesh"]["dim"])
+        self.nc = len(case["mesh"]["cell_volume"])
+        self.nv = len(case["vgrid"]["w"])
+        keep = []
+        mesh, vgrid, g, prim0 = _structs(case, fstore, keep)
         if stream is None:
             stream = current_stream_handle()
         self.stream = stream
         h = C.c_void_p()
-        code = L.ugks_create(C.byref(mesh), C.byref(vgrid), C.byref(g), d(case["prim0"]), stream, C.byref(h))
+        code = L.ugks_create(C.byref(mesh), C.byref(vgrid), C.byref(g), prim0, stream, C.byref(h))
         _check(L, None, code)
         self._h = h
         self.ncomp = L.ugks_n_comp(h)
-        self._keep = []
 
     def close(self):
         if getattr(self, "_h", None):
@@ -182,6 +203,17 @@ class Solver:
         r = np.zeros(self.dim + 2) if residual else None
         _check(self._L, self._h, self._L.ugks_step(self._h, int(n), r.ctypes.data_as(_dp) if residual else None))
         return r
+
+    def step_async(self, n: int = 1):
+        """Enqueue n steps and return at once (see poll)."""
+        _check(self._L, self._h, self._L.ugks_step_async(self._h, int(n)))
+
+    def poll(self):
+        """None while the enqueued steps run, else the last step's residual."""
+        done = C.c_int(0)
+        r = np.zeros(self.dim + 2)
+        _check(self._L, self._h, self._L.ugks_poll(self._h, C.byref(done), r.ctypes.data_as(_dp)))
+        return r if done.value else None
 
     def macros(self):
         W = np.zeros((self.nc, self.dim + 2))

@@ -1,0 +1,89 @@
+"""Serving on the GPU: admission by footprint, overlapped cases, and each
+result equal to the same case run alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2412_06546_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_06546_amd import ugks
+    ugks.load_library()
+    return ugks
+
+
+def _mix():
+    return [
+        cases.case_periodic_wave(nx=10, ny=6, nv=20, seed=1),
+        cases.case_cylinder_small(n_theta=32, n_r=10, nv=20),
+        cases.case_periodic_wave(nx=16, ny=8, nv=32, seed=2, Pr=2.0 / 3.0, omega=0.81),
+        cases.case_box_wave_3d(n=3, kind="prism", nv=8),
+        cases.case_cylinder_small(n_theta=40, n_r=12, nv=28, ma=3.0),
+        cases.case_periodic_wave(nx=8, ny=8, nv=16, seed=3),
+    ]
+
+
+def test_footprint_estimate_matches_allocation():
+    ugks = _gpu()
+    cs = _mix()
+    c = cases.case_cylinder_small()
+    keep = (c["vgrid"]["u"] ** 2).sum(1) < 100
+    c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(c["vgrid"]["u"][keep]), w=np.ascontiguousarray(c["vgrid"]["w"][keep]))
+    cs.append(c)
+    for c in cs:
+        for fs in ("f64", "f32"):
+            est = ugks.footprint_estimate(c, fs)
+            s = ugks.Solver(c, fstore=fs)
+            assert s.footprint_bytes == est, (c.get("name"), fs)
+            s.close()
+
+
+def test_each_result_in_the_mix_equals_the_result_alone():
+    ugks = _gpu()
+    from paper_2412_06546_amd.serve import Request, Server
+    cs = _mix()
+    steps = 25
+    fps = [ugks.footprint_estimate(c) for c in cs]
+    budget = sorted(fps)[-1] + sorted(fps)[-2]           # at most about two at a time
+    reqs = [Request(i, c, arrival=0.002 * i, tol=0.0, max_steps=steps) for i, c in enumerate(cs)]
+    print(f"serving {len(cs)} cases, budget {budget} B", flush=True)
+    srv = Server(budget, max_active=4, chunk=7)
+    res = srv.run(reqs)
+    s = Server.summary(res)
+    print(s, flush=True)
+    assert s["completed"] == len(cs)
+    assert srv.peak_used <= budget
+    assert any(r.admitted > r.arrival for r in res)      # some waited for memory
+    for r, c in zip(res, cs):
+        assert r.steps == steps
+        alone = ugks.Solver(c)
+        alone.step(steps)
+        W, q = alone.macros()
+        alone.close()
+        assert np.array_equal(r.W, W), r.rid
+        assert np.array_equal(r.q, q), r.rid
+
+
+def test_async_steps_match_synchronous_steps():
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    a, b = ugks.Solver(c), ugks.Solver(c)
+    a.step(12)
+    b.step_async(5)
+    while b.poll() is None:
+        pass
+    b.step_async(7)
+    r = None
+    while r is None:
+        r = b.poll()
+    assert np.array_equal(a.macros()[0], b.macros()[0])
+    with pytest.raises(ugks.UgksError):
+        b.step_async(1)
+        b.step_async(1)    # a second batch before the first was polled

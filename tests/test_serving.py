@@ -1,0 +1,105 @@
+"""Scheduling logic of the serving loop, on a fake backend (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_2412_06546_amd.serve import Request, Server
+
+
+class FakeJob:
+    def __init__(self, clock, cost, decay):
+        self.clock, self.cost, self.decay = clock, cost, decay
+        self.nc, self.nv = 10, 4
+        self.busy_until = None
+        self.done_steps = 0
+        self.r = 1.0
+
+    def step_async(self, n):
+        assert self.busy_until is None, "one batch outstanding at a time"
+        self.busy_until = self.clock.t + self.cost * n
+        self.n = n
+
+    def poll(self):
+        if self.busy_until is None or self.clock.t < self.busy_until:
+            return None
+        self.busy_until = None
+        self.done_steps += self.n
+        self.r = self.decay ** (self.done_steps - 1)
+        return np.array([self.r, 1.0 * self.r, 0.5 * self.r, 2.0 * self.r])
+
+    def macros(self):
+        return np.full((self.nc, 4), float(self.done_steps)), np.zeros((self.nc, 2))
+
+    def close(self):
+        self.closed = True
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def tick(self):
+        self.t += 0.01
+
+
+class FakeBackend:
+    def __init__(self, clock, sizes, costs, decays):
+        self.clock, self.sizes, self.costs, self.decays = clock, sizes, costs, decays
+        self.started = []
+
+    def footprint(self, req):
+        return self.sizes[req.rid]
+
+    def start(self, req):
+        self.started.append(req.rid)
+        return FakeJob(self.clock, self.costs[req.rid], self.decays[req.rid])
+
+
+def _run(sizes, costs, decays, arrivals, budget, max_active=8, tol=1e-3, max_steps=200, chunk=5):
+    clock = FakeClock()
+    be = FakeBackend(clock, sizes, costs, decays)
+    srv = Server(budget, max_active=max_active, chunk=chunk, backend=be, clock=clock, idle=clock.tick)
+    reqs = [Request(i, {}, arrival=a, tol=tol, max_steps=max_steps) for i, a in enumerate(arrivals)]
+    return srv, be, srv.run(reqs)
+
+
+def test_admission_respects_budget_and_order():
+    sizes = [40, 30, 50, 20, 60, 10]
+    srv, be, res = _run(sizes, [0.02] * 6, [0.5] * 6, [0.0, 0.0, 0.01, 0.02, 0.02, 0.5], budget=100)
+    assert srv.peak_used <= 100
+    assert be.started == sorted(be.started)          # arrival (FIFO) order
+    assert all(r.error == "" for r in res)
+    # memory in use never exceeds the budget at any logged instant
+    assert max(u for _, _, _, u in srv.log) <= 100
+    # requests waited for memory: some were admitted after they arrived
+    assert any(r.admitted > r.arrival + 1e-9 for r in res)
+
+
+def test_oversized_request_is_rejected_without_blocking_the_queue():
+    srv, be, res = _run([50, 500, 20], [0.01] * 3, [0.5] * 3, [0.0, 0.0, 0.0], budget=100)
+    assert "exceeds the budget" in res[1].error
+    assert res[0].error == "" and res[2].error == ""
+    assert 1 not in be.started
+
+
+def test_convergence_and_step_cap():
+    # decay 0.5 per step reaches 1e-3 after 11 steps; decay 0.999 never does
+    srv, be, res = _run([10, 10], [0.01, 0.01], [0.5, 0.999], [0.0, 0.0], budget=100, tol=1e-3, max_steps=50)
+    assert res[0].converged and res[0].steps < 50 and res[0].residual <= 1e-3
+    assert not res[1].converged and res[1].steps == 50
+    s = Server.summary(res)
+    assert s["converged"] == 1 and s["capped"] == 1
+    assert s["p99_time_to_result_s"] >= s["p50_time_to_result_s"] > 0
+
+
+def test_slots_limit_concurrency():
+    srv, be, res = _run([1] * 6, [0.05] * 6, [0.9] * 6, [0.0] * 6, budget=100, max_active=2, max_steps=20)
+    live = 0
+    peak = 0
+    for _, ev, _, _ in srv.log:
+        live += 1 if ev == "admit" else -1
+        peak = max(peak, live)
+    assert peak == 2
+    assert all(r.steps == 20 for r in res)
