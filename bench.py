@@ -112,6 +112,30 @@ def run_gpu(case, fstore: str, steps: int, warmup: int):
     return out
 
 
+def run_serving(args):
+    """Continuous batching of a Poisson stream of independent 2D cases: all-
+    triangle cylinder meshes of 2k-50k cells, 20^2-64^2 velocity grids, Ma in
+    [0.5, 6], Kn in [1e-3, 1], f in FP32 with FP64 macros, each run to a
+    residual of 1e-6 or the step cap."""
+    from paper_2412_06546_amd import serve
+    t0 = time.perf_counter()
+    reqs = serve.poisson_stream(n_cases=args.serving, rate=4.0, max_steps=args.serving_steps, fstore="f32")
+    print(f"# generated {len(reqs)} cases in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    srv = serve.Server(int(args.serving_budget_gb * 1e9), max_active=16, chunk=20)
+    res = srv.run(reqs)
+    summ = serve.Server.summary(res)
+    for r in res:
+        if r.error:
+            print(f"# case {r.rid} ({reqs[r.rid].case['name']}): {r.error}", file=sys.stderr, flush=True)
+    line = {"metric": "serving time-to-result (p50/p99) and cell-velocity updates/s", "value": summ["p50_time_to_result_s"],
+            "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": f"Poisson stream (4/s) of {len(reqs)} cylinder cases, 2k-50k triangles, "
+                                   f"20^2-64^2 velocities, tol 1e-6, cap {args.serving_steps} steps, f32",
+                       "budget_bytes": srv.budget, "peak_bytes": srv.peak_used},
+            "serving": summ}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +145,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="instead: serve a Poisson stream (4/s) of N cylinder cases and report p50/p99")
+    ap.add_argument("--serving-steps", type=int, default=400, help="step cap per served case")
+    ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -135,6 +163,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, 5)
+        return
+    if args.serving:
+        run_serving(args)
         return
 
     from paper_2412_06546_amd import cases

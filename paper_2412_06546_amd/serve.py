@@ -183,12 +183,15 @@ class Server:
 
 
 def poisson_stream(n_cases: int = 128, rate: float = 4.0, seed: int = 0, n_cells=(2000, 50000), n_1d=(20, 64),
-                   ma=(0.5, 6.0), kn=(1e-3, 1.0), tol: float = 1e-6, max_steps: int = 1000, fstore: str = "f32"):
+                   ma=(0.5, 6.0), kn=(1e-3, 1.0), tol: float = 1e-6, max_steps: int = 1000, fstore: str = "f32",
+                   dv_max: float = 0.7):
     """Requests of the serving workload: Poisson arrivals (rate per second),
     cylinder cases with N_c log-uniform in n_cells (all triangles), N_1D x N_1D
     velocity grids with N_1D uniform, Ma uniform, Kn log-uniform; velocity
     half-width max(6, 0.4 U_inf + 6 sqrt(R T_s)) around 0 (the paper's sizing
-    rule for its cylinder velocity mesh, Section 4.1)."""
+    rule for its cylinder velocity mesh, Section 4.1).  N_1D is raised where
+    needed so that the spacing stays below dv_max (in units of the free-stream
+    sqrt(2 R T)): a coarser grid cannot carry the free-stream Maxwellian."""
     import math
     from . import cases
     rng = cases.SplitMix64(seed)
@@ -206,7 +209,9 @@ def poisson_stream(n_cases: int = 128, rate: float = 4.0, seed: int = 0, n_cells
         T_s = 1.0 + m * m / 3.0
         u_inf = m * cases.sound_speed(1.0)
         half = max(6.0, 0.4 * u_inf + 6.0 * math.sqrt(cases.R_GAS * T_s))
+        n1 = max(n1, int(math.ceil(2.0 * half / dv_max)) + 1)    # trapezoid points: spacing 2 half / (n1 - 1)
         case = cases.case_cylinder(n_theta=n_theta, n_r=n_r, n_tri_rings=n_r, nv=n1, half_width=half, ma=m, kn=k,
                                    h_first=0.02, seed=seed + rid)
+        case["name"] += f"_ma{m:.2f}_kn{k:.1e}"
         out.append(Request(rid, case, arrival=t, tol=tol, max_steps=max_steps, fstore=fstore))
     return out

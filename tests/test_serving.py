@@ -103,3 +103,19 @@ def test_slots_limit_concurrency():
         peak = max(peak, live)
     assert peak == 2
     assert all(r.steps == 20 for r in res)
+
+
+def test_poisson_stream_recipe():
+    """Arrivals increase, every velocity grid resolves the free stream (spacing
+    at most dv_max), meshes stay within the requested cell range."""
+    from paper_2412_06546_amd.serve import poisson_stream
+    reqs = poisson_stream(n_cases=4, n_cells=(2000, 3000), n_1d=(20, 24), ma=(5.5, 6.0), max_steps=7)
+    arr = [r.arrival for r in reqs]
+    assert all(b > a for a, b in zip(arr, arr[1:]))
+    for r in reqs:
+        u = r.case["vgrid"]["u"]
+        n1 = int(round(np.sqrt(len(u))))
+        du = np.diff(np.unique(u[:, 0])).max()
+        assert du <= 0.7 + 1e-12 and n1 > 24
+        assert 1500 <= len(r.case["mesh"]["cell_volume"]) <= 3500
+        assert r.max_steps == 7 and "_ma" in r.case["name"]
