@@ -167,10 +167,19 @@ int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
  * ugks_set_f use the caller's order. */
 int ugks_velocity_order(const ugks_t *h, int *perm_out);
 
+/* The library stores cells in its own order too: along a Morton (Z-order)
+ * curve through the cell centroids, so that consecutive stored cells -- the
+ * workgroups that share one XCD's L2 cache -- are mesh neighbours whatever
+ * the caller's numbering.  perm_out [n_cells] receives, for each stored
+ * position, the caller's cell index.  Every entry point that takes or
+ * returns per-cell host data (prim0, ugks_macros, ugks_get_f, ugks_set_f,
+ * the cell named by an error) uses the caller's numbering. */
+int ugks_cell_order(const ugks_t *h, int *perm_out);
+
 /* Device pointer of the current f (for zero-copy inspection):
- * [n_cells][n_comp][n_vel] in the storage precision and the library's
- * velocity order (ugks_velocity_order); valid until the next ugks_step or
- * ugks_destroy. */
+ * [n_cells][n_comp][n_vel] in the storage precision, the library's cell
+ * order (ugks_cell_order) and velocity order (ugks_velocity_order); valid
+ * until the next ugks_step or ugks_destroy. */
 const void *ugks_device_f(const ugks_t *h);
 
 void ugks_destroy(ugks_t *h);

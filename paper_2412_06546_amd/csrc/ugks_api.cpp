@@ -35,7 +35,8 @@ struct ugks {
     std::vector<hipEvent_t> ev;  // 3 per step: before prologue, before sweep, after sweep
     double prof_ms[2] = {0.0, 0.0};
     long prof_n = 0;
-    std::vector<int> perm;  // internal velocity index -> caller's index
+    std::vector<int> perm;     // stored velocity index -> caller's index
+    std::vector<int> cell_of;  // stored cell index -> caller's index
     // asynchronous stepping: pinned copies of the error flag and residual,
     // and an event marking the end of the last enqueued steps
     int *h_err = nullptr;
@@ -149,16 +150,11 @@ std::vector<int> direction_order(int D, int nv, const double *u)
     return idx;
 }
 
-template <int D>
-void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg, std::vector<FaceGeo<D>> &fgv,
-                    double limiter_k)
+// Caller's face records checked before anything is indexed by them.
+void validate_faces(const ugks_mesh_t *m, int nbc)
 {
-    constexpr int MF = Dim<D>::MF;
-    const int nc = m->n_cells, nf = m->n_faces;
-    cg.assign(nc, CellGeo<D>{});
-    fgv.assign(nf, FaceGeo<D>{});
-    std::vector<int> slot_count(nc, 0);
-    for (int f = 0; f < nf; ++f) {
+    const int nc = m->n_cells;
+    for (int f = 0; f < m->n_faces; ++f) {
         const int l = m->face_cells[2 * f], r = m->face_cells[2 * f + 1];
         const int bc = m->face_bc ? m->face_bc[f] : UGKS_BC_INTERIOR;
         const int bid = m->face_bc_id ? m->face_bc_id[f] : 0;
@@ -166,9 +162,118 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
         if ((r < 0) != (bc != UGKS_BC_INTERIOR))
             throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": boundary type does not match its cells"};
         if (bc < 0 || bc > 3) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": unknown boundary type"};
-        if (bc != UGKS_BC_INTERIOR && bc != UGKS_BC_OUTFLOW && (bid < 0 || bid >= h->nbc))
+        if (bc != UGKS_BC_INTERIOR && bc != UGKS_BC_OUTFLOW && (bid < 0 || bid >= nbc))
             throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": boundary state index out of range"};
         if (!(m->face_area[f] > 0.0)) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": non-positive area"};
+    }
+}
+
+// The library stores cells along a Morton (Z-order) curve through their
+// centroids, so that a run of consecutive stored cells -- the workgroups
+// that one XCD, and so one L2, receives -- is a compact patch of the mesh
+// whatever the caller's numbering; neighbours' f slabs are then re-read from
+// L2 rather than HBM.  Faces are stored sorted by their first stored cell,
+// which keeps the face prologue's cell reads local as well.  The relabelled
+// mesh owns its arrays; cell_of/face_of map stored indices to the caller's.
+struct StoredMesh {
+    std::vector<int> cell_of, face_of, pos_of;
+    std::vector<double> vol, cen, nrm, area, fcen, shift;
+    std::vector<int> fcells, bc, bcid;
+    ugks_mesh_t mesh{};
+};
+
+void relabel(const ugks_mesh_t *m, StoredMesh &S)
+{
+    const int D = m->dim, nc = m->n_cells, nf = m->n_faces;
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int c = 0; c < nc; ++c)
+        for (int d = 0; d < D; ++d) {
+            lo[d] = std::min(lo[d], m->cell_centroid[(size_t)c * D + d]);
+            hi[d] = std::max(hi[d], m->cell_centroid[(size_t)c * D + d]);
+        }
+    const int bits = 21;
+    const double top = (double)((1u << bits) - 1);
+    std::vector<std::pair<unsigned long long, int>> key(nc);
+    for (int c = 0; c < nc; ++c) {
+        unsigned long long code = 0;
+        for (int d = 0; d < D; ++d) {
+            const double span = hi[d] - lo[d];
+            const double x = span > 0.0 ? (m->cell_centroid[(size_t)c * D + d] - lo[d]) / span : 0.0;
+            const unsigned long long qd = (unsigned long long)std::min(top, std::max(0.0, std::floor(x * top)));
+            for (int b = 0; b < bits; ++b) code |= ((qd >> b) & 1ull) << (b * D + d);
+        }
+        key[c] = {code, c};
+    }
+    std::sort(key.begin(), key.end());
+    S.cell_of.resize(nc);
+    S.pos_of.resize(nc);
+    for (int i = 0; i < nc; ++i) {
+        S.cell_of[i] = key[i].second;
+        S.pos_of[key[i].second] = i;
+    }
+    std::vector<std::pair<long long, int>> fkey(nf);
+    for (int f = 0; f < nf; ++f) {
+        const int l = S.pos_of[m->face_cells[2 * f]], r = m->face_cells[2 * f + 1];
+        const int first = r >= 0 ? std::min(l, S.pos_of[r]) : l;
+        fkey[f] = {(long long)first, f};
+    }
+    std::sort(fkey.begin(), fkey.end());
+    S.face_of.resize(nf);
+    for (int i = 0; i < nf; ++i) S.face_of[i] = fkey[i].second;
+
+    S.vol.resize(nc);
+    S.cen.resize((size_t)nc * D);
+    for (int i = 0; i < nc; ++i) {
+        const int c = S.cell_of[i];
+        S.vol[i] = m->cell_volume[c];
+        for (int d = 0; d < D; ++d) S.cen[(size_t)i * D + d] = m->cell_centroid[(size_t)c * D + d];
+    }
+    S.nrm.resize((size_t)nf * D);
+    S.fcen.resize((size_t)nf * D);
+    S.shift.assign((size_t)nf * D, 0.0);
+    S.area.resize(nf);
+    S.fcells.resize(2 * (size_t)nf);
+    S.bc.resize(nf);
+    S.bcid.resize(nf);
+    for (int i = 0; i < nf; ++i) {
+        const int f = S.face_of[i], r = m->face_cells[2 * f + 1];
+        S.fcells[2 * i] = S.pos_of[m->face_cells[2 * f]];
+        S.fcells[2 * i + 1] = r >= 0 ? S.pos_of[r] : -1;
+        S.area[i] = m->face_area[f];
+        S.bc[i] = m->face_bc ? m->face_bc[f] : UGKS_BC_INTERIOR;
+        S.bcid[i] = m->face_bc_id ? m->face_bc_id[f] : 0;
+        for (int d = 0; d < D; ++d) {
+            S.nrm[(size_t)i * D + d] = m->face_normal[(size_t)f * D + d];
+            S.fcen[(size_t)i * D + d] = m->face_centroid[(size_t)f * D + d];
+            if (m->face_shift) S.shift[(size_t)i * D + d] = m->face_shift[(size_t)f * D + d];
+        }
+    }
+    S.mesh = *m;
+    S.mesh.cell_volume = S.vol.data();
+    S.mesh.cell_centroid = S.cen.data();
+    S.mesh.face_cells = S.fcells.data();
+    S.mesh.face_normal = S.nrm.data();
+    S.mesh.face_area = S.area.data();
+    S.mesh.face_centroid = S.fcen.data();
+    S.mesh.face_shift = S.shift.data();
+    S.mesh.face_bc = S.bc.data();
+    S.mesh.face_bc_id = S.bcid.data();
+}
+
+template <int D>
+void build_geometry(const StoredMesh &S, std::vector<CellGeo<D>> &cg, std::vector<FaceGeo<D>> &fgv, double limiter_k)
+{
+    const ugks_mesh_t *m = &S.mesh;
+    auto cname = [&](int c) { return "cell " + std::to_string(S.cell_of[c]); };
+    auto fname = [&](int f) { return "face " + std::to_string(S.face_of[f]); };
+    constexpr int MF = Dim<D>::MF;
+    const int nc = m->n_cells, nf = m->n_faces;
+    cg.assign(nc, CellGeo<D>{});
+    fgv.assign(nf, FaceGeo<D>{});
+    std::vector<int> slot_count(nc, 0);
+    for (int f = 0; f < nf; ++f) {
+        const int l = m->face_cells[2 * f], r = m->face_cells[2 * f + 1];
+        const int bc = m->face_bc[f], bid = m->face_bc_id[f];
         FaceGeo<D> &F = fgv[f];
         F.l = l;
         F.r = r;
@@ -176,7 +281,7 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
         F.bcid = bid;
         F.area = m->face_area[f];
         for (int d = 0; d < D; ++d) {
-            const double sh = m->face_shift ? m->face_shift[(size_t)f * D + d] : 0.0;
+            const double sh = m->face_shift[(size_t)f * D + d];
             F.n[d] = m->face_normal[(size_t)f * D + d];
             F.dl[d] = m->face_centroid[(size_t)f * D + d] - m->cell_centroid[(size_t)l * D + d];
             F.dr[d] = r >= 0 ? m->face_centroid[(size_t)f * D + d] - sh - m->cell_centroid[(size_t)r * D + d] : 0.0;
@@ -185,7 +290,7 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
             const int c = s == 0 ? l : r;
             if (c < 0) continue;
             const int j = slot_count[c]++;
-            if (j >= MF) throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + " has more than " + std::to_string(MF) + " faces"};
+            if (j >= MF) throw Fail{UGKS_ERR_ARG, cname(c) + " has more than " + std::to_string(MF) + " faces"};
             CellGeo<D> &g = cg[c];
             g.face[j] = f;
             g.side[j] = s;
@@ -196,8 +301,8 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
     for (int c = 0; c < nc; ++c) {
         CellGeo<D> &g = cg[c];
         g.nf = slot_count[c];
-        if (g.nf < D + 1) throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + " has fewer than dim+1 faces"};
-        if (!(m->cell_volume[c] > 0.0)) throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + ": non-positive volume"};
+        if (g.nf < D + 1) throw Fail{UGKS_ERR_ARG, cname(c) + " has fewer than dim+1 faces"};
+        if (!(m->cell_volume[c] > 0.0)) throw Fail{UGKS_ERR_ARG, cname(c) + ": non-positive volume"};
         g.inv_vol = 1.0 / m->cell_volume[c];
         const double kh = limiter_k * std::pow(m->cell_volume[c], 1.0 / D);
         g.eps2 = kh * kh * kh;
@@ -215,7 +320,7 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
             if (n < 0) continue;
             const int f = g.face[j];
             for (int d = 0; d < D; ++d) {
-                const double sh = m->face_shift ? m->face_shift[(size_t)f * D + d] : 0.0;
+                const double sh = m->face_shift[(size_t)f * D + d];
                 dn[j][d] = m->cell_centroid[(size_t)n * D + d] + (g.side[j] == 0 ? sh : -sh) - m->cell_centroid[(size_t)c * D + d];
             }
             for (int a = 0; a < D; ++a)
@@ -225,7 +330,7 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
             int bj = -1;
             for (int t = 0; t < slot_count[n]; ++t)
                 if (gn.face[t] == f && gn.side[t] != g.side[j]) bj = t;
-            if (bj < 0) throw Fail{UGKS_ERR_ARG, "inconsistent face adjacency at face " + std::to_string(f)};
+            if (bj < 0) throw Fail{UGKS_ERR_ARG, "inconsistent face adjacency at " + fname(f)};
             g.back[j] = bj;
         }
         double Gi[9] = {0}, tr = 0.0, det;
@@ -264,11 +369,11 @@ void build_geometry(ugks_t *h, const ugks_mesh_t *m, std::vector<CellGeo<D>> &cg
     }
 }
 
-template <int D> void create_d(ugks_t *h, const ugks_mesh_t *m, const ugks_gas_t *gas)
+template <int D> void create_d(ugks_t *h, const StoredMesh &S, const ugks_gas_t *gas)
 {
     std::vector<CellGeo<D>> cg;
     std::vector<FaceGeo<D>> fgv;
-    build_geometry<D>(h, m, cg, fgv, gas->limiter_k);
+    build_geometry<D>(S, cg, fgv, gas->limiter_k);
     h->cgeo = dev_alloc<CellGeo<D>>(h, cg.size());
     h->fgeo = dev_alloc<FaceGeo<D>>(h, fgv.size());
     h->feq = dev_alloc<FaceEq<D>>(h, fgv.size());
@@ -299,6 +404,14 @@ int fail(ugks_t *h, const Fail &e)
     if (h) h->msg = e.msg;
     else g_create_error = e.msg;
     return e.code;
+}
+
+// err[1] holds the lowest stored index of a failing cell; the message names
+// the caller's index.
+std::string nonphysical_message(const ugks_t *h, int stored)
+{
+    const int c = stored >= 0 && stored < h->nc ? h->cell_of[stored] : stored;
+    return "non-physical state (rho <= 0, T <= 0 or non-finite) at cell " + std::to_string(c);
 }
 
 void release(ugks_t *h)
@@ -354,8 +467,12 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             const double *p = prim0 + (size_t)i * (D + 2);
             if (!(p[0] > 0.0) || !(p[D + 1] > 0.0)) throw Fail{UGKS_ERR_ARG, "prim0: rho and T must be positive"};
         }
-        if (D == 2) create_d<2>(h, mesh, gas);
-        else create_d<3>(h, mesh, gas);
+        validate_faces(mesh, h->nbc);
+        StoredMesh S;
+        relabel(mesh, S);
+        h->cell_of = S.cell_of;
+        if (D == 2) create_d<2>(h, S, gas);
+        else create_d<3>(h, S, gas);
         int n1d[3] = {0, 0, 0};
         std::vector<double> axes;
         std::vector<int> kidx;
@@ -401,7 +518,10 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         upload(h->u, uT.data(), sizeof(double) * uT.size(), h->stream);
         upload(h->w, wP.data(), sizeof(double) * nv, h->stream);
         if (h->nbc) upload(h->bcp, gas->bc_prim, sizeof(double) * h->nbc * (D + 2), h->stream);
-        upload(prim_d, prim0, sizeof(double) * nc * (D + 2), h->stream);
+        std::vector<double> primS(nc * (D + 2));
+        for (size_t i = 0; i < nc; ++i)
+            for (int m = 0; m < D + 2; ++m) primS[i * (D + 2) + m] = prim0[(size_t)h->cell_of[i] * (D + 2) + m];
+        upload(prim_d, primS.data(), sizeof(double) * nc * (D + 2), h->stream);
         const int err0[2] = {0, 0x7fffffff};
         upload(h->err, err0, sizeof(err0), h->stream);
 
@@ -493,7 +613,7 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
                 h->prof_ms[1] += a;
                 h->prof_n++;
             }
-        if (err[0]) return fail(h, Fail{UGKS_ERR_NONPHYSICAL, "non-physical state (rho <= 0, T <= 0 or non-finite) first at cell " + std::to_string(err[1])});
+        if (err[0]) return fail(h, Fail{UGKS_ERR_NONPHYSICAL, nonphysical_message(h, err[1])});
     } catch (const Fail &e) {
         return fail(h, e);
     }
@@ -548,8 +668,7 @@ extern "C" int ugks_poll(ugks_t *h, int *done, double *residual_out)
     if (residual_out)
         for (int m = 0; m < h->dim + 2; ++m) residual_out[m] = h->h_res[m];
     if (h->h_err[0])
-        return fail(h, Fail{UGKS_ERR_NONPHYSICAL,
-                            "non-physical state (rho <= 0, T <= 0 or non-finite) first at cell " + std::to_string(h->h_err[1])});
+        return fail(h, Fail{UGKS_ERR_NONPHYSICAL, nonphysical_message(h, h->h_err[1])});
     return UGKS_OK;
 }
 
@@ -571,10 +690,16 @@ extern "C" int ugks_macros(ugks_t *h, double *W_out, double *q_out)
 {
     if (!h) return UGKS_ERR_ARG;
     try {
-        if (W_out)
-            hip_check(hipMemcpyAsync(W_out, h->W, sizeof(double) * h->nc * (h->dim + 2), hipMemcpyDeviceToHost, h->stream), "copy W");
-        if (q_out) hip_check(hipMemcpyAsync(q_out, h->q, sizeof(double) * h->nc * h->dim, hipMemcpyDeviceToHost, h->stream), "copy q");
+        const size_t nc = h->nc, NW = h->dim + 2, D = h->dim;
+        std::vector<double> W(W_out ? nc * NW : 0), q(q_out ? nc * D : 0);
+        if (W_out) hip_check(hipMemcpyAsync(W.data(), h->W, sizeof(double) * W.size(), hipMemcpyDeviceToHost, h->stream), "copy W");
+        if (q_out) hip_check(hipMemcpyAsync(q.data(), h->q, sizeof(double) * q.size(), hipMemcpyDeviceToHost, h->stream), "copy q");
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        for (size_t i = 0; i < nc; ++i) {
+            const size_t c = h->cell_of[i];
+            if (W_out) std::copy(&W[i * NW], &W[i * NW] + NW, W_out + c * NW);
+            if (q_out) std::copy(&q[i * D], &q[i * D] + D, q_out + c * D);
+        }
     } catch (const Fail &e) {
         return fail(h, e);
     }
@@ -596,8 +721,11 @@ extern "C" int ugks_get_f(ugks_t *h, double *f_out)
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
             for (size_t i = 0; i < n; ++i) tmp[i] = t32[i];
         }
-        for (size_t r = 0; r < rows; ++r)
-            for (size_t k = 0; k < nv; ++k) f_out[r * nv + h->perm[k]] = tmp[r * nv + k];
+        const size_t nk = h->ncomp;
+        for (size_t r = 0; r < rows; ++r) {
+            double *dst = f_out + ((size_t)h->cell_of[r / nk] * nk + r % nk) * nv;
+            for (size_t k = 0; k < nv; ++k) dst[h->perm[k]] = tmp[r * nv + k];
+        }
     } catch (const Fail &e) {
         return fail(h, e);
     }
@@ -610,8 +738,11 @@ extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
     try {
         const size_t nv = h->nv, rows = (size_t)h->nc * h->ncomp, n = rows * nv;
         std::vector<double> tmp(n);
-        for (size_t r = 0; r < rows; ++r)
-            for (size_t k = 0; k < nv; ++k) tmp[r * nv + k] = f_in[r * nv + h->perm[k]];
+        const size_t nk = h->ncomp;
+        for (size_t r = 0; r < rows; ++r) {
+            const double *src = f_in + ((size_t)h->cell_of[r / nk] * nk + r % nk) * nv;
+            for (size_t k = 0; k < nv; ++k) tmp[r * nv + k] = src[h->perm[k]];
+        }
         if (h->fstore == UGKS_F64) {
             upload(h->f[h->cur], tmp.data(), sizeof(double) * n, h->stream);
             hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
@@ -633,6 +764,13 @@ extern "C" int ugks_velocity_order(const ugks_t *h, int *perm_out)
 {
     if (!h || !perm_out) return UGKS_ERR_ARG;
     std::copy(h->perm.begin(), h->perm.end(), perm_out);
+    return UGKS_OK;
+}
+
+extern "C" int ugks_cell_order(const ugks_t *h, int *perm_out)
+{
+    if (!h || !perm_out) return UGKS_ERR_ARG;
+    std::copy(h->cell_of.begin(), h->cell_of.end(), perm_out);
     return UGKS_OK;
 }
 

@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     L.ugks_profile_read.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_long)]
     L.ugks_velocity_order.restype = C.c_int
     L.ugks_velocity_order.argtypes = [C.c_void_p, _ip]
+    L.ugks_cell_order.restype = C.c_int
+    L.ugks_cell_order.argtypes = [C.c_void_p, _ip]
     L.ugks_device_f.restype = C.c_void_p
     L.ugks_device_f.argtypes = [C.c_void_p]
     L.ugks_destroy.restype = None
@@ -230,6 +232,12 @@ class Solver:
         """Stored velocity position -> caller's velocity index."""
         perm = np.zeros(self.nv, dtype=np.int32)
         _check(self._L, self._h, self._L.ugks_velocity_order(self._h, perm.ctypes.data_as(_ip)))
+        return perm
+
+    def cell_order(self):
+        """Stored cell position -> caller's cell index."""
+        perm = np.zeros(self.nc, dtype=np.int32)
+        _check(self._L, self._h, self._L.ugks_cell_order(self._h, perm.ctypes.data_as(_ip)))
         return perm
 
     def profile(self, enable: bool = True):

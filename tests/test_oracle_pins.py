@@ -531,6 +531,23 @@ def test_mirror_symmetry():
     np.testing.assert_allclose(Wb, exp, rtol=1e-12, atol=1e-13)
 
 
+def test_renumbering_cells_and_faces_commutes_with_the_step():
+    """The scheme is defined on the mesh, not on its numbering: renumbering
+    cells and faces (which also reorders each cell's faces) permutes the
+    result and changes nothing else."""
+    from renumber import renumber
+    base = cases.case_cylinder_small(n_theta=24, n_r=8, nv=12)
+    shuf, cp = renumber(base, 3)
+    a, b = oracle.Oracle(base), oracle.Oracle(shuf)
+    a.step(4)
+    b.step(4)
+    Wa, qa = a.macros()
+    Wb, qb = b.macros()
+    np.testing.assert_allclose(Wb, Wa[cp], rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(qb, qa[cp], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(b.f(), a.f()[cp], rtol=1e-12, atol=1e-15)
+
+
 # --------------------------------------------------------------------------
 # 3D: the same invariants on tetrahedra, hexahedra and prisms
 # --------------------------------------------------------------------------
