@@ -66,6 +66,9 @@ def lib():
         L.orc_get.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_set_f.argtypes = [C.c_void_p, _dp]
         L.orc_residual.argtypes = [C.c_void_p, _dp]
+        L.orc_n_wall.restype = C.c_int
+        L.orc_n_wall.argtypes = [C.c_void_p]
+        L.orc_wall_flux.argtypes = [C.c_void_p, _dp]
         L.orc_time_integrals.argtypes = [C.c_double, C.c_double, _dp]
         L.orc_prim_of_cons.argtypes = [C.c_int, _dp, _dp]
         L.orc_cons_of_prim.argtypes = [C.c_int, _dp, _dp]
@@ -166,6 +169,16 @@ class Oracle:
         r = np.zeros(self.dim + 2)
         self._L.orc_residual(self._h, r.ctypes.data_as(_dp))
         return r
+
+    def wall_flux(self):
+        """Macroscopic flux through every wall face (increasing face index)
+        in the last step, per unit area and time: [n_wall][dim + 2]
+        (Section 2.5)."""
+        n = self._L.orc_n_wall(self._h)
+        F = np.zeros((n, self.dim + 2))
+        if n:
+            self._L.orc_wall_flux(self._h, F.ctypes.data_as(_dp))
+        return F
 
 
 # ---- pieces, for the pin tests ---------------------------------------------

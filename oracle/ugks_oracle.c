@@ -89,6 +89,8 @@ typedef struct orc {
     double *Ginv;          /* [nc][D][D]; all zero when the stencil is degenerate */
     double *eps2;          /* Venkatakrishnan epsilon^2 per cell */
     int nwall, *wall_face;
+    double *wallF; /* [nwall][NW]: macroscopic flux through each wall face in the
+                      last step, per unit area and time (Section 2.5) */
     double dt;
     double *f; /* [nv][nc][NC]: velocity-major, as the k loop walks it */
     double *W; /* [nc][NW] conservative */
@@ -547,6 +549,7 @@ orc_t *orc_create(const orc_input_t *in)
     o->wall_face = (int *)malloc(sizeof(int) * (o->nwall ? o->nwall : 1));
     for (int f = 0, n = 0; f < o->nf; ++f)
         if (o->fbc[f] == 3) o->wall_face[n++] = f;
+    o->wallF = (double *)calloc((size_t)(o->nwall ? o->nwall : 1) * o->NW, sizeof(double));
 
     /* least-squares normal matrices, inverted once */
     o->Ginv = (double *)calloc((size_t)o->nc * D * D, sizeof(double));
@@ -633,7 +636,7 @@ void orc_destroy(orc_t *o)
     free(o->vol); free(o->xc); free(o->fcell); free(o->fn); free(o->fa); free(o->fx); free(o->fs);
     free(o->fbc); free(o->fbcid); free(o->u); free(o->w); free(o->bcp);
     free(o->ncf); free(o->cf); free(o->cside); free(o->dcf); free(o->nnb); free(o->nb); free(o->dnb);
-    free(o->Ginv); free(o->eps2); free(o->wall_face); free(o->f); free(o->W); free(o->q);
+    free(o->Ginv); free(o->eps2); free(o->wall_face); free(o->wallF); free(o->f); free(o->W); free(o->q);
     free(o);
 }
 
@@ -662,6 +665,16 @@ void orc_get(const orc_t *o, double *W, double *q, double *f)
 }
 
 void orc_residual(const orc_t *o, double *res) { memcpy(res, o->res, sizeof(double) * o->NW); }
+
+/* Section 2.5: the macroscopic flux F_w through every wall face in the last
+ * step (wall faces in increasing face index), per unit area and time:
+ * mass, momentum [D], energy.  Surface pressure p_w = F_m . n, shear stress
+ * |F_m - p_w n| and heat flux F_energy follow from it. */
+int orc_n_wall(const orc_t *o) { return o->nwall; }
+void orc_wall_flux(const orc_t *o, double *out)
+{
+    memcpy(out, o->wallF, sizeof(double) * (size_t)o->nwall * o->NW);
+}
 
 /* ------------------------------------------------------------------------ */
 /* one time step (Algorithm 1)                                              */
@@ -928,6 +941,8 @@ static void one_step(orc_t *o)
             for (int d = 0; d < D; ++d) F[1 + d] += o->w[k] * uk[d] * Hf;
             F[D + 1] += o->w[k] * 0.5 * (u2 * Hf + Bf);
         }
+        /* surface quantities: the wall's macroscopic flux per unit time */
+        for (int m = 0; m < NW; ++m) o->wallF[(size_t)wi * NW + m] = F[m] / dt;
     }
 
     /* line 10: Eq. macroscopicUpdata */

@@ -436,6 +436,69 @@ def test_closed_channel_conserves_mass():
     assert abs(m1 - m0) < 1e-14 * m0
 
 
+def _wall_flux_by_definition(case, f_gas, dt):
+    """Macroscopic wall flux of the first step from a spatially uniform gas
+    (zero slopes), written out from Section 2.5: particles leaving the gas
+    carry the gas distribution, particles leaving the wall the wall
+    Maxwellian of density rho_w fixed by zero net mass flux; moments
+    (1, u, (u^2 h + b)/2) of u_n times the time integral, per unit time."""
+    m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
+    u, w = vg["u"], vg["w"]
+    D = m["dim"]
+    out = []
+    for f in np.nonzero(m["face_bc"] == cases.BC_WALL)[0]:
+        n = m["face_normal"][f]
+        bp = np.asarray(gas["bc_prim"])[m["face_bc_id"][f]]
+        Uw, lam = bp[1:1 + D], 1.0 / bp[D + 1]
+        gh = (lam / math.pi) ** (D / 2.0) * np.exp(-lam * ((u - Uw) ** 2).sum(1))   # unit density
+        gb = (3 - D) / (2.0 * lam) * gh
+        un = u @ n
+        out_k = un > 0
+        rho_w = -(w * un * f_gas[0])[out_k].sum() / (w * un * gh)[~out_k].sum()
+        h = np.where(out_k, f_gas[0], rho_w * gh)
+        b = np.where(out_k, f_gas[1], rho_w * gb) if D == 2 else 0.0 * h
+        F = [(w * un * h).sum()] + [(w * un * u[:, d] * h).sum() for d in range(D)]
+        F.append((w * un * 0.5 * ((u ** 2).sum(1) * h + b)).sum())
+        out.append(np.array(F))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("U,T", [((0.0, 0.0), 1.0), ((0.4, 0.0), 1.3)])
+def test_wall_flux_of_a_uniform_gas_by_definition(U, T):
+    """Wall flux (surface quantities) of the first step from a uniform gas
+    between two walls, one moving: equal to the definition evaluated
+    directly; with the gas at rest at the wall temperature it is the
+    discrete pressure along the normal, with no mass flux, shear or heat
+    flux."""
+    mesh = cases.channel_quads(4, 5, 1.0, 1.0, y_bc=(cases.BC_WALL, 1))
+    top = mesh["face_centroid"][:, 1] > 0.5
+    mesh["face_bc_id"] = np.where((mesh["face_bc"] == cases.BC_WALL) & top, 2, mesh["face_bc_id"])
+    nc = len(mesh["cell_volume"])
+    bcp = np.array([[1.0, 0.0, 0.0, 1.0], [1.0, 0.0, 0.0, 1.0], [1.0, 0.25, 0.0, 1.0]])
+    prim = [0.9, U[0], U[1], T]
+    c = _small_case(mesh, nv=16, L=6.0, prim0=np.tile(prim, (nc, 1)), bc_prim=bcp)
+    o = oracle.Oracle(c)
+    f0 = o.f()[0]
+    o.step(1)
+    got = o.wall_flux()
+    ref = _wall_flux_by_definition(c, f0, o.dt)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * scale)
+    assert np.abs(got[:, 0]).max() <= 1e-13 * scale       # no particle crosses a wall
+    if U == (0.0, 0.0) and T == 1.0:
+        # bottom wall at rest and at the gas temperature: pressure only
+        u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+        bottom = [k for k, f in enumerate(np.nonzero(mesh["face_bc"] == cases.BC_WALL)[0])
+                  if not top[f]]
+        for k in bottom:
+            n = mesh["face_normal"][np.nonzero(mesh["face_bc"] == cases.BC_WALL)[0][k]]
+            p_disc = (w * (u @ n) ** 2 * f0[0]).sum()
+            Fm = got[k, 1:3]
+            assert Fm @ n == pytest.approx(p_disc, rel=1e-12)
+            assert np.linalg.norm(Fm - (Fm @ n) * n) <= 1e-13 * p_disc
+            assert abs(got[k, 3]) <= 1e-13 * p_disc
+
+
 @pytest.mark.parametrize("Pr", [1.0, 2.0 / 3.0])
 def test_uniform_relaxation_closed_form(Pr):
     """A spatially uniform non-equilibrium state: fluxes cancel, W stays, and
