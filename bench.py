@@ -101,7 +101,7 @@ def run_gpu(case, fstore: str, steps: int, warmup: int):
     sweep_ms, pro_ms, n = s.profile_read()
     s.profile(False)
     W, _ = s.macros()
-    bytes_per_value = 8 if fstore == "f64" else 4
+    bytes_per_value = {"f64": 8, "f32": 4, "bf16": 2}[fstore]
     alg_bytes = nc * nv * ncomp * bytes_per_value * 2      # read f once, write f once
     sweep_avg_s = sweep_ms / n / 1e3
     out = dict(ms_per_step=ms / steps, wall_s=wall, updates_per_s=nc * nv * steps / (ms / 1e3),
@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--fstore", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--fstore", choices=["f64", "f32", "bf16"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -174,13 +174,13 @@ def main():
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
     main_run = run_gpu(case, args.fstore, args.steps, args.warmup)
     print(f"# gpu {args.fstore}: {main_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    other = None
+    other = []
     if not args.no_secondary:
-        fs2 = "f32" if args.fstore == "f64" else "f64"
-        r2 = run_gpu(case, fs2, max(5, args.steps // 2), args.warmup)
-        other = {"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
-                 "sweep_ms": r2["sweep_ms_avg"], "achieved_gbs": r2["achieved_gbs"]}
-        print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        for fs2 in [x for x in ("f64", "f32", "bf16") if x != args.fstore]:
+            r2 = run_gpu(case, fs2, max(5, args.steps // 2), args.warmup)
+            other.append({"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
+                          "sweep_ms": r2["sweep_ms_avg"], "achieved_gbs": r2["achieved_gbs"]})
+            print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     traffic = measured_traffic(args.fstore)
     roofline = {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

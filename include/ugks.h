@@ -56,9 +56,13 @@ extern "C" {
 #define UGKS_BC_OUTFLOW 2  /* far field, ghost = the interior cell's state */
 #define UGKS_BC_WALL 3     /* Maxwellian isothermal wall (U_w, T_w) = bc_prim[face_bc_id] */
 
-/* f storage precision; every macroscopic quantity and every coefficient is FP64 */
+/* f storage precision; every macroscopic quantity, every coefficient and all
+ * arithmetic on f are FP64 (f is widened on load and rounded on store).
+ * UGKS_BF16 rounds to nearest (ties to even) from FP64 and flushes values
+ * below the FP32 normal range (1.18e-38) to zero. */
 #define UGKS_F64 0
 #define UGKS_F32 1
+#define UGKS_BF16 2
 
 /* Physical mesh (Section 2.3): finite volumes Omega_i with faces S_ij. */
 typedef struct {
@@ -95,7 +99,7 @@ typedef struct {
     double dt_override; /* > 0: use this time step instead of the CFL one */
     double limiter_k;   /* Venkatakrishnan constant K: eps^2 = (K |Omega_i|^(1/dim))^3 */
     int limiter;        /* 0 none (unlimited least squares), 1 Venkatakrishnan */
-    int fstore;         /* UGKS_F64 or UGKS_F32 storage of f */
+    int fstore;         /* UGKS_F64, UGKS_F32 or UGKS_BF16 storage of f */
     int n_bc;
     const double *bc_prim; /* [n_bc][dim+2]: (rho, U, T); walls use (U_w, T_w) */
 } ugks_gas_t;
@@ -160,6 +164,22 @@ int ugks_is_tensor_grid(const ugks_t *h);   /* 1 if the separable velocity path 
  * number of steps timed. */
 int ugks_profile(ugks_t *h, int enable);
 int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
+
+/* Surface quantities (Section 2.5).  ugks_n_wall_faces gives the number of
+ * faces of type UGKS_BC_WALL.  ugks_wall_flux writes out [n_wall][dim+2]:
+ * for every wall face, in increasing (caller's) face index, the macroscopic
+ * flux through the face during the last step, per unit area and per unit
+ * time -- mass (zero up to round-off: rho_w is chosen so), momentum F_m
+ * [dim], energy -- the moments (1, u, (|u|^2 h + b)/2) of u_n times the time
+ * integral of the wall distribution (outgoing: the limited reconstruction
+ * of the interior f transported freely; incoming: the wall Maxwellian of
+ * density rho_w).  n is the face normal (out of the gas, into the wall):
+ * surface pressure p_w = F_m . n, shear stress |F_m - p_w n|, heat flux =
+ * the energy component.  Recomputed from the f that started the last step
+ * (kept in the second f buffer); UGKS_ERR_STATE if no step ran since
+ * creation or ugks_set_f, or while asynchronous steps are outstanding. */
+int ugks_n_wall_faces(const ugks_t *h);
+int ugks_wall_flux(ugks_t *h, double *out);
 
 /* The library stores velocities in its own order (by direction, so that the
  * lanes of a wavefront agree on upwind sides).  perm_out [n_vel] receives,

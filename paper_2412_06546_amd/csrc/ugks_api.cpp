@@ -25,6 +25,13 @@ struct ugks {
     double *u = nullptr, *w = nullptr, *bcp = nullptr, *W = nullptr, *q = nullptr, *gW = nullptr, *dW2 = nullptr;
     double *cell_dt = nullptr, *res = nullptr, *u1d = nullptr;
     int *err = nullptr, *kidx = nullptr;
+    // surface quantities: stored indices of the wall faces (in the caller's
+    // face order), their flux in the last step, and whether a step has run
+    // since creation or set_f (f[1 - cur] then holds the f that started it)
+    int n_wallf = 0;
+    int *wallf = nullptr;
+    double *wallF = nullptr;
+    int stepped = 0;
     double dt = 0.0;
     long nstep = 0;
     int tensor = 0;
@@ -53,6 +60,31 @@ struct Fail {
     int code;
     std::string msg;
 };
+
+// bfloat16 storage on the host side (same rounding as the device: nearest,
+// ties to even, straight from FP64; below the FP32 normal range -> zero)
+uint16_t bf16_of(double x)
+{
+    if (x != x) return 0x7fc0;
+    uint64_t u;
+    std::memcpy(&u, &x, 8);
+    u += 0x00000fffffffffffull + ((u >> 45) & 1ull);
+    u &= ~0x00001fffffffffffull;
+    double r;
+    std::memcpy(&r, &u, 8);
+    float f = std::fabs(r) < 1.1754943508222875e-38 ? std::copysign(0.0f, (float)r) : (float)r;
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    return (uint16_t)(b >> 16);
+}
+double double_of_bf16(uint16_t v)
+{
+    const uint32_t b = (uint32_t)v << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+size_t fvalue_bytes(int fstore) { return fstore == UGKS_BF16 ? 2 : (fstore == UGKS_F32 ? 4 : 8); }
 
 template <typename T> T *dev_alloc(ugks_t *h, size_t n)
 {
@@ -386,7 +418,7 @@ template <int D> void create_d(ugks_t *h, const StoredMesh &S, const ugks_gas_t 
 // Device bytes a handle owns once created (the same sizes ugks_create
 // allocates; the temporary initial-state buffer is not counted).
 template <typename T> size_t nbytes(size_t n) { return sizeof(T) * (n ? n : 1); }
-size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab)
+size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab, size_t nwallf)
 {
     const size_t NW = D + 2, ncomp = D == 2 ? 2 : 1;
     size_t b = D == 2 ? nbytes<CellGeo<2>>(nc) + nbytes<FaceGeo<2>>(nf) + nbytes<FaceEq<2>>(nf)
@@ -395,7 +427,8 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
     b += nbytes<double>(nc * NW) + nbytes<double>(nc * D) + nbytes<double>(nc * NW * D) + nbytes<double>(nc * NW);
     b += nbytes<double>(nc) + nbytes<double>(NW) + nbytes<int>(2);
     if (ntab) b += nbytes<double>(ntab) + nbytes<int>(nv);
-    b += 2 * nc * ncomp * nv * (fstore ? sizeof(float) : sizeof(double));
+    b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
+    b += nbytes<int>(nwallf) + nbytes<double>(nwallf * NW);
     return b;
 }
 
@@ -420,7 +453,7 @@ void release(ugks_t *h)
     if (h->h_res) (void)hipHostFree(h->h_res);
     if (h->done_ev) (void)hipEventDestroy(h->done_ev);
     void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
-                    h->cell_dt, h->res, h->err, h->u1d, h->kidx};
+                    h->cell_dt, h->res, h->err, h->u1d, h->kidx, h->wallf, h->wallF};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -451,7 +484,8 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (!mesh->cell_volume || !mesh->cell_centroid || !mesh->face_cells || !mesh->face_normal || !mesh->face_area ||
             !mesh->face_centroid || !vgrid->u || !vgrid->w)
             throw Fail{UGKS_ERR_ARG, "NULL mesh or velocity array"};
-        if (gas->fstore != UGKS_F64 && gas->fstore != UGKS_F32) throw Fail{UGKS_ERR_ARG, "fstore must be UGKS_F64 or UGKS_F32"};
+        if (gas->fstore != UGKS_F64 && gas->fstore != UGKS_F32 && gas->fstore != UGKS_BF16)
+            throw Fail{UGKS_ERR_ARG, "fstore must be UGKS_F64, UGKS_F32 or UGKS_BF16"};
         if (!(gas->Pr > 0.0) || !(gas->mu_ref > 0.0) || !(gas->cfl > 0.0) || gas->limiter_k < 0.0)
             throw Fail{UGKS_ERR_ARG, "Pr, mu_ref and cfl must be positive, limiter_k non-negative"};
         if (gas->n_bc < 0 || (gas->n_bc > 0 && !gas->bc_prim)) throw Fail{UGKS_ERR_ARG, "bc_prim missing"};
@@ -503,6 +537,18 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         h->cell_dt = dev_alloc<double>(h, nc);
         h->res = dev_alloc<double>(h, D + 2);
         h->err = dev_alloc<int>(h, 2);
+        {
+            std::vector<std::pair<int, int>> wf;  // (caller's face, stored face)
+            for (int f = 0; f < h->nf; ++f)
+                if (S.bc[f] == UGKS_BC_WALL) wf.push_back({S.face_of[f], f});
+            std::sort(wf.begin(), wf.end());
+            std::vector<int> list;
+            for (auto &x : wf) list.push_back(x.second);
+            h->n_wallf = (int)list.size();
+            h->wallf = dev_alloc<int>(h, list.size());
+            h->wallF = dev_alloc<double>(h, list.size() * (D + 2));
+            if (!list.empty()) upload(h->wallf, list.data(), sizeof(int) * list.size(), h->stream);
+        }
         if (h->tensor) {
             h->u1d = dev_alloc<double>(h, axes.size());
             h->kidx = dev_alloc<int>(h, kidx.size());
@@ -510,7 +556,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             upload(h->kidx, kidx.data(), sizeof(int) * kidx.size(), h->stream);
         }
         double *prim_d = dev_alloc<double>(h, nc * (D + 2));
-        const size_t fbytes = nc * h->ncomp * nv * (h->fstore ? sizeof(float) : sizeof(double));
+        const size_t fbytes = nc * h->ncomp * nv * fvalue_bytes(h->fstore);
         for (int b = 0; b < 2; ++b) {
             hip_check(hipMalloc(&h->f[b], fbytes), "hipMalloc of f");
             h->bytes += fbytes;
@@ -595,6 +641,7 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
             if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s + 2], h->stream), "hipEventRecord");
             h->cur ^= 1;
             h->nstep++;
+            h->stepped = 1;
         }
         int err[2];
         hip_check(hipMemcpyAsync(err, h->err, sizeof(err), hipMemcpyDeviceToHost, h->stream), "copy error flag");
@@ -637,6 +684,7 @@ extern "C" int ugks_step_async(ugks_t *h, int nsteps)
             hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
             h->cur ^= 1;
             h->nstep++;
+            h->stepped = 1;
         }
         hip_check(launch_residual(h->P, h->res, h->stream), "residual launch");
         hip_check(hipMemcpyAsync(h->h_err, h->err, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy flag");
@@ -683,7 +731,10 @@ extern "C" size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vg
     if (detect_tensor(mesh->dim, vgrid->n_vel, vgrid->u, n1d, axes, kidx) &&
         (size_t)(Dim<3>::MF + 1) * axes.size() * sizeof(double) <= 48 * 1024)
         ntab = axes.size();
-    return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab);
+    size_t nwallf = 0;
+    if (mesh->face_bc)
+        for (int f = 0; f < mesh->n_faces; ++f) nwallf += mesh->face_bc[f] == UGKS_BC_WALL;
+    return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab, nwallf);
 }
 
 extern "C" int ugks_macros(ugks_t *h, double *W_out, double *q_out)
@@ -715,11 +766,16 @@ extern "C" int ugks_get_f(ugks_t *h, double *f_out)
         if (h->fstore == UGKS_F64) {
             hip_check(hipMemcpyAsync(tmp.data(), h->f[h->cur], sizeof(double) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        } else {
+        } else if (h->fstore == UGKS_F32) {
             std::vector<float> t32(n);
             hip_check(hipMemcpyAsync(t32.data(), h->f[h->cur], sizeof(float) * n, hipMemcpyDeviceToHost, h->stream), "copy f");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
             for (size_t i = 0; i < n; ++i) tmp[i] = t32[i];
+        } else {
+            std::vector<uint16_t> t16(n);
+            hip_check(hipMemcpyAsync(t16.data(), h->f[h->cur], 2 * n, hipMemcpyDeviceToHost, h->stream), "copy f");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+            for (size_t i = 0; i < n; ++i) tmp[i] = double_of_bf16(t16[i]);
         }
         const size_t nk = h->ncomp;
         for (size_t r = 0; r < rows; ++r) {
@@ -735,6 +791,8 @@ extern "C" int ugks_get_f(ugks_t *h, double *f_out)
 extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
 {
     if (!h || !f_in) return UGKS_ERR_ARG;
+    if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
+    h->stepped = 0;
     try {
         const size_t nv = h->nv, rows = (size_t)h->nc * h->ncomp, n = rows * nv;
         std::vector<double> tmp(n);
@@ -747,11 +805,37 @@ extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
             upload(h->f[h->cur], tmp.data(), sizeof(double) * n, h->stream);
             hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        } else {
+        } else if (h->fstore == UGKS_F32) {
             std::vector<float> t32(n);
             for (size_t i = 0; i < n; ++i) t32[i] = (float)tmp[i];
             upload(h->f[h->cur], t32.data(), sizeof(float) * n, h->stream);
             hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        } else {
+            std::vector<uint16_t> t16(n);
+            for (size_t i = 0; i < n; ++i) t16[i] = bf16_of(tmp[i]);
+            upload(h->f[h->cur], t16.data(), 2 * n, h->stream);
+            hip_check(launch_moments(h->P, h->f[h->cur], h->stream), "k_moments launch");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        }
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_n_wall_faces(const ugks_t *h) { return h ? h->n_wallf : 0; }
+
+extern "C" int ugks_wall_flux(ugks_t *h, double *out)
+{
+    if (!h || !out) return UGKS_ERR_ARG;
+    if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
+    if (!h->stepped) return fail(h, Fail{UGKS_ERR_STATE, "no step since creation or ugks_set_f"});
+    try {
+        if (h->n_wallf) {
+            hip_check(launch_wall_flux(h->P, h->f[1 - h->cur], h->wallf, h->n_wallf, h->wallF, h->stream), "wall flux launch");
+            hip_check(hipMemcpyAsync(out, h->wallF, sizeof(double) * h->n_wallf * (h->dim + 2), hipMemcpyDeviceToHost,
+                                     h->stream), "copy wall flux");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         }
     } catch (const Fail &e) {

@@ -90,5 +90,7 @@ hipError_t launch_moments(const Params &p, const void *f, hipStream_t s);
 hipError_t launch_prologue(const Params &p, hipStream_t s);  // k_cell_grad + k_face_eq
 hipError_t launch_sweep(const Params &p, const void *f_in, void *f_out, hipStream_t s);
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s);
+// macroscopic flux [n][dim+2] through the wall faces faces[0..n) in the step that started from f
+hipError_t launch_wall_flux(const Params &p, const void *f, const int *faces, int n, double *out, hipStream_t s);
 
 }  // namespace ugx

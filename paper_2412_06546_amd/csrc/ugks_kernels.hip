@@ -32,6 +32,34 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int N_DOF = 3;  // translational + internal degrees of freedom (monatomic)
 
 // ------------------------------------------------------------------------
+// storage types of f: FP64, FP32 or bfloat16 (all arithmetic is FP64)
+// ------------------------------------------------------------------------
+struct bf16s {
+    unsigned short bits;
+};
+__device__ __forceinline__ double to_f64(double x) { return x; }
+__device__ __forceinline__ double to_f64(float x) { return (double)x; }
+__device__ __forceinline__ double to_f64(bf16s x) { return (double)__uint_as_float((unsigned)x.bits << 16); }
+
+template <typename FT> __device__ __forceinline__ FT from_f64(double x);
+template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_f64<float>(double x) { return (float)x; }
+// Round to nearest, ties to even, directly from FP64 to the 8 significant
+// bits of bfloat16: round the FP64 significand at its bit 45, then the
+// result is exact in FP32 and its upper half is the bfloat16 pattern
+// (values below the FP32 normal range are flushed to signed zero).
+template <> __device__ __forceinline__ bf16s from_f64<bf16s>(double x)
+{
+    if (x != x) return bf16s{0x7fc0};
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    u += 0x00000fffffffffffull + ((u >> 45) & 1ull);
+    u &= ~0x00001fffffffffffull;
+    const double r = __longlong_as_double((long long)u);
+    const float f = fabs(r) < 1.1754943508222875e-38 ? copysignf(0.0f, (float)r) : (float)r;
+    return bf16s{(unsigned short)(__float_as_uint(f) >> 16)};
+}
+
+// ------------------------------------------------------------------------
 // small helpers
 // ------------------------------------------------------------------------
 template <int D> __device__ __forceinline__ double pow_lam_pi(double lam)
@@ -142,7 +170,7 @@ __device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const 
     const FT *fcell = f + (size_t)c * NC * nv;  // wave-uniform base of the cell's slab
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-        fc[m] = static_cast<double>(fcell[m * nv + k]);
+        fc[m] = to_f64(fcell[m * nv + k]);
         fmx[m] = fmn[m] = fc[m];
 #pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
@@ -156,7 +184,7 @@ __device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const 
         const FT *fnb = f + (size_t)n * NC * nv;
 #pragma unroll
         for (int m = 0; m < NC; ++m) {
-            const double fj = static_cast<double>(fnb[m * nv + k]);
+            const double fj = to_f64(fnb[m * nv + k]);
             const double df = fj - fc[m];
 #pragma unroll
             for (int d = 0; d < D; ++d) gr[m][d] = fma(g.lsq[j][d], df, gr[m][d]);
@@ -302,8 +330,8 @@ __global__ __launch_bounds__(256) void k_init(Params p, const double *__restrict
     const double lam = 1.0 / pr[D + 1];
     double H, B;
     equilibrium<D>(u, U, lam, pr[0] * pow_lam_pi<D>(lam), 0.0, zq, H, B);
-    f[((size_t)i * NC + 0) * p.nv + k] = static_cast<FT>(H);
-    if constexpr (NC > 1) f[((size_t)i * NC + 1) * p.nv + k] = static_cast<FT>(B);
+    f[((size_t)i * NC + 0) * p.nv + k] = from_f64<FT>(H);
+    if constexpr (NC > 1) f[((size_t)i * NC + 1) * p.nv + k] = from_f64<FT>(B);
 }
 
 // ------------------------------------------------------------------------
@@ -319,8 +347,8 @@ __global__ __launch_bounds__(256) void k_moments(Params p, const FT *__restrict_
 #pragma unroll
     for (int n = 0; n < NW; ++n) m[n] = 0.0;
     for (int k = threadIdx.x; k < p.nv; k += 256) {
-        double h = static_cast<double>(f[((size_t)i * NC) * p.nv + k]);
-        double b = NC > 1 ? static_cast<double>(f[((size_t)i * NC + NC - 1) * p.nv + k]) : 0.0;
+        double h = to_f64(f[((size_t)i * NC) * p.nv + k]);
+        double b = NC > 1 ? to_f64(f[((size_t)i * NC + NC - 1) * p.nv + k]) : 0.0;
         double w = p.w[k], u2 = 0.0;
         m[0] += w * h;
 #pragma unroll
@@ -337,8 +365,8 @@ __global__ __launch_bounds__(256) void k_moments(Params p, const FT *__restrict_
 #pragma unroll
     for (int d = 0; d < D; ++d) qq[d] = 0.0;
     for (int k = threadIdx.x; k < p.nv; k += 256) {
-        double h = static_cast<double>(f[((size_t)i * NC) * p.nv + k]);
-        double b = NC > 1 ? static_cast<double>(f[((size_t)i * NC + NC - 1) * p.nv + k]) : 0.0;
+        double h = to_f64(f[((size_t)i * NC) * p.nv + k]);
+        double b = NC > 1 ? to_f64(f[((size_t)i * NC + NC - 1) * p.nv + k]) : 0.0;
         double c[D], c2 = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -856,7 +884,7 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             fout[base + (size_t)c * nv + k] =
-                static_cast<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
+                from_f64<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
         // moments of the net outflow (Eq. macroscopicFlux summed over faces)
         const double wk = p.w[k];
         mom[0] += wk * out[0];
@@ -885,8 +913,8 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             c[d] = p.u[d * nv + k] - p1.U[d];
             c2 += c[d] * c[d];
         }
-        const double h = static_cast<double>(fout[base + k]);
-        const double b = NC > 1 ? static_cast<double>(fout[base + (size_t)(NC - 1) * nv + k]) : 0.0;
+        const double h = to_f64(fout[base + k]);
+        const double b = NC > 1 ? to_f64(fout[base + (size_t)(NC - 1) * nv + k]) : 0.0;
         const double wt = 0.5 * p.w[k] * (c2 * h + b);
 #pragma unroll
         for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
@@ -925,7 +953,7 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const size_t o = base + (size_t)c * nv + k;
-            fout[o] = static_cast<FT>((static_cast<double>(fout[o]) + a1 * fp[c]) * inv1);
+            fout[o] = from_f64<FT>((to_f64(fout[o]) + a1 * fp[c]) * inv1);
         }
     }
     if (tid == 0) {
@@ -943,6 +971,89 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             atomicOr(p.err, 1);
             atomicMin(p.err + 1, i);
         }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Surface quantities (Section 2.5): the macroscopic flux through each wall
+// face in a step, from the f that started the step.  One workgroup per wall
+// face: particles leaving the gas carry the limited reconstruction of f
+// (free transport over the step), particles leaving the wall the wall
+// Maxwellian of density rho_w; both sums are kept apart, rho_w follows from
+// zero net mass flux, and F = (out + rho_w * in) / dt per unit area.
+// ------------------------------------------------------------------------
+template <int D, typename FT, int BS>
+__global__ __launch_bounds__(BS) void k_wall_flux(Params p, const FT *__restrict__ fin,
+                                                  const int *__restrict__ wall_faces, double *__restrict__ out)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2;
+    __shared__ double red[(BS / 64) * 2 * NW];
+    const int f = wall_faces[blockIdx.x];
+    const FaceGeo<D> &F = static_cast<const FaceGeo<D> *>(p.fgeo)[f];
+    const FaceEq<D> &e = static_cast<const FaceEq<D> *>(p.feq)[f];
+    const int i = F.l;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    int j = 0;
+    for (int t = 0; t < gi.nf; ++t)
+        if (gi.face[t] == f) j = t;
+    const int nv = p.nv;
+    const double dt = p.dt;
+    double acc[2 * NW];
+#pragma unroll
+    for (int m = 0; m < 2 * NW; ++m) acc[m] = 0.0;
+    for (int k = threadIdx.x; k < nv; k += BS) {
+        double u[D], u2 = 0.0, un = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 += u[d] * u[d];
+            un += u[d] * F.n[d];
+        }
+        const double wk = p.w[k];
+        double I[2] = {0.0, 0.0};
+        int off = 0;
+        if (un > 0.0) {
+            double fi[NC], gri[NC][D];
+            limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double v = fi[c], ug = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    v += gri[c][d] * gi.dvec[j][d];
+                    ug += u[d] * gri[c][d];
+                }
+                I[c] = dt * v - 0.5 * dt * dt * ug;
+            }
+        } else {
+            double c2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const double cd = u[d] - e.U[d];
+                c2 += cd * cd;
+            }
+            const double H = e.pref * exp(-e.lam * c2);
+            I[0] = dt * H;
+            I[1] = NC > 1 ? dt * e.bh * H : 0.0;
+            off = NW;
+        }
+        const double a = wk * un;
+        double mom[NW];
+        mom[0] = a * I[0];
+#pragma unroll
+        for (int d = 0; d < D; ++d) mom[1 + d] = a * u[d] * I[0];
+        mom[NW - 1] = a * 0.5 * (u2 * I[0] + I[1]);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            acc[m] += off ? 0.0 : mom[m];
+            acc[NW + m] += off ? mom[m] : 0.0;
+        }
+    }
+    block_reduce<BS>(acc, red, OpAdd{});
+    if (threadIdx.x == 0) {
+        const double rho_w = acc[NW] != 0.0 ? -acc[0] / acc[NW] : 0.0;
+#pragma unroll
+        for (int m = 0; m < NW; ++m) out[(size_t)blockIdx.x * NW + m] = (acc[m] + rho_w * acc[NW + m]) / dt;
     }
 }
 
@@ -985,8 +1096,11 @@ template <int D, typename FT> hipError_t init_d(const Params &p, const double *p
 }
 hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_t s)
 {
-    if (p.dim == 2) return p.fstore ? init_d<2, float>(p, prim0, f, s) : init_d<2, double>(p, prim0, f, s);
-    return p.fstore ? init_d<3, float>(p, prim0, f, s) : init_d<3, double>(p, prim0, f, s);
+    if (p.dim == 2)
+        return p.fstore == 2 ? init_d<2, bf16s>(p, prim0, f, s)
+                             : (p.fstore ? init_d<2, float>(p, prim0, f, s) : init_d<2, double>(p, prim0, f, s));
+    return p.fstore == 2 ? init_d<3, bf16s>(p, prim0, f, s)
+                         : (p.fstore ? init_d<3, float>(p, prim0, f, s) : init_d<3, double>(p, prim0, f, s));
 }
 
 template <int D, typename FT> hipError_t moments_d(const Params &p, const void *f, hipStream_t s)
@@ -996,8 +1110,11 @@ template <int D, typename FT> hipError_t moments_d(const Params &p, const void *
 }
 hipError_t launch_moments(const Params &p, const void *f, hipStream_t s)
 {
-    if (p.dim == 2) return p.fstore ? moments_d<2, float>(p, f, s) : moments_d<2, double>(p, f, s);
-    return p.fstore ? moments_d<3, float>(p, f, s) : moments_d<3, double>(p, f, s);
+    if (p.dim == 2)
+        return p.fstore == 2 ? moments_d<2, bf16s>(p, f, s)
+                             : (p.fstore ? moments_d<2, float>(p, f, s) : moments_d<2, double>(p, f, s));
+    return p.fstore == 2 ? moments_d<3, bf16s>(p, f, s)
+                         : (p.fstore ? moments_d<3, float>(p, f, s) : moments_d<3, double>(p, f, s));
 }
 
 template <int D> hipError_t prologue_d(const Params &p, hipStream_t s)
@@ -1031,8 +1148,29 @@ template <int D, typename FT> hipError_t sweep_d(const Params &p, const void *fi
 }
 hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s)
 {
-    if (p.dim == 2) return p.fstore ? sweep_d<2, float>(p, fi, fo, s) : sweep_d<2, double>(p, fi, fo, s);
-    return p.fstore ? sweep_d<3, float>(p, fi, fo, s) : sweep_d<3, double>(p, fi, fo, s);
+    if (p.dim == 2)
+        return p.fstore == 2 ? sweep_d<2, bf16s>(p, fi, fo, s)
+                             : (p.fstore ? sweep_d<2, float>(p, fi, fo, s) : sweep_d<2, double>(p, fi, fo, s));
+    return p.fstore == 2 ? sweep_d<3, bf16s>(p, fi, fo, s)
+                         : (p.fstore ? sweep_d<3, float>(p, fi, fo, s) : sweep_d<3, double>(p, fi, fo, s));
+}
+
+template <int D, typename FT>
+hipError_t wall_flux_d(const Params &p, const void *f, const int *faces, int n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_wall_flux<D, FT, 256>), dim3(n), dim3(256), 0, s, p, static_cast<const FT *>(f), faces, out);
+    return hipGetLastError();
+}
+hipError_t launch_wall_flux(const Params &p, const void *f, const int *faces, int n, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (p.dim == 2)
+        return p.fstore == 2 ? wall_flux_d<2, bf16s>(p, f, faces, n, out, s)
+                             : (p.fstore ? wall_flux_d<2, float>(p, f, faces, n, out, s)
+                                         : wall_flux_d<2, double>(p, f, faces, n, out, s));
+    return p.fstore == 2 ? wall_flux_d<3, bf16s>(p, f, faces, n, out, s)
+                         : (p.fstore ? wall_flux_d<3, float>(p, f, faces, n, out, s)
+                                     : wall_flux_d<3, double>(p, f, faces, n, out, s));
 }
 
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s)

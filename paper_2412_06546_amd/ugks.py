@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libugks.so")
 
 UGKS_OK, UGKS_ERR_ARG, UGKS_ERR_ALLOC, UGKS_ERR_HIP, UGKS_ERR_NONPHYSICAL, UGKS_ERR_STATE = 0, -1, -2, -3, -4, -5
-UGKS_F64, UGKS_F32 = 0, 1
+UGKS_F64, UGKS_F32, UGKS_BF16 = 0, 1, 2
+UGKS_BC_WALL = 3
+_FSTORE = {"f64": UGKS_F64, "f32": UGKS_F32, "bf16": UGKS_BF16}
 _ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
              -5: "UGKS_ERR_STATE"}
 
@@ -91,6 +93,10 @@ def load_library(path: str = LIB_PATH):
     L.ugks_profile_read.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_long)]
     L.ugks_velocity_order.restype = C.c_int
     L.ugks_velocity_order.argtypes = [C.c_void_p, _ip]
+    L.ugks_n_wall_faces.restype = C.c_int
+    L.ugks_n_wall_faces.argtypes = [C.c_void_p]
+    L.ugks_wall_flux.restype = C.c_int
+    L.ugks_wall_flux.argtypes = [C.c_void_p, _dp]
     L.ugks_cell_order.restype = C.c_int
     L.ugks_cell_order.argtypes = [C.c_void_p, _ip]
     L.ugks_device_f.restype = C.c_void_p
@@ -142,7 +148,7 @@ def _structs(case, fstore, keep):
     vgrid = ugks_vgrid_t(dim, len(vg["w"]), d(vg["u"]), d(vg["w"]))
     bc = np.asarray(gas["bc_prim"], dtype=np.float64)
     g = ugks_gas_t(gas["Pr"], gas["omega"], gas["mu_ref"], gas["cfl"], gas["dt_override"], gas["limiter_k"],
-                   int(gas["limiter"]), UGKS_F32 if fstore == "f32" else UGKS_F64, bc.shape[0], d(bc))
+                   int(gas["limiter"]), _FSTORE[fstore], bc.shape[0], d(bc))
     return mesh, vgrid, g, d(case["prim0"])
 
 
@@ -172,6 +178,8 @@ class Solver:
         _check(L, None, code)
         self._h = h
         self.ncomp = L.ugks_n_comp(h)
+        m = case["mesh"]
+        self.wall_normals = np.asarray(m["face_normal"])[np.asarray(m["face_bc"]) == UGKS_BC_WALL].copy()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -233,6 +241,28 @@ class Solver:
         perm = np.zeros(self.nv, dtype=np.int32)
         _check(self._L, self._h, self._L.ugks_velocity_order(self._h, perm.ctypes.data_as(_ip)))
         return perm
+
+    def wall_flux(self):
+        """Macroscopic flux through every wall face in the last step, per unit
+        area and time: [n_wall][dim + 2] (mass, momentum, energy)."""
+        n = self._L.ugks_n_wall_faces(self._h)
+        F = np.zeros((n, self.dim + 2))
+        _check(self._L, self._h, self._L.ugks_wall_flux(self._h, F.ctypes.data_as(_dp)))
+        return F
+
+    def surface(self, rho_inf: float, u_inf: float):
+        """Surface pressure, shear stress and heat flux of every wall face in
+        the last step, and the coefficients Cp, Ct, Ch (Section 4.1): the
+        first two divided by rho_inf u_inf^2 / 2, the heat flux by
+        rho_inf u_inf^3 / 2."""
+        F = self.wall_flux()
+        n = self.wall_normals
+        Fm = F[:, 1:1 + self.dim]
+        p = (Fm * n).sum(1)
+        sigma = np.linalg.norm(Fm - p[:, None] * n, axis=1)
+        qw = F[:, -1]
+        d = 0.5 * rho_inf * u_inf ** 2
+        return {"p": p, "sigma": sigma, "q": qw, "Cp": p / d, "Ct": sigma / d, "Ch": qw / (d * u_inf)}
 
     def cell_order(self):
         """Stored cell position -> caller's cell index."""

@@ -207,6 +207,77 @@ def test_fp32_storage_error_is_small():
     assert err <= 1e-5
 
 
+def _prim(W):
+    """(rho, U, T) of conservative W (R = 1/2, three degrees of freedom)."""
+    D = W.shape[1] - 2
+    rho = W[:, 0]
+    U = W[:, 1:1 + D] / rho[:, None]
+    T = (4.0 / 3.0) * (W[:, -1] / rho - 0.5 * (U ** 2).sum(1))
+    return rho, U, T
+
+
+def prim_errors(Wg, Wo):
+    """Relative errors of rho, U (scaled by max(|U|, sqrt(2 R T))) and T."""
+    rg, Ug, Tg = _prim(Wg)
+    ro, Uo, To = _prim(Wo)
+    su = max(np.abs(Uo).max(), np.sqrt(To.max()))
+    return {"rho": np.abs(rg - ro).max() / ro.max(), "U": np.abs(Ug - Uo).max() / su,
+            "T": np.abs(Tg - To).max() / To.max()}
+
+
+def _bf16_rne(x):
+    """bfloat16 rounding (nearest, ties to even) of float64 values, done on
+    the float64 bit pattern with numpy integers; values below the FP32
+    normal range become zero."""
+    x = np.asarray(x, dtype=np.float64)
+    u = x.view(np.uint64).copy()
+    u += np.uint64(0x00000FFFFFFFFFFF) + ((u >> np.uint64(45)) & np.uint64(1))
+    u &= ~np.uint64(0x00001FFFFFFFFFFF)
+    r = u.view(np.float64)
+    return np.where(np.abs(r) < np.finfo(np.float32).tiny, 0.0 * r, r)
+
+
+def test_bf16_storage_rounds_to_nearest_even():
+    """set_f / get_f through bfloat16 storage: exactly representable values
+    survive, ties go to the even significand, everything else to the
+    nearest bfloat16."""
+    ugks = _gpu()
+    c = cases.case_periodic_wave(nx=6, ny=4, nv=10)
+    s = ugks.Solver(c, fstore="bf16")
+    f = s.f()
+    rng = np.random.default_rng(11)
+    vals = rng.uniform(0.0, 2.0, f.size) * 10.0 ** rng.integers(-30, 3, f.size)
+    special = [1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -7, 0.5 + 2.0 ** -10, 1e-40, 3.0]
+    expect = [1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, 0.5, 0.0, 3.0]
+    vals[:len(special)] = special
+    s.set_f(vals.reshape(f.shape))
+    got = s.f().reshape(-1)
+    np.testing.assert_array_equal(got[:len(special)], expect)
+    np.testing.assert_array_equal(got, _bf16_rne(vals))
+
+
+@pytest.mark.parametrize("fstore,tol", [("f32", 1e-5), ("bf16", 5e-2)])
+def test_storage_precision_error_per_quantity(fstore, tol):
+    """Reduced-precision storage of f (all arithmetic FP64) against the FP64
+    oracle after 20 steps of the cut-down cylinder: errors in rho, U, T and
+    the last step's residual are printed; the bound is the FP32 target for
+    f32 and a sanity bound for bf16 (whose error is reported, not targeted)."""
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    _say(f"case {c['name']}: {fstore} f storage, 20 steps")
+    s, o = ugks.Solver(c, fstore=fstore), oracle.Oracle(c)
+    s.step(19)
+    o.step(19)
+    rg = s.step(1, residual=True)
+    o.step(1)
+    Wg, _ = s.macros()
+    Wo, _ = o.macros()
+    e = prim_errors(Wg, Wo)
+    _say(f"    {fstore}-f relative errors: rho {e['rho']:.3e}  U {e['U']:.3e}  T {e['T']:.3e}; "
+         f"residual {np.array2string(rg, precision=3)}")
+    assert max(e.values()) <= tol
+
+
 def test_impulsive_start_cylinder_fp64():
     """Free-stream start: the leeward first-layer cells empty fast; 10 steps
     of that transient against the oracle."""
@@ -269,6 +340,41 @@ def test_caller_numbering_is_free():
     o = oracle.Oracle(shuf)
     o.step(10)
     _compare(b, o)
+
+
+def _wall_flux_err(Fg, Fo):
+    """Largest difference per component, relative to that component's
+    largest magnitude (at least 1e-3 of the largest flux of any component;
+    the mass flux is round-off and is held to the global scale)."""
+    top = np.abs(Fo).max()
+    scale = np.maximum(np.abs(Fo).max(axis=0), 1e-3 * top)
+    scale[0] = top
+    return (np.abs(Fg - Fo).max(axis=0) / scale).max()
+
+
+@pytest.mark.parametrize("which", ["cylinder", "channel3d"])
+def test_wall_flux_matches_oracle(which):
+    """Surface quantities (Section 2.5): the macroscopic flux through every
+    wall face in the last step, per unit area and time, against the oracle;
+    the 3D channel has a sliding (moving) wall, so shear is non-zero."""
+    ugks = _gpu()
+    c = cases.case_cylinder_small() if which == "cylinder" else cases.case_channel_3d(kind="hex")
+    steps = 10 if which == "cylinder" else 5
+    _say(f"case {c['name']}: wall flux after {steps} steps, fp64")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    with pytest.raises(ugks.UgksError) as e:
+        s.wall_flux()
+    assert e.value.code == ugks.UGKS_ERR_STATE
+    s.step(steps)
+    o.step(steps)
+    Fg, Fo = s.wall_flux(), o.wall_flux()
+    assert Fg.shape == Fo.shape and len(Fg) > 0
+    err = _wall_flux_err(Fg, Fo)
+    sf = s.surface(1.0, 1.0)
+    _say(f"    wall flux rel err {err:.2e}; max shear {sf['sigma'].max():.3e}, max |heat flux| {np.abs(sf['q']).max():.3e}")
+    assert err <= 1e-12
+    if which == "channel3d":
+        assert sf["sigma"].max() > 1e-3
 
 
 def test_full_size_cylinder_fp64():

@@ -38,7 +38,7 @@ def test_footprint_estimate_matches_allocation():
     c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(c["vgrid"]["u"][keep]), w=np.ascontiguousarray(c["vgrid"]["w"][keep]))
     cs.append(c)
     for c in cs:
-        for fs in ("f64", "f32"):
+        for fs in ("f64", "f32", "bf16"):
             est = ugks.footprint_estimate(c, fs)
             s = ugks.Solver(c, fstore=fs)
             assert s.footprint_bytes == est, (c.get("name"), fs)
