@@ -673,13 +673,18 @@ template <int D, bool TENSOR> struct Gauss {
 //   heat:   each thread re-reads its stage-1 values -> q^{n+1};
 //   pass 2: each thread re-reads its stage-1 values, applies stage 2 and
 //           writes f^{n+1}.
+// Pass 1 parks the stage-1 values in LDS when the cell's slab fits there
+// beside the tables with four workgroups per CU (then f_out is written once),
+// otherwise in f_out itself.
 #ifndef UGKS_XCDS
 #define UGKS_XCDS 8  // accelerator complex dies of an MI355X
 #endif
 #ifndef UGKS_XCD_RUN
 #define UGKS_XCD_RUN 32
 #endif
-template <int D, typename FT, int BS, bool TENSOR>
+// S1L: the stage-1 values of the cell are kept in LDS (when the slab fits
+// beside the tables without costing occupancy), else in f_out until stage 2.
+template <int D, typename FT, int BS, bool TENSOR, bool S1L>
 __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
@@ -703,6 +708,8 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
     double *red = smem + NT * ntab;
     const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
     const size_t base = (size_t)i * NC * nv;
+    constexpr int NRED = (NW > 2 * MF) ? NW : 2 * MF;
+    FT *s1 = S1L ? reinterpret_cast<FT *>(red + (BS / 64) * NRED) : fout + base;
 
     // state at t^n
     double Wn[NW];
@@ -883,8 +890,7 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            fout[base + (size_t)c * nv + k] =
-                from_f64<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
+            s1[(size_t)c * nv + k] = from_f64<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
         // moments of the net outflow (Eq. macroscopicFlux summed over faces)
         const double wk = p.w[k];
         mom[0] += wk * out[0];
@@ -913,8 +919,8 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
             c[d] = p.u[d * nv + k] - p1.U[d];
             c2 += c[d] * c[d];
         }
-        const double h = to_f64(fout[base + k]);
-        const double b = NC > 1 ? to_f64(fout[base + (size_t)(NC - 1) * nv + k]) : 0.0;
+        const double h = to_f64(s1[k]);
+        const double b = NC > 1 ? to_f64(s1[(size_t)(NC - 1) * nv + k]) : 0.0;
         const double wt = 0.5 * p.w[k] * (c2 * h + b);
 #pragma unroll
         for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
@@ -952,8 +958,7 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
         shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const size_t o = base + (size_t)c * nv + k;
-            fout[o] = from_f64<FT>((to_f64(fout[o]) + a1 * fp[c]) * inv1);
+            fout[base + (size_t)c * nv + k] = from_f64<FT>((to_f64(s1[(size_t)c * nv + k]) + a1 * fp[c]) * inv1);
         }
     }
     if (tid == 0) {
@@ -1128,16 +1133,24 @@ hipError_t launch_prologue(const Params &p, hipStream_t s)
     return p.dim == 2 ? prologue_d<2>(p, s) : prologue_d<3>(p, s);
 }
 
+// LDS a workgroup may take while four of them still fit on a CU (160 KB)
+constexpr size_t kLdsPerWorkgroup = 40 * 1024;
+
 template <int D, typename FT, int BS, bool TENSOR>
 void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
 {
     constexpr int NW = D + 2, MF = Dim<D>::MF;
     constexpr int NRED = (NW > 2 * MF) ? NW : 2 * MF;
     const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (TENSOR ? p.ntab : 0) + (BS / 64) * NRED);
+    const size_t slab = sizeof(FT) * Dim<D>::NC * (size_t)p.nv;
     constexpr int span = UGKS_XCDS * UGKS_XCD_RUN;
     const unsigned grid = (unsigned)(((p.nc + span - 1) / span) * span);
-    hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR>), dim3(grid), dim3(BS), lds, s, p, static_cast<const FT *>(fi),
-                       static_cast<FT *>(fo));
+    if (lds + slab <= kLdsPerWorkgroup)
+        hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, true>), dim3(grid), dim3(BS), lds + slab, s, p,
+                           static_cast<const FT *>(fi), static_cast<FT *>(fo));
+    else
+        hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, false>), dim3(grid), dim3(BS), lds, s, p,
+                           static_cast<const FT *>(fi), static_cast<FT *>(fo));
 }
 
 template <int D, typename FT> hipError_t sweep_d(const Params &p, const void *fi, void *fo, hipStream_t s)
