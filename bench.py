@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fstore", choices=["f64", "f32", "bf16"], default="f64")
+    ap.add_argument("--workload", choices=["cylinder", "sphere"], default="cylinder",
+                    help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -169,7 +171,7 @@ def main():
         return
 
     from paper_2412_06546_amd import cases
-    case = cases.case_cylinder()
+    case = cases.case_cylinder() if args.workload == "cylinder" else cases.case_sphere()
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
     main_run = run_gpu(case, args.fstore, args.steps, args.warmup)
@@ -182,7 +184,7 @@ def main():
                           "sweep_ms": r2["sweep_ms_avg"], "achieved_gbs": r2["achieved_gbs"]})
             print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
-    traffic = measured_traffic(args.fstore)
+    traffic = measured_traffic(args.fstore) if args.workload == "cylinder" else None
     roofline = {"bound": "hbm", "achieved": round(main_run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(main_run["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
@@ -201,7 +203,9 @@ def main():
         "vs_baseline": None,
         "dtype": args.fstore,
         "data": "synthetic",
-        "config": {"workload": f"{case['name']}: 2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall",
+        "config": {"workload": f"{case['name']}: " + ("2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall"
+                                                        if args.workload == "cylinder" else
+                                                        "3D sphere Ma 4 Kn 0.05 Shakhov, isothermal wall"),
                    "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64",
                    "prologue_ms": round(main_run["prologue_ms_avg"], 4),
                    "footprint_bytes": main_run["footprint_bytes"]},

@@ -510,3 +510,151 @@ def case_channel_3d(n=3, kind="hex", nv=8, half_width=5.0, kn=0.1, Pr=2.0 / 3.0,
     prim0[:, 0] = 1.0 + 0.05 * np.sin(2 * math.pi * x[:, 0])
     prim0[:, 4] = 1.0
     return dict(name=f"channel3d_{kind}_{len(x)}_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+
+
+# --------------------------------------------------------------------------
+# large 3D meshes from connectivity arrays (vectorised)
+# --------------------------------------------------------------------------
+def mesh_from_tets(X, T, classify_boundary):
+    """Face data of a tetrahedral mesh given vertex coordinates X [nv][3] and
+    tetrahedra T [nc][4] (any orientation).  classify_boundary(xc, n) takes
+    arrays of boundary face centroids and outward normals and returns arrays
+    (bc, bc_id)."""
+    X = np.asarray(X, dtype=np.float64)
+    T = np.asarray(T, dtype=np.int64).copy()
+    P = X[T]
+    vol6 = np.einsum("ij,ij->i", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]))
+    neg = vol6 < 0
+    T[neg, 1], T[neg, 2] = T[neg, 2].copy(), T[neg, 1].copy()
+    P = X[T]
+    vol = np.abs(vol6) / 6.0
+    if (vol <= 0).any():
+        raise ValueError("degenerate tetrahedron")
+    cen = P.mean(axis=1)
+    nc = len(T)
+    # the four faces of a positively oriented tetrahedron, outward
+    loc = np.array([[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]])
+    F = T[:, loc].reshape(-1, 3)
+    owner = np.repeat(np.arange(nc), 4)
+    key = np.sort(F, axis=1)
+    order = np.lexsort((owner, key[:, 2], key[:, 1], key[:, 0]))
+    key, F, owner = key[order], F[order], owner[order]
+    first = np.ones(len(key), dtype=bool)
+    first[1:] = (key[1:] != key[:-1]).any(axis=1)
+    start = np.nonzero(first)[0]
+    count = np.diff(np.append(start, len(key)))
+    if (count > 2).any():
+        raise ValueError("face shared by more than two cells")
+    Ff = F[start]
+    l = owner[start]
+    r = np.where(count == 2, owner[np.minimum(start + 1, len(owner) - 1)], -1)
+    A = X[Ff]
+    av = 0.5 * np.cross(A[:, 1] - A[:, 0], A[:, 2] - A[:, 0])
+    area = np.linalg.norm(av, axis=1)
+    normal = av / area[:, None]
+    xc = A.mean(axis=1)
+    bc = np.zeros(len(Ff), dtype=np.int32)
+    bid = np.zeros(len(Ff), dtype=np.int32)
+    b = r < 0
+    if b.any():
+        cb, ib = classify_boundary(xc[b], normal[b])
+        bc[b], bid[b] = cb, ib
+    return dict(dim=3, cell_volume=vol, cell_centroid=cen,
+                face_cells=np.stack([l, r], 1).astype(np.int32), face_normal=normal, face_area=area,
+                face_centroid=xc, face_shift=np.zeros_like(xc), face_bc=bc, face_bc_id=bid)
+
+
+def prisms_to_tets(Pz):
+    """Split prisms [n][6] (bottom triangle 0,1,2; top 3,4,5 above them)
+    into three tetrahedra each, conformingly: every quadrilateral side is cut
+    along the diagonal through its lowest global vertex index (the rule of
+    Dompierre et al., which always admits a three-tetrahedron split)."""
+    Pz = np.asarray(Pz, dtype=np.int64)
+    p = np.argmin(Pz, axis=1)
+    q = p % 3
+    rot = np.stack([q, (q + 1) % 3, (q + 2) % 3], 1)
+    top = (p >= 3)[:, None]
+    perm = np.where(top, np.concatenate([rot + 3, rot], 1), np.concatenate([rot, rot + 3], 1))
+    I = np.take_along_axis(Pz, perm, axis=1)
+    a = np.minimum(I[:, 1], I[:, 5]) < np.minimum(I[:, 2], I[:, 4])
+    tA = np.stack([I[:, [0, 1, 2, 5]], I[:, [0, 1, 5, 4]], I[:, [0, 4, 5, 3]]], 1)
+    tB = np.stack([I[:, [0, 1, 2, 4]], I[:, [0, 4, 2, 5]], I[:, [0, 4, 5, 3]]], 1)
+    return np.where(a[:, None, None], tA, tB).reshape(-1, 4)
+
+
+def cubed_sphere_shell(n, n_r, r_wall=1.0, r_far=6.0, h_first=5e-3):
+    """Vertices and prisms of a spherical shell: the six faces of a cube,
+    each an n x n grid of equal-angle points projected onto the sphere and
+    cut into triangles, extruded over n_r layers whose thickness grows
+    geometrically from h_first at the wall to r_far."""
+    span = r_far - r_wall
+    lo, hi = 1.0 + 1e-12, 3.0
+    for _ in range(200):
+        g = 0.5 * (lo + hi)
+        s = h_first * (g ** n_r - 1.0) / (g - 1.0)
+        lo, hi = (g, hi) if s < span else (lo, g)
+    radii = r_wall + h_first * (g ** np.arange(n_r + 1) - 1.0) / (g - 1.0)
+    radii[-1] = r_far
+    t = np.tan(-0.25 * math.pi + 0.5 * math.pi * np.arange(n + 1) / n)
+    pts, tris = [], []
+    for ax in range(3):
+        for sgn in (-1.0, 1.0):
+            a, b = np.meshgrid(t, t, indexing="ij")
+            v = np.zeros((n + 1, n + 1, 3))
+            v[..., ax] = sgn
+            v[..., (ax + 1) % 3] = a
+            v[..., (ax + 2) % 3] = b
+            v /= np.linalg.norm(v, axis=2, keepdims=True)
+            base = len(pts) * 0 + sum(len(x) for x in pts)
+            pts.append(v.reshape(-1, 3))
+            idx = base + np.arange((n + 1) * (n + 1)).reshape(n + 1, n + 1)
+            q00, q10, q11, q01 = idx[:-1, :-1], idx[1:, :-1], idx[1:, 1:], idx[:-1, 1:]
+            tris.append(np.stack([q00, q10, q11], -1).reshape(-1, 3))
+            tris.append(np.stack([q00, q11, q01], -1).reshape(-1, 3))
+    S = np.concatenate(pts)
+    # merge the points shared by neighbouring cube faces
+    _, uniq, inv = np.unique(np.round(S, 12), axis=0, return_index=True, return_inverse=True)
+    inv = inv.reshape(-1)
+    S = S[uniq]
+    tri = inv[np.concatenate(tris)]
+    ns = len(S)
+    X = (radii[:, None, None] * S[None, :, :]).reshape(-1, 3)
+    layers = np.arange(n_r)[:, None, None] * ns
+    prisms = np.concatenate([tri[None] + layers, tri[None] + layers + ns], axis=2).reshape(-1, 6)
+    return X, prisms
+
+
+def case_sphere(n=8, n_r=22, nv=24, half_width=10.0, ma=4.0, kn=0.05, Pr=0.72, omega=0.81, t_wall=1.0,
+                r_far=6.0, h_first=5e-3, wall_layer=0.2):
+    """3D sphere: a cubed-sphere shell around the unit sphere out to radius
+    6, n x n points per cube face, n_r layers from a 5e-3 first layer, each
+    prism cut into three tetrahedra (36 n^2 n_r cells: 50,688 by default);
+    Shakhov Pr = 0.72, Ma = 4, Kn = 0.05 on the diameter, isothermal wall at
+    T_inf; 24^3 trapezoid grid on [-10,10]^3.  Start: rho = T = 1 with the
+    potential flow around the sphere brought to rest over a wall layer."""
+    u_inf = ma * sound_speed(1.0)
+    X, prisms = cubed_sphere_shell(n, n_r, 1.0, r_far, h_first)
+    T = prisms_to_tets(prisms)
+    r_mid = 0.5 * (1.0 + r_far)
+    uvec = np.array([u_inf, 0.0, 0.0])
+
+    def classify(xc, nrm):
+        wall = np.linalg.norm(xc, axis=1) < r_mid
+        bc = np.where(wall, BC_WALL, np.where(nrm @ uvec < 0.0, BC_INFLOW, BC_OUTFLOW)).astype(np.int32)
+        return bc, np.where(wall, 1, 0).astype(np.int32)
+
+    mesh = mesh_from_tets(X, T, classify)
+    vg = tensor_vgrid(nv, half_width, 3)
+    bc = np.array([[1.0, u_inf, 0.0, 0.0, 1.0],
+                   [1.0, 0.0, 0.0, 0.0, t_wall]])
+    gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 2.0), bc_prim=bc, dim=3)
+    x = mesh["cell_centroid"]
+    r = np.linalg.norm(x, axis=1)
+    # potential flow past the unit sphere, phi = U x (1 + 1/(2 r^3)), brought
+    # to rest at the wall over wall_layer
+    vel = u_inf * (1.0 + 0.5 / r ** 3)[:, None] * np.array([1.0, 0.0, 0.0]) \
+        - (1.5 * u_inf * x[:, 0] / r ** 5)[:, None] * x
+    damp = 1.0 - np.exp(-(r - 1.0) / wall_layer)
+    prim0 = np.tile(bc[0], (len(x), 1))
+    prim0[:, 1:4] = vel * damp[:, None]
+    return dict(name=f"sphere_{len(x)}tet_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)

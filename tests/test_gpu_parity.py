@@ -395,6 +395,31 @@ def test_full_size_cylinder_fp64():
     assert f_rel_err(fg, fo) <= TOL
 
 
+def test_full_size_sphere_3d():
+    """The 3D sphere at its full size: 50,688 tetrahedra x 13,824 velocities
+    (24^3), Shakhov, Ma 4, wall and far field.  One step against the oracle:
+    FP64 to 1e-12 on W and q; FP32 storage to 1e-5."""
+    ugks = _gpu()
+    import torch
+    c = cases.case_sphere()
+    _say(f"case {c['name']}: full size, 1 step, fp64 and fp32 against the oracle")
+    o = oracle.Oracle(c)
+    s = ugks.Solver(c)
+    assert s.dt == pytest.approx(o.dt, rel=1e-15)
+    o.step(1)
+    s.step(1)
+    _compare(s, o, f_too=False)
+    s.close()
+    torch.cuda.synchronize()
+    s32 = ugks.Solver(c, fstore="f32")
+    s32.step(1)
+    Wg, _ = s32.macros()
+    Wo, _ = o.macros()
+    e = prim_errors(Wg, Wo)
+    _say(f"    fp32-f: rho {e['rho']:.2e} U {e['U']:.2e} T {e['T']:.2e}")
+    assert max(e.values()) <= 1e-5
+
+
 @pytest.mark.parametrize("kind", ["tet", "hex", "prism"])
 def test_3d_periodic_fp64(kind):
     """3D cells (4, 6 and 5 faces), 9^3 = 729 velocities: two full blocks of
