@@ -142,8 +142,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fstore", choices=["f64", "f32", "bf16"], default="f64")
-    ap.add_argument("--workload", choices=["cylinder", "sphere"], default="cylinder",
-                    help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities)")
+    ap.add_argument("--workload", choices=["cylinder", "sphere", "liftingbody"], default="cylinder",
+                    help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities); "
+                         "liftingbody: the X38-sized case (1,059,968 cells x 4,550 velocities, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -171,7 +172,8 @@ def main():
         return
 
     from paper_2412_06546_amd import cases
-    case = cases.case_cylinder() if args.workload == "cylinder" else cases.case_sphere()
+    case = {"cylinder": cases.case_cylinder, "sphere": cases.case_sphere,
+            "liftingbody": cases.case_lifting_body}[args.workload]()
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
     main_run = run_gpu(case, args.fstore, args.steps, args.warmup)
@@ -203,9 +205,11 @@ def main():
         "vs_baseline": None,
         "dtype": args.fstore,
         "data": "synthetic",
-        "config": {"workload": f"{case['name']}: " + ("2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall"
-                                                        if args.workload == "cylinder" else
-                                                        "3D sphere Ma 4 Kn 0.05 Shakhov, isothermal wall"),
+        "config": {"workload": f"{case['name']}: " + {
+                       "cylinder": "2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall",
+                       "sphere": "3D sphere Ma 4 Kn 0.05 Shakhov, isothermal wall",
+                       "liftingbody": "3D X38-sized lifting body Ma 8 AoA 20 Kn 0.01 Shakhov, wall 5.39 T_inf, "
+                                      "unstructured velocity set"}[args.workload],
                    "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64",
                    "prologue_ms": round(main_run["prologue_ms_avg"], 4),
                    "footprint_bytes": main_run["footprint_bytes"]},
@@ -213,7 +217,7 @@ def main():
     }
     if other:
         line["other_precision"] = other
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "liftingbody":
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds, 5)
     print(json.dumps(line), flush=True)

@@ -112,6 +112,7 @@ typedef struct ugks ugks_t;
  * The time step is fixed at creation (the velocity grid does not change):
  * dt = cfl * min over cells and velocities of
  *      |Omega_i| / sum_faces S max(0, u_k . n_outward).
+ * Limits: at most 16,000,000 cells and 16,384 velocities (UGKS_ERR_ARG).
  * Returns UGKS_OK and *out, or an error code (*out = NULL). */
 int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas,
                 const double *prim0, void *stream, ugks_t **out);

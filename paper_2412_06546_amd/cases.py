@@ -658,3 +658,207 @@ def case_sphere(n=8, n_r=22, nv=24, half_width=10.0, ma=4.0, kn=0.05, Pr=0.72, o
     prim0 = np.tile(bc[0], (len(x), 1))
     prim0[:, 1:4] = vel * damp[:, None]
     return dict(name=f"sphere_{len(x)}tet_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+
+
+def mesh_from_cells(X, classify_boundary, tets=None, prisms=None, hexes=None):
+    """Face data of a mesh of tetrahedra [n][4], prisms [n][6] (bottom
+    triangle 0,1,2, top 3,4,5 above) and hexahedra [n][8] (bottom quad 0..3,
+    top 4..7 above), vectorised.  Face area vectors are exact for bilinear
+    quadrilaterals (half the cross product of the diagonals) and oriented out
+    of the first cell; cell volumes and centroids come from tetrahedra
+    between the vertex average and the face triangles."""
+    X = np.asarray(X, dtype=np.float64)
+    groups = []
+    if tets is not None:
+        groups.append((np.asarray(tets, np.int64), [(1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1)]))
+    if prisms is not None:
+        groups.append((np.asarray(prisms, np.int64), [(0, 2, 1), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)]))
+    if hexes is not None:
+        groups.append((np.asarray(hexes, np.int64), [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5),
+                                                     (2, 3, 7, 6), (3, 0, 4, 7)]))
+    tri_f, tri_o, quad_f, quad_o = [], [], [], []
+    vols, cens = [], []
+    off = 0
+    for C, loc in groups:
+        G = X[C].mean(axis=1)
+        V = np.zeros(len(C))
+        M = np.zeros((len(C), 3))
+        for fl in loc:
+            F = C[:, list(fl)]
+            P = X[F]
+            # orient outward (cells are convex): normal away from the vertex average
+            if len(fl) == 3:
+                av = 0.5 * np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+            else:
+                av = 0.5 * np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 1])
+            flip = np.einsum("ij,ij->i", av, P.mean(axis=1) - G) < 0
+            F = np.where(flip[:, None], F[:, ::-1], F)
+            P = X[F]
+            tris = [(0, 1, 2)] if len(fl) == 3 else [(0, 1, 2), (0, 2, 3)]
+            for a, b, c in tris:
+                tv = np.einsum("ij,ij->i", P[:, a] - G, np.cross(P[:, b] - G, P[:, c] - G)) / 6.0
+                V += tv
+                M += tv[:, None] * (G + P[:, a] + P[:, b] + P[:, c]) / 4.0
+            owner = off + np.arange(len(C))
+            (tri_f if len(fl) == 3 else quad_f).append(F)
+            (tri_o if len(fl) == 3 else quad_o).append(owner)
+        if (V <= 0).any():
+            raise ValueError("cell with non-positive volume")
+        vols.append(V)
+        cens.append(M / V[:, None])
+        off += len(C)
+    vol = np.concatenate(vols)
+    cen = np.concatenate(cens)
+    out = {k: [] for k in ("l", "r", "av", "xc")}
+    for Fs, Os in ((tri_f, tri_o), (quad_f, quad_o)):
+        if not Fs:
+            continue
+        F = np.concatenate(Fs)
+        own = np.concatenate(Os)
+        key = np.sort(F, axis=1)
+        order = np.lexsort((own,) + tuple(key[:, j] for j in range(key.shape[1] - 1, -1, -1)))
+        key, F, own = key[order], F[order], own[order]
+        first = np.ones(len(key), dtype=bool)
+        first[1:] = (key[1:] != key[:-1]).any(axis=1)
+        start = np.nonzero(first)[0]
+        count = np.diff(np.append(start, len(key)))
+        if (count > 2).any():
+            raise ValueError("face shared by more than two cells")
+        Ff = F[start]
+        P = X[Ff]
+        if F.shape[1] == 3:
+            av = 0.5 * np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+            xc = P.mean(axis=1)
+        else:
+            av = 0.5 * np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 1])
+            a1 = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+            a2 = 0.5 * np.linalg.norm(np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]), axis=1)
+            c1 = (P[:, 0] + P[:, 1] + P[:, 2]) / 3.0
+            c2 = (P[:, 0] + P[:, 2] + P[:, 3]) / 3.0
+            xc = (a1[:, None] * c1 + a2[:, None] * c2) / (a1 + a2)[:, None]
+        out["l"].append(own[start])
+        out["r"].append(np.where(count == 2, own[np.minimum(start + 1, len(own) - 1)], -1))
+        out["av"].append(av)
+        out["xc"].append(xc)
+    l, r = np.concatenate(out["l"]), np.concatenate(out["r"])
+    av, xc = np.concatenate(out["av"]), np.concatenate(out["xc"])
+    area = np.linalg.norm(av, axis=1)
+    normal = av / area[:, None]
+    bc = np.zeros(len(l), dtype=np.int32)
+    bid = np.zeros(len(l), dtype=np.int32)
+    b = r < 0
+    if b.any():
+        cb, ib = classify_boundary(xc[b], normal[b])
+        bc[b], bid[b] = cb, ib
+    return dict(dim=3, cell_volume=vol, cell_centroid=cen, face_cells=np.stack([l, r], 1).astype(np.int32),
+                face_normal=normal, face_area=area, face_centroid=xc, face_shift=np.zeros_like(xc),
+                face_bc=bc, face_bc_id=bid)
+
+
+def lifting_body_shell(n, n_r, axes=(3.0, 1.2, 0.6), r_far=12.0, h_first=5e-3, prism_patches=(4, 5)):
+    """Hexahedra and prisms around a synthetic lifting body, an ellipsoid
+    with semi-axes `axes`: the six faces of a cube, n x n equal-angle points
+    each, projected onto the body and joined by straight lines to a far-field
+    sphere of radius r_far, n_r layers growing geometrically from h_first
+    (relative to the local line length).  Cube faces listed in prism_patches
+    (0..5: -x, +x, -y, +y, -z, +z) are cut into triangles and give prisms;
+    the others give hexahedra."""
+    lo, hi = 1.0 + 1e-12, 3.0
+    for _ in range(200):
+        g = 0.5 * (lo + hi)
+        s = h_first * (g ** n_r - 1.0) / (g - 1.0)
+        lo, hi = (g, hi) if s < 1.0 else (lo, g)
+    eta = h_first * (g ** np.arange(n_r + 1) - 1.0) / (g - 1.0)
+    eta[-1] = 1.0
+    t = np.tan(-0.25 * math.pi + 0.5 * math.pi * np.arange(n + 1) / n)
+    pts, quads, tri = [], [], []
+    base = 0
+    patch = 0
+    for ax in range(3):
+        for sgn in (-1.0, 1.0):
+            a, b = np.meshgrid(t, t, indexing="ij")
+            v = np.zeros((n + 1, n + 1, 3))
+            v[..., ax] = sgn
+            v[..., (ax + 1) % 3] = a
+            v[..., (ax + 2) % 3] = b
+            v /= np.linalg.norm(v, axis=2, keepdims=True)
+            pts.append(v.reshape(-1, 3))
+            idx = base + np.arange((n + 1) * (n + 1)).reshape(n + 1, n + 1)
+            q = np.stack([idx[:-1, :-1], idx[1:, :-1], idx[1:, 1:], idx[:-1, 1:]], -1).reshape(-1, 4)
+            if patch in prism_patches:
+                tri.append(q[:, [0, 1, 2]])
+                tri.append(q[:, [0, 2, 3]])
+            else:
+                quads.append(q)
+            base += (n + 1) * (n + 1)
+            patch += 1
+    S = np.concatenate(pts)
+    _, uniq, inv = np.unique(np.round(S, 12), axis=0, return_index=True, return_inverse=True)
+    inv = inv.reshape(-1)
+    S = S[uniq]
+    ns = len(S)
+    body = S * np.asarray(axes)[None, :]
+    far = S * r_far
+    X = (body[None] + eta[:, None, None] * (far - body)[None]).reshape(-1, 3)
+    layers = np.arange(n_r)[:, None, None] * ns
+    hexes = prisms = None
+    if quads:
+        Q = inv[np.concatenate(quads)]
+        hexes = np.concatenate([Q[None] + layers, Q[None] + layers + ns], axis=2).reshape(-1, 8)
+    if tri:
+        Tr = inv[np.concatenate(tri)]
+        prisms = np.concatenate([Tr[None] + layers, Tr[None] + layers + ns], axis=2).reshape(-1, 6)
+    return X, hexes, prisms
+
+
+def octree_vgrid(n_base, half_width, centres, radius):
+    """Unstructured velocity set: an n_base^3 Cartesian partition of
+    [-half_width, half_width]^3 whose cells within `radius` of any of the
+    `centres` (e.g. the free-stream and wall Maxwellians) are split into
+    eight; the points are the cell centres and the weights the cell volumes
+    (Section 2.3, unstructured velocity meshes)."""
+    h = 2.0 * half_width / n_base
+    g = -half_width + h * (np.arange(n_base) + 0.5)
+    C = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    near = np.zeros(len(C), dtype=bool)
+    for c in centres:
+        near |= np.linalg.norm(C - np.asarray(c)[None], axis=1) < radius
+    sub = np.array([[a, b, c] for a in (-0.25, 0.25) for b in (-0.25, 0.25) for c in (-0.25, 0.25)]) * h
+    u = np.concatenate([C[~near], (C[near][:, None, :] + sub[None]).reshape(-1, 3)])
+    w = np.concatenate([np.full((~near).sum(), h ** 3), np.full(8 * near.sum(), (0.5 * h) ** 3)])
+    return dict(dim=3, u=np.ascontiguousarray(u), w=w)
+
+
+def case_lifting_body(n=52, n_r=49, ma=8.0, kn=0.01, Pr=0.72, omega=0.81, t_wall=5.39, aoa_deg=20.0,
+                      n_base=14, half_width=15.0, refine_radius=7.05, closed=False, start="freestream"):
+    """X38-sized synthetic blunt body: about 1.06 million cells (hexahedra,
+    and prisms on the two z patches) around an ellipsoidal lifting body out
+    to a radius-12 far field; Ma 8 at 20 degrees angle of attack, Kn 0.01,
+    Shakhov Pr 0.72, wall at 5.39 T_inf; an unstructured velocity set of
+    4,550 points refined around the free-stream and wall Maxwellians.
+    closed=True turns the far field into a resting wall at T_inf (a closed
+    vessel, whose mass the scheme conserves exactly at any size);
+    start='rest' starts from gas at rest at T_inf."""
+    u_inf = ma * sound_speed(1.0)
+    a = math.radians(aoa_deg)
+    U = np.array([u_inf * math.cos(a), 0.0, u_inf * math.sin(a)])
+    X, hexes, prisms = lifting_body_shell(n, n_r)
+
+    def classify(xc, nrm):
+        body = np.linalg.norm(xc, axis=1) < 6.0
+        if closed:
+            return np.full(len(xc), BC_WALL, np.int32), np.where(body, 1, 2).astype(np.int32)
+        far = np.where(nrm @ U < 0.0, BC_INFLOW, BC_OUTFLOW)
+        return np.where(body, BC_WALL, far).astype(np.int32), np.where(body, 1, 0).astype(np.int32)
+
+    mesh = mesh_from_cells(X, classify, prisms=prisms, hexes=hexes)
+    vg = octree_vgrid(n_base, half_width, [U, np.zeros(3)], refine_radius)
+    bc = np.array([[1.0, U[0], U[1], U[2], 1.0],
+                   [1.0, 0.0, 0.0, 0.0, t_wall],
+                   [1.0, 0.0, 0.0, 0.0, 1.0]])
+    gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 6.0), bc_prim=bc, dim=3)
+    if start not in ("freestream", "rest"):
+        raise ValueError(start)
+    prim0 = np.tile(bc[0] if start == "freestream" else bc[2], (len(mesh["cell_volume"]), 1))
+    nc, nv = len(mesh["cell_volume"]), len(vg["w"])
+    return dict(name=f"liftingbody_{nc}_v{nv}", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)

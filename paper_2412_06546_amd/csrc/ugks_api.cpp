@@ -481,6 +481,8 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (mesh->n_cells <= 0 || mesh->n_faces <= 0 || vgrid->n_vel <= 0)
             throw Fail{UGKS_ERR_ARG, "empty mesh or velocity grid"};
         if (vgrid->n_vel > 16384) throw Fail{UGKS_ERR_ARG, "more than 16384 discrete velocities"};
+        // per-cell launches of 256 threads must stay below 2^32 work-items
+        if (mesh->n_cells > 16000000) throw Fail{UGKS_ERR_ARG, "more than 16,000,000 cells"};
         if (!mesh->cell_volume || !mesh->cell_centroid || !mesh->face_cells || !mesh->face_normal || !mesh->face_area ||
             !mesh->face_centroid || !vgrid->u || !vgrid->w)
             throw Fail{UGKS_ERR_ARG, "NULL mesh or velocity array"};

@@ -312,26 +312,32 @@ __global__ __launch_bounds__(256) void k_cfl(Params p, double *cell_dt)
 // ------------------------------------------------------------------------
 // initial state: discrete Maxwellian of (rho, U, T)
 // ------------------------------------------------------------------------
+// One workgroup per cell, threads over its velocities (a thread per
+// (cell, velocity) would exceed the 2^32 work-items of one grid dimension on
+// the largest meshes).
 template <int D, typename FT>
 __global__ __launch_bounds__(256) void k_init(Params p, const double *__restrict__ prim0, FT *__restrict__ f)
 {
     constexpr int NC = Dim<D>::NC;
-    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (size_t)p.nc * p.nv) return;
-    const int i = (int)(t / p.nv), k = (int)(t % p.nv);
+    const int i = blockIdx.x;
     const double *pr = prim0 + (size_t)i * (D + 2);
-    double u[D], U[D], zq[D];
+    double U[D], zq[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        u[d] = p.u[d * p.nv + k];
         U[d] = pr[1 + d];
         zq[d] = 0.0;
     }
     const double lam = 1.0 / pr[D + 1];
-    double H, B;
-    equilibrium<D>(u, U, lam, pr[0] * pow_lam_pi<D>(lam), 0.0, zq, H, B);
-    f[((size_t)i * NC + 0) * p.nv + k] = from_f64<FT>(H);
-    if constexpr (NC > 1) f[((size_t)i * NC + 1) * p.nv + k] = from_f64<FT>(B);
+    const double pref = pr[0] * pow_lam_pi<D>(lam);
+    for (int k = threadIdx.x; k < p.nv; k += 256) {
+        double u[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) u[d] = p.u[d * p.nv + k];
+        double H, B;
+        equilibrium<D>(u, U, lam, pref, 0.0, zq, H, B);
+        f[((size_t)i * NC + 0) * p.nv + k] = from_f64<FT>(H);
+        if constexpr (NC > 1) f[((size_t)i * NC + 1) * p.nv + k] = from_f64<FT>(B);
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -1094,9 +1100,7 @@ hipError_t launch_cfl(const Params &p, double *cell_dt, hipStream_t s)
 
 template <int D, typename FT> hipError_t init_d(const Params &p, const double *prim0, void *f, hipStream_t s)
 {
-    size_t n = (size_t)p.nc * p.nv;
-    hipLaunchKernelGGL((k_init<D, FT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, prim0,
-                       static_cast<FT *>(f));
+    hipLaunchKernelGGL((k_init<D, FT>), dim3(p.nc), dim3(256), 0, s, p, prim0, static_cast<FT *>(f));
     return hipGetLastError();
 }
 hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_t s)

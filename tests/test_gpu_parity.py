@@ -420,6 +420,28 @@ def test_full_size_sphere_3d():
     assert max(e.values()) <= 1e-5
 
 
+def test_full_size_lifting_body_conserves_mass():
+    """The X38-sized case at its full size (1,059,968 hexahedra and prisms x
+    4,550 unstructured velocities, 77 GB of f in FP64), closed: the far field
+    is a resting wall at T_inf and the body a wall at 5.39 T_inf, gas at
+    rest.  The oracle cannot run at this size; what holds at any size is
+    that no mass crosses a wall and interior fluxes cancel in pairs, so the
+    total mass is conserved to round-off."""
+    ugks = _gpu()
+    c = cases.case_lifting_body(closed=True, start="rest")
+    _say(f"case {c['name']}: full size, closed, fp64, 3 steps")
+    vol = c["mesh"]["cell_volume"]
+    s = ugks.Solver(c)
+    W0, _ = s.macros()
+    m0 = (W0[:, 0] * vol).sum()
+    s.step(3)
+    W, _ = s.macros()
+    m1 = (W[:, 0] * vol).sum()
+    _say(f"    relative mass change {abs(m1 - m0) / m0:.2e}; max |U| {np.abs(W[:, 1:4] / W[:, :1]).max():.3e}")
+    assert abs(m1 - m0) <= 1e-12 * m0
+    assert np.abs(W - W0).max() > 0.0
+
+
 @pytest.mark.parametrize("kind", ["tet", "hex", "prism"])
 def test_3d_periodic_fp64(kind):
     """3D cells (4, 6 and 5 faces), 9^3 = 729 velocities: two full blocks of
