@@ -65,20 +65,27 @@ def copy_calibration(nbytes: int, reps: int):
 
 def cpu_baseline(case, target_s: float, max_steps: int):
     """The FP64 oracle as it stands, on the host cores, on the same workload;
-    set-up (time step, initial state) excluded."""
+    set-up (time step, initial state) excluded.  Timed with all cores
+    (bounded by target_s), then one step on one core."""
     import oracle
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
-    o = oracle.Oracle(case)
+    o = oracle.Oracle(case, omp_threads=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    cores = o.threads
     steps, t = 0, 0.0
     while steps < max_steps and t < target_s:
         t0 = time.perf_counter()
         o.step(1)
         t += time.perf_counter() - t0
         steps += 1
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    o.set_threads(cores)
     return {"value": nc * nv * steps / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} full steps of the same {nc}-cell x {nv}-velocity workload ({t:.1f} s, "
-                      f"OpenMP over cells, gcc -O2)"}
+            "single_core_value": nc * nv / t1,
+            "sample": f"{steps} full steps of the same {nc}-cell x {nv}-velocity workload on {cores} threads "
+                      f"({t:.1f} s, OpenMP over cells, gcc -O2), then 1 step on 1 thread ({t1:.1f} s)"}
 
 
 def run_gpu(case, fstore: str, steps: int, warmup: int):

@@ -66,6 +66,8 @@ def lib():
         L.orc_get.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_set_f.argtypes = [C.c_void_p, _dp]
         L.orc_residual.argtypes = [C.c_void_p, _dp]
+        L.orc_set_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_n_wall.restype = C.c_int
         L.orc_n_wall.argtypes = [C.c_void_p]
         L.orc_wall_flux.argtypes = [C.c_void_p, _dp]
@@ -97,9 +99,8 @@ class Oracle:
     """One flow case advanced by the CPU oracle."""
 
     def __init__(self, case, omp_threads: int | None = None):
-        if omp_threads is not None:
-            os.environ["OMP_NUM_THREADS"] = str(omp_threads)
         L = lib()
+        self.threads = L.orc_set_threads(int(omp_threads) if omp_threads else 0)
         m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
         self.dim = int(m["dim"])
         self.nc = len(m["cell_volume"])
@@ -141,6 +142,11 @@ class Oracle:
     @property
     def dt(self) -> float:
         return self._L.orc_dt(self._h)
+
+    def set_threads(self, n: int) -> int:
+        """OpenMP threads of the oracle's loops from now on."""
+        self.threads = self._L.orc_set_threads(int(n))
+        return self.threads
 
     @property
     def nstep(self) -> int:

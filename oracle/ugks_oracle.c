@@ -44,6 +44,9 @@
  *    stage-1 distribution about U^{n+1}.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -641,6 +644,18 @@ void orc_destroy(orc_t *o)
 }
 
 double orc_dt(const orc_t *o) { return o->dt; }
+
+/* threads of the OpenMP loops from now on (timing at one core and at all) */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 long orc_nstep(const orc_t *o) { return o->nstep; }
 
 /* f in [cell][component][velocity] order, then W and q as its moments */
