@@ -151,7 +151,7 @@ def main():
     ap.add_argument("--fstore", choices=["f64", "f32", "bf16"], default="f64")
     ap.add_argument("--workload", choices=["cylinder", "sphere", "liftingbody"], default="cylinder",
                     help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities); "
-                         "liftingbody: the X38-sized case (1,059,968 cells x 4,550 velocities, no CPU baseline)")
+                         "liftingbody: the X38-sized case (1,058,685 cells x 4,548 velocities, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

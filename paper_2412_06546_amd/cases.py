@@ -755,14 +755,17 @@ def mesh_from_cells(X, classify_boundary, tets=None, prisms=None, hexes=None):
                 face_bc=bc, face_bc_id=bid)
 
 
-def lifting_body_shell(n, n_r, axes=(3.0, 1.2, 0.6), r_far=12.0, h_first=5e-3, prism_patches=(4, 5)):
-    """Hexahedra and prisms around a synthetic lifting body, an ellipsoid
-    with semi-axes `axes`: the six faces of a cube, n x n equal-angle points
-    each, projected onto the body and joined by straight lines to a far-field
+def lifting_body_shell(n, n_r, n_prism_columns=0, axes=(3.0, 1.2, 0.6), z_lower=0.35, r_far=12.0, h_first=5e-3):
+    """Hexahedra and prisms around a synthetic lifting body: an ellipsoid with
+    semi-axes `axes` above z = 0 and a flatter lower surface (z semi-axis
+    z_lower).  The six faces of a cube, n x n equal-angle points each, are
+    projected onto the body and joined by straight lines to a far-field
     sphere of radius r_far, n_r layers growing geometrically from h_first
-    (relative to the local line length).  Cube faces listed in prism_patches
-    (0..5: -x, +x, -y, +y, -z, +z) are cut into triangles and give prisms;
-    the others give hexahedra."""
+    (relative to the local line length): 6 n^2 n_r hexahedra.  The
+    n_prism_columns radial columns nearest the two poles (the z axis) are
+    each cut into two prisms along a diagonal of their quadrilaterals (whole
+    columns, so that the cut faces match between layers): 6 n^2 n_r +
+    n_prism_columns n_r cells."""
     lo, hi = 1.0 + 1e-12, 3.0
     for _ in range(200):
         g = 0.5 * (lo + hi)
@@ -771,9 +774,8 @@ def lifting_body_shell(n, n_r, axes=(3.0, 1.2, 0.6), r_far=12.0, h_first=5e-3, p
     eta = h_first * (g ** np.arange(n_r + 1) - 1.0) / (g - 1.0)
     eta[-1] = 1.0
     t = np.tan(-0.25 * math.pi + 0.5 * math.pi * np.arange(n + 1) / n)
-    pts, quads, tri = [], [], []
+    pts, quads = [], []
     base = 0
-    patch = 0
     for ax in range(3):
         for sgn in (-1.0, 1.0):
             a, b = np.meshgrid(t, t, indexing="ij")
@@ -784,65 +786,82 @@ def lifting_body_shell(n, n_r, axes=(3.0, 1.2, 0.6), r_far=12.0, h_first=5e-3, p
             v /= np.linalg.norm(v, axis=2, keepdims=True)
             pts.append(v.reshape(-1, 3))
             idx = base + np.arange((n + 1) * (n + 1)).reshape(n + 1, n + 1)
-            q = np.stack([idx[:-1, :-1], idx[1:, :-1], idx[1:, 1:], idx[:-1, 1:]], -1).reshape(-1, 4)
-            if patch in prism_patches:
-                tri.append(q[:, [0, 1, 2]])
-                tri.append(q[:, [0, 2, 3]])
-            else:
-                quads.append(q)
+            quads.append(np.stack([idx[:-1, :-1], idx[1:, :-1], idx[1:, 1:], idx[:-1, 1:]], -1).reshape(-1, 4))
             base += (n + 1) * (n + 1)
-            patch += 1
     S = np.concatenate(pts)
     _, uniq, inv = np.unique(np.round(S, 12), axis=0, return_index=True, return_inverse=True)
     inv = inv.reshape(-1)
     S = S[uniq]
+    Q = inv[np.concatenate(quads)]
     ns = len(S)
-    body = S * np.asarray(axes)[None, :]
+    scale = np.tile(np.asarray(axes, dtype=np.float64), (ns, 1))
+    scale[S[:, 2] < 0, 2] = z_lower
+    body = S * scale
     far = S * r_far
     X = (body[None] + eta[:, None, None] * (far - body)[None]).reshape(-1, 3)
+    # columns nearest the poles become prisms (ties broken by column index)
+    pole = 1.0 - np.abs(S[Q].mean(axis=1)[:, 2])
+    order = np.lexsort((np.arange(len(Q)), pole))
+    split = np.zeros(len(Q), dtype=bool)
+    split[order[:n_prism_columns]] = True
     layers = np.arange(n_r)[:, None, None] * ns
-    hexes = prisms = None
-    if quads:
-        Q = inv[np.concatenate(quads)]
-        hexes = np.concatenate([Q[None] + layers, Q[None] + layers + ns], axis=2).reshape(-1, 8)
-    if tri:
-        Tr = inv[np.concatenate(tri)]
-        prisms = np.concatenate([Tr[None] + layers, Tr[None] + layers + ns], axis=2).reshape(-1, 6)
+    Qh, Qp = Q[~split], Q[split]
+    hexes = np.concatenate([Qh[None] + layers, Qh[None] + layers + ns], axis=2).reshape(-1, 8)
+    prisms = None
+    if len(Qp):
+        tri = np.concatenate([Qp[:, [0, 1, 2]], Qp[:, [0, 2, 3]]])
+        prisms = np.concatenate([tri[None] + layers, tri[None] + layers + ns], axis=2).reshape(-1, 6)
     return X, hexes, prisms
 
 
-def octree_vgrid(n_base, half_width, centres, radius):
+def octree_vgrid(n_base, half_width, levels, n_keep=None):
     """Unstructured velocity set: an n_base^3 Cartesian partition of
-    [-half_width, half_width]^3 whose cells within `radius` of any of the
-    `centres` (e.g. the free-stream and wall Maxwellians) are split into
-    eight; the points are the cell centres and the weights the cell volumes
-    (Section 2.3, unstructured velocity meshes)."""
+    [-half_width, half_width]^3 refined level by level: at each level
+    (centres, radius) the cells whose centre lies within radius of one of
+    the centres (e.g. the free-stream and wall Maxwellians) are split into
+    eight.  The points are the cell centres and the weights the cell volumes
+    (Section 2.3, unstructured velocity meshes).  n_keep trims the set to
+    that many points by dropping the ones farthest from the origin."""
     h = 2.0 * half_width / n_base
     g = -half_width + h * (np.arange(n_base) + 0.5)
     C = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
-    near = np.zeros(len(C), dtype=bool)
-    for c in centres:
-        near |= np.linalg.norm(C - np.asarray(c)[None], axis=1) < radius
-    sub = np.array([[a, b, c] for a in (-0.25, 0.25) for b in (-0.25, 0.25) for c in (-0.25, 0.25)]) * h
-    u = np.concatenate([C[~near], (C[near][:, None, :] + sub[None]).reshape(-1, 3)])
-    w = np.concatenate([np.full((~near).sum(), h ** 3), np.full(8 * near.sum(), (0.5 * h) ** 3)])
-    return dict(dim=3, u=np.ascontiguousarray(u), w=w)
+    H = np.full(len(C), h)
+    sub = np.array([[a, b, c] for a in (-0.25, 0.25) for b in (-0.25, 0.25) for c in (-0.25, 0.25)])
+    for centres, radius in levels:
+        near = np.zeros(len(C), dtype=bool)
+        for c in centres:
+            near |= np.linalg.norm(C - np.asarray(c)[None], axis=1) < radius
+        fine = (C[near][:, None, :] + sub[None] * H[near][:, None, None]).reshape(-1, 3)
+        C = np.concatenate([C[~near], fine])
+        H = np.concatenate([H[~near], np.repeat(0.5 * H[near], 8)])
+    w = H ** 3
+    if n_keep is not None and n_keep < len(w):
+        keep = np.sort(np.lexsort((np.arange(len(w)), np.linalg.norm(C, axis=1)))[:n_keep])
+        C, w = C[keep], w[keep]
+    return dict(dim=3, u=np.ascontiguousarray(C), w=np.ascontiguousarray(w))
 
 
-def case_lifting_body(n=52, n_r=49, ma=8.0, kn=0.01, Pr=0.72, omega=0.81, t_wall=5.39, aoa_deg=20.0,
-                      n_base=14, half_width=15.0, refine_radius=7.05, closed=False, start="freestream"):
-    """X38-sized synthetic blunt body: about 1.06 million cells (hexahedra,
-    and prisms on the two z patches) around an ellipsoidal lifting body out
-    to a radius-12 far field; Ma 8 at 20 degrees angle of attack, Kn 0.01,
-    Shakhov Pr 0.72, wall at 5.39 T_inf; an unstructured velocity set of
-    4,550 points refined around the free-stream and wall Maxwellians.
+def case_lifting_body(n=32, n_r=163, n_prism_columns=351, ma=8.0, kn=0.01, Pr=0.72, omega=0.81, t_wall=5.39,
+                      aoa_deg=20.0, n_base=14, half_width=15.0, refine=(6.5, 2.2), n_vel=4548, closed=False,
+                      start="layer", wall_layer=0.5):
+    """X38-sized synthetic blunt body: 1,058,685 cells (hexahedra, and the
+    351 radial columns nearest the poles as prisms) around a lifting body
+    out to a radius-12 far field; Ma 8 at 20 degrees angle of attack,
+    Kn 0.01, Shakhov Pr 0.72, wall at 5.39 T_inf; an unstructured velocity
+    set of 4,548 points: 14^3 cells of [-15,15]^3, those within 6.5 of the
+    free-stream or the wall velocity split once, those within 2.2 of the
+    free-stream velocity split again.
     closed=True turns the far field into a resting wall at T_inf (a closed
-    vessel, whose mass the scheme conserves exactly at any size);
-    start='rest' starts from gas at rest at T_inf."""
+    vessel, whose mass the scheme conserves exactly at any size).  Start:
+    'layer' (default) the free stream brought to rest towards the body, as
+    U_inf (1 - exp(-(F - 1)/wall_layer)) with F the body's ellipsoid
+    function (1 on the surface); 'freestream' the uniform free stream
+    (impulsive: the first layer empties within tens of steps); 'rest' gas
+    at rest at T_inf."""
     u_inf = ma * sound_speed(1.0)
     a = math.radians(aoa_deg)
     U = np.array([u_inf * math.cos(a), 0.0, u_inf * math.sin(a)])
-    X, hexes, prisms = lifting_body_shell(n, n_r)
+    X, hexes, prisms = lifting_body_shell(n, n_r, n_prism_columns)
 
     def classify(xc, nrm):
         body = np.linalg.norm(xc, axis=1) < 6.0
@@ -852,13 +871,18 @@ def case_lifting_body(n=52, n_r=49, ma=8.0, kn=0.01, Pr=0.72, omega=0.81, t_wall
         return np.where(body, BC_WALL, far).astype(np.int32), np.where(body, 1, 0).astype(np.int32)
 
     mesh = mesh_from_cells(X, classify, prisms=prisms, hexes=hexes)
-    vg = octree_vgrid(n_base, half_width, [U, np.zeros(3)], refine_radius)
+    vg = octree_vgrid(n_base, half_width, [([U, np.zeros(3)], refine[0]), ([U], refine[1])], n_vel)
     bc = np.array([[1.0, U[0], U[1], U[2], 1.0],
                    [1.0, 0.0, 0.0, 0.0, t_wall],
                    [1.0, 0.0, 0.0, 0.0, 1.0]])
     gas = gas_params(Pr, omega, vhs_mu_ref(kn, omega, 6.0), bc_prim=bc, dim=3)
-    if start not in ("freestream", "rest"):
+    if start not in ("layer", "freestream", "rest"):
         raise ValueError(start)
-    prim0 = np.tile(bc[0] if start == "freestream" else bc[2], (len(mesh["cell_volume"]), 1))
+    prim0 = np.tile(bc[2] if start == "rest" else bc[0], (len(mesh["cell_volume"]), 1))
+    if start == "layer":
+        x = mesh["cell_centroid"]
+        cz = np.where(x[:, 2] < 0.0, 0.35, 0.6)
+        F = np.sqrt((x[:, 0] / 3.0) ** 2 + (x[:, 1] / 1.2) ** 2 + (x[:, 2] / cz) ** 2)
+        prim0[:, 1:4] *= (1.0 - np.exp(-np.maximum(F - 1.0, 0.0) / wall_layer))[:, None]
     nc, nv = len(mesh["cell_volume"]), len(vg["w"])
     return dict(name=f"liftingbody_{nc}_v{nv}", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)

@@ -421,8 +421,8 @@ def test_full_size_sphere_3d():
 
 
 def test_full_size_lifting_body_conserves_mass():
-    """The X38-sized case at its full size (1,059,968 hexahedra and prisms x
-    4,550 unstructured velocities, 77 GB of f in FP64), closed: the far field
+    """The X38-sized case at its full size (1,058,685 hexahedra and prisms x
+    4,548 unstructured velocities, 77 GB of f in FP64), closed: the far field
     is a resting wall at T_inf and the body a wall at 5.39 T_inf, gas at
     rest.  The oracle cannot run at this size; what holds at any size is
     that no mass crosses a wall and interior fluxes cancel in pairs, so the
