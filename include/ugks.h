@@ -155,7 +155,8 @@ double ugks_dt(const ugks_t *h);            /* time step, or -1 for a NULL handl
 int ugks_n_comp(const ugks_t *h);           /* stored components per (cell, velocity) */
 long ugks_step_count(const ugks_t *h);      /* steps taken since creation */
 size_t ugks_footprint_bytes(const ugks_t *h); /* device bytes owned by the handle */
-int ugks_is_tensor_grid(const ugks_t *h);   /* 1 if the separable velocity path is used */
+int ugks_is_tensor_grid(const ugks_t *h);   /* 1 if Gaussians are tabulated per axis (few distinct
+                                               coordinate values per axis), 0 if evaluated directly */
 
 /* Timing of the step's kernels with HIP events on the handle's stream.
  * ugks_profile(h, 1) resets the counters and records events around every

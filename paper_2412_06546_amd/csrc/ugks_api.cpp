@@ -105,45 +105,36 @@ void upload(void *dst, const void *src, size_t bytes, hipStream_t s)
     hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync H2D");
 }
 
-// A velocity set laid out as a Cartesian product with the last axis
-// contiguous: u_k = (x_a, y_b[, z_c]) at k = (a * ny + b) * nz + c.
-// Returns 1 and the axes when it is one.
+// Separable Gaussians: exp(-lam |u - U|^2) is the product over the axes of
+// exp(-lam (u_d - U_d)^2), so it can be tabulated per axis over the distinct
+// values that the velocity set's coordinates take on that axis.  That holds
+// for Cartesian grids, and equally for octree-refined or ball-restricted
+// sets, whose points share few coordinate values per axis.  Returns 1 with
+// the axes (the sorted distinct values, x then y [then z]), their counts and
+// every velocity's packed axis indices (a | b << 10 | c << 20), when every
+// axis has at most 1023 distinct values.
 int detect_tensor(int D, int nv, const double *u, int n1d[3], std::vector<double> &axes, std::vector<int> &kidx)
 {
-    int n_last = 1;
-    while (n_last < nv && u[(size_t)n_last * D + 0] == u[0]) ++n_last;
-    int nx, ny, nz = 1;
-    if (nv % n_last) return 0;
-    if (D == 2) {
-        ny = n_last;
-        nx = nv / n_last;
-    } else {
-        while (nz < n_last && u[(size_t)nz * 3 + 1] == u[1]) ++nz;
-        if (n_last % nz) return 0;
-        ny = n_last / nz;
-        nx = nv / n_last;
+    std::vector<double> vals[3];
+    for (int d = 0; d < D; ++d) {
+        vals[d].resize(nv);
+        for (int k = 0; k < nv; ++k) vals[d][k] = u[(size_t)k * D + d];
+        std::sort(vals[d].begin(), vals[d].end());
+        vals[d].erase(std::unique(vals[d].begin(), vals[d].end()), vals[d].end());
+        if (vals[d].size() > 1023) return 0;
     }
-    if (nx > 1023 || ny > 1023 || nz > 1023) return 0;
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < ny; ++b)
-            for (int c = 0; c < nz; ++c) {
-                const size_t k = ((size_t)a * ny + b) * nz + c;
-                if (u[k * D] != u[(size_t)a * n_last * D]) return 0;
-                if (u[k * D + 1] != u[(size_t)b * nz * D + 1]) return 0;
-                if (D == 3 && u[k * D + 2] != u[(size_t)c * D + 2]) return 0;
-            }
-    n1d[0] = nx;
-    n1d[1] = ny;
-    n1d[2] = D == 3 ? nz : 0;
     axes.clear();
-    for (int a = 0; a < nx; ++a) axes.push_back(u[(size_t)a * n_last * D]);
-    for (int b = 0; b < ny; ++b) axes.push_back(u[(size_t)b * nz * D + 1]);
-    if (D == 3)
-        for (int c = 0; c < nz; ++c) axes.push_back(u[(size_t)c * D + 2]);
-    kidx.resize(nv);
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < ny; ++b)
-            for (int c = 0; c < nz; ++c) kidx[((size_t)a * ny + b) * nz + c] = a | (b << 10) | (c << 20);
+    for (int d = 0; d < 3; ++d) {
+        n1d[d] = d < D ? (int)vals[d].size() : 0;
+        if (d < D) axes.insert(axes.end(), vals[d].begin(), vals[d].end());
+    }
+    kidx.assign(nv, 0);
+    for (int k = 0; k < nv; ++k)
+        for (int d = 0; d < D; ++d) {
+            const double x = u[(size_t)k * D + d];
+            const int a = (int)(std::lower_bound(vals[d].begin(), vals[d].end(), x) - vals[d].begin());
+            kidx[k] |= a << (10 * d);
+        }
     return 1;
 }
 

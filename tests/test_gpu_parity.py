@@ -470,8 +470,9 @@ def test_3d_channel_sliding_wall_fp64(kind):
 
 def test_3d_unstructured_velocity_set_fp64():
     """A velocity point set that is not a Cartesian product (points of a
-    Cartesian grid kept inside a ball, weights = cell volumes): the direct
-    exponential path."""
+    Cartesian grid kept inside a ball, weights = cell volumes): its points
+    share few coordinate values per axis, so the Gaussians are still
+    tabulated per axis."""
     ugks = _gpu()
     c = cases.case_box_wave_3d(kind="tet", nv=12, half_width=5.0)
     u, w = c["vgrid"]["u"], c["vgrid"]["w"]
@@ -479,9 +480,42 @@ def test_3d_unstructured_velocity_set_fp64():
     c["vgrid"] = dict(dim=3, u=np.ascontiguousarray(u[keep]), w=np.ascontiguousarray(w[keep]))
     _say(f"case {c['name']} ball of {keep.sum()} velocities: fp64, 10 steps")
     s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert s.tensor_grid
+    s.step(10)
+    o.step(10)
+    _compare(s, o)
+
+
+def test_3d_scattered_velocity_set_fp64():
+    """Velocity points with no shared coordinates (a ball of grid points,
+    each moved by a seeded jitter): too many distinct values per axis for
+    the per-axis tables, so every Gaussian is a direct exponential."""
+    ugks = _gpu()
+    c = cases.case_box_wave_3d(kind="hex", nv=12, half_width=5.0)
+    u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+    keep = (u ** 2).sum(1) <= 5.0 ** 2
+    rng = np.random.default_rng(5)
+    uj = u[keep] + rng.uniform(-0.05, 0.05, (keep.sum(), 3))
+    c["vgrid"] = dict(dim=3, u=np.ascontiguousarray(uj), w=np.ascontiguousarray(w[keep]))
+    _say(f"case {c['name']} scattered {keep.sum()} velocities: fp64, 10 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
     assert not s.tensor_grid
     s.step(10)
     o.step(10)
+    _compare(s, o)
+
+
+def test_octree_velocity_set_lifting_body_fp64():
+    """The X38-sized case's 4,548-point octree velocity set (two refinement
+    levels, cell volumes as weights) on a cut-down of its mesh (hexahedra
+    and prisms, wall and far field), against the oracle."""
+    ugks = _gpu()
+    c = cases.case_lifting_body(n=4, n_r=3, n_prism_columns=10)
+    _say(f"case {c['name']}: fp64, 5 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert s.tensor_grid
+    s.step(5)
+    o.step(5)
     _compare(s, o)
 
 
@@ -493,7 +527,7 @@ def test_2d_unstructured_velocity_set_fp64():
     c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(u[keep]), w=np.ascontiguousarray(w[keep]))
     _say(f"case {c['name']} disc of {keep.sum()} velocities: fp64, 20 steps")
     s, o = ugks.Solver(c), oracle.Oracle(c)
-    assert not s.tensor_grid
+    assert s.tensor_grid
     s.step(20)
     o.step(20)
     _compare(s, o)
