@@ -134,6 +134,26 @@ int ugks_step(ugks_t *h, int nsteps, double *residual_out);
 int ugks_step_async(ugks_t *h, int nsteps);
 int ugks_poll(ugks_t *h, int *done, double *residual_out);
 
+/* Batched stepping (continuous batching of many cases on one GPU): the
+ * steps of several handles run in the same launches -- one grid per kernel
+ * holds the cells (or faces) of every case end to end, each workgroup finds
+ * its case from a table of per-case offsets -- so small cases fill the GPU
+ * together and the launch count does not grow with the number of cases.
+ * ugks_batch_create makes a batch object for up to max_cases handles on
+ * `stream` (a hipStream_t).  ugks_batch_step enqueues nsteps steps of every
+ * handle in hs[0..n) and returns at once; each handle is then pending as
+ * after ugks_step_async (ugks_poll gives its residual and non-physical
+ * flag).  All handles must have been created on the batch's stream, have
+ * the same dimension, and have nothing outstanding (UGKS_ERR_ARG /
+ * UGKS_ERR_STATE otherwise; the text from ugks_batch_last_error).  A case's
+ * results are bitwise those of stepping it alone.  Handles may be created
+ * and destroyed between calls; only the handles passed in are touched. */
+typedef struct ugks_batch ugks_batch_t;
+int ugks_batch_create(int max_cases, void *stream, ugks_batch_t **out);
+int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int nsteps);
+const char *ugks_batch_last_error(const ugks_batch_t *b);
+void ugks_batch_destroy(ugks_batch_t *b);
+
 /* Device bytes ugks_create would allocate for these inputs (host-side
  * computation, no GPU needed): admission control against an HBM budget.
  * Returns 0 for invalid arguments. */

@@ -438,6 +438,27 @@ std::string nonphysical_message(const ugks_t *h, int stored)
     return "non-physical state (rho <= 0, T <= 0 or non-finite) at cell " + std::to_string(c);
 }
 
+// pinned copies of the flag and residual, and the completion event, for
+// asynchronous stepping (allocated on first use)
+void ensure_async(ugks_t *h)
+{
+    if (h->h_err) return;
+    hip_check(hipHostMalloc((void **)&h->h_err, 2 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&h->h_res, (h->dim + 2) * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    hip_check(hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming), "hipEventCreate");
+}
+
+// after the steps and the residual kernel: copy flag and residual to pinned
+// memory, mark the end, and leave the handle pending until ugks_poll
+void finish_async(ugks_t *h)
+{
+    hip_check(hipMemcpyAsync(h->h_err, h->err, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy flag");
+    hip_check(hipMemcpyAsync(h->h_res, h->res, (h->dim + 2) * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+              "copy residual");
+    hip_check(hipEventRecord(h->done_ev, h->stream), "hipEventRecord");
+    h->pending = 1;
+}
+
 void release(ugks_t *h)
 {
     if (h->h_err) (void)hipHostFree(h->h_err);
@@ -666,12 +687,7 @@ extern "C" int ugks_step_async(ugks_t *h, int nsteps)
     if (nsteps <= 0) return fail(h, Fail{UGKS_ERR_ARG, "nsteps must be positive"});
     if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "previous asynchronous steps not yet polled to completion"});
     try {
-        if (!h->h_err) {
-            hip_check(hipHostMalloc((void **)&h->h_err, 2 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
-            hip_check(hipHostMalloc((void **)&h->h_res, (h->dim + 2) * sizeof(double), hipHostMallocDefault),
-                      "hipHostMalloc");
-            hip_check(hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming), "hipEventCreate");
-        }
+        ensure_async(h);
         for (int s = 0; s < nsteps; ++s) {
             hip_check(launch_prologue(h->P, h->stream), "prologue launch");
             hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
@@ -680,11 +696,7 @@ extern "C" int ugks_step_async(ugks_t *h, int nsteps)
             h->stepped = 1;
         }
         hip_check(launch_residual(h->P, h->res, h->stream), "residual launch");
-        hip_check(hipMemcpyAsync(h->h_err, h->err, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy flag");
-        hip_check(hipMemcpyAsync(h->h_res, h->res, (h->dim + 2) * sizeof(double), hipMemcpyDeviceToHost, h->stream),
-                  "copy residual");
-        hip_check(hipEventRecord(h->done_ev, h->stream), "hipEventRecord");
-        h->pending = 1;
+        finish_async(h);
     } catch (const Fail &e) {
         return fail(h, e);
     }
@@ -887,3 +899,147 @@ extern "C" void ugks_destroy(ugks_t *h)
 }
 
 extern "C" const char *ugks_last_error(const ugks_t *h) { return h ? h->msg.c_str() : g_create_error.c_str(); }
+
+// ------------------------------------------------------------------------
+// batched stepping of several cases by the same launches
+// ------------------------------------------------------------------------
+struct ugks_batch {
+    hipStream_t stream = nullptr;
+    int max_cases = 0;
+    BatchItem *items = nullptr;  // device [max_cases]
+    int *off = nullptr;          // device: prologue offsets [2][max + 1], sweep offsets up to [max + max]
+    BatchItem *h_items = nullptr;  // pinned staging of the same
+    int *h_off = nullptr;
+    hipEvent_t up_ev = nullptr;    // recorded after the last uploads
+    int uploaded = 0;
+    std::string msg;
+};
+
+extern "C" int ugks_batch_create(int max_cases, void *stream, ugks_batch_t **out)
+{
+    if (!out || max_cases <= 0) return UGKS_ERR_ARG;
+    *out = nullptr;
+    ugks_batch_t *b = new (std::nothrow) ugks_batch_t();
+    if (!b) return UGKS_ERR_ALLOC;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->max_cases = max_cases;
+    const size_t noff = 4 * (size_t)max_cases + 3;
+    if (hipMalloc((void **)&b->items, sizeof(BatchItem) * max_cases) != hipSuccess ||
+        hipMalloc((void **)&b->off, sizeof(int) * noff) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_items, sizeof(BatchItem) * max_cases, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_off, sizeof(int) * noff, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->up_ev, hipEventDisableTiming) != hipSuccess) {
+        if (b->items) (void)hipFree(b->items);
+        if (b->off) (void)hipFree(b->off);
+        if (b->h_items) (void)hipHostFree(b->h_items);
+        if (b->h_off) (void)hipHostFree(b->h_off);
+        delete b;
+        g_create_error = "allocation of the batch descriptors failed";
+        return UGKS_ERR_ALLOC;
+    }
+    *out = b;
+    return UGKS_OK;
+}
+
+extern "C" int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int nsteps)
+{
+    if (!b) return UGKS_ERR_ARG;
+    auto bad = [&](int code, const std::string &m) {
+        b->msg = m;
+        return code;
+    };
+    if (!hs || n <= 0 || n > b->max_cases) return bad(UGKS_ERR_ARG, "n must be in 1..max_cases");
+    if (nsteps <= 0) return bad(UGKS_ERR_ARG, "nsteps must be positive");
+    const int D = hs[0] ? hs[0]->dim : 0;
+    for (int c = 0; c < n; ++c) {
+        const ugks_t *h = hs[c];
+        if (!h) return bad(UGKS_ERR_ARG, "NULL handle in the batch");
+        if (h->stream != b->stream) return bad(UGKS_ERR_ARG, "every handle of a batch must use the batch's stream");
+        if (h->dim != D) return bad(UGKS_ERR_ARG, "cases of one batch must have the same dimension");
+        if (h->pending) return bad(UGKS_ERR_STATE, "a handle still has asynchronous steps outstanding");
+        for (int e = 0; e < c; ++e)
+            if (hs[e] == h) return bad(UGKS_ERR_ARG, "a handle appears twice in the batch");
+    }
+    try {
+        for (int c = 0; c < n; ++c) ensure_async(hs[c]);
+        // cases grouped by the sweep's template (storage, tables, stage-1 place)
+        std::vector<int> order(n);
+        std::vector<long> key(n);
+        std::vector<size_t> lds(n);
+        for (int c = 0; c < n; ++c) {
+            bool s1l = false;
+            lds[c] = sweep_lds_bytes(hs[c]->P, &s1l);
+            key[c] = hs[c]->fstore * 4 + (hs[c]->P.ntab > 0 ? 2 : 0) + (s1l ? 1 : 0);
+            order[c] = c;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key[a] < key[c]; });
+        // the staging buffers are reused: wait until the previous uploads have left them
+        if (b->uploaded) hip_check(hipEventSynchronize(b->up_ev), "hipEventSynchronize");
+        BatchItem *items = b->h_items;
+        int *off = b->h_off;
+        std::fill(off, off + 4 * (size_t)n + 3, 0);
+        int *og = off, *of = og + (n + 1), *os = of + (n + 1);
+        for (int j = 0; j < n; ++j) {
+            const ugks_t *h = hs[order[j]];
+            items[j].p = h->P;
+            items[j].f[0] = h->f[0];
+            items[j].f[1] = h->f[1];
+            items[j].res = h->res;
+            items[j].cur = h->cur;
+            og[j + 1] = og[j] + (h->nc + 255) / 256;
+            of[j + 1] = of[j] + (h->nf + 127) / 128;
+        }
+        struct Group { int first, count, grid; size_t lds; long key; int *off_host; size_t off_at; };
+        std::vector<Group> groups;
+        size_t at = 0;
+        for (int j = 0; j < n;) {
+            int e = j;
+            size_t mx = 0;
+            while (e < n && key[order[e]] == key[order[j]]) mx = std::max(mx, lds[order[e++]]);
+            Group g{j, e - j, 0, mx, key[order[j]], os + at, (size_t)(os - off) + at};
+            g.off_host[0] = 0;
+            for (int q = 0; q < g.count; ++q) g.off_host[q + 1] = g.off_host[q] + sweep_grid(hs[order[j + q]]->nc);
+            g.grid = g.off_host[g.count];
+            at += g.count + 1;
+            groups.push_back(g);
+            j = e;
+        }
+        upload(b->items, items, sizeof(BatchItem) * n, b->stream);
+        upload(b->off, off, sizeof(int) * (4 * (size_t)n + 3), b->stream);
+        hip_check(hipEventRecord(b->up_ev, b->stream), "hipEventRecord");
+        b->uploaded = 1;
+        const int *dog = b->off, *dof = b->off + (n + 1);
+        for (int st = 0; st < nsteps; ++st) {
+            hip_check(launch_batch_prologue(b->items, n, dog, og[n], dof, of[n], D, b->stream), "batched prologue");
+            for (const Group &g : groups)
+                hip_check(launch_batch_sweep(b->items + g.first, g.count, b->off + g.off_at, g.grid, st, D,
+                                             (int)(g.key / 4), (g.key & 2) != 0, (g.key & 1) != 0, g.lds, b->stream),
+                          "batched sweep");
+        }
+        hip_check(launch_batch_residual(b->items, n, D, b->stream), "batched residual");
+        for (int c = 0; c < n; ++c) {
+            ugks_t *h = hs[c];
+            h->cur ^= (nsteps & 1);
+            h->nstep += nsteps;
+            h->stepped = 1;
+            finish_async(h);
+        }
+    } catch (const Fail &e) {
+        return bad(e.code, e.msg);
+    }
+    return UGKS_OK;
+}
+
+extern "C" const char *ugks_batch_last_error(const ugks_batch_t *b) { return b ? b->msg.c_str() : g_create_error.c_str(); }
+
+extern "C" void ugks_batch_destroy(ugks_batch_t *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(b->items);
+    (void)hipFree(b->off);
+    (void)hipHostFree(b->h_items);
+    (void)hipHostFree(b->h_off);
+    (void)hipEventDestroy(b->up_ev);
+    delete b;
+}

@@ -84,6 +84,29 @@ struct Params {
     int *err;          // [2]: flag, first bad cell
 };
 
+// One case of a batched launch (several cases advanced by the same kernels):
+// its parameters, its two f buffers and which one holds f when the batch
+// starts, and where its residual goes.
+struct BatchItem {
+    Params p;
+    const void *f[2];
+    double *res;
+    int cur;
+};
+
+// Dynamic LDS of the sweep for one case, and whether its stage-1 values
+// stay in LDS (s1l).
+size_t sweep_lds_bytes(const Params &p, bool *s1l);
+// Batched launches over items[0..n): off_* are the per-case first workgroup
+// (n + 1 entries, the last one the grid size) of each kernel's grid.
+hipError_t launch_batch_prologue(const BatchItem *items, int n, const int *off_grad, int grid_grad,
+                                 const int *off_face, int grid_face, int dim, hipStream_t s);
+hipError_t launch_batch_sweep(const BatchItem *items, int n, const int *off, int grid, int step, int dim, int fstore,
+                              bool tensor, bool s1l, size_t lds, hipStream_t s);
+hipError_t launch_batch_residual(const BatchItem *items, int n, int dim, hipStream_t s);
+// workgroups of the per-cell sweep grid for nc cells (a multiple of the XCD span)
+int sweep_grid(int nc);
+
 hipError_t launch_cfl(const Params &p, double *cell_dt, hipStream_t s);
 hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_t s);
 hipError_t launch_moments(const Params &p, const void *f, hipStream_t s);

@@ -396,10 +396,9 @@ __global__ __launch_bounds__(256) void k_moments(Params p, const FT *__restrict_
 // Alg. 1 line 2: limited gradients of the conservative variables
 // ------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(256) void k_cell_grad(Params p)
+__device__ __forceinline__ void cell_grad(const Params &p, int i)
 {
     constexpr int NW = D + 2, MF = Dim<D>::MF;
-    const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= p.nc) return;
     const CellGeo<D> &g = static_cast<const CellGeo<D> *>(p.cgeo)[i];
     double gr[NW][D], Wi[NW];
@@ -442,6 +441,12 @@ __global__ __launch_bounds__(256) void k_cell_grad(Params p)
     (void)MF;
     for (int m = 0; m < NW; ++m)
         for (int d = 0; d < D; ++d) p.gW[((size_t)i * NW + m) * D + d] = bad ? 0.0 : gr[m][d];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_cell_grad(Params p)
+{
+    cell_grad<D>(p, blockIdx.x * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -548,10 +553,9 @@ __device__ void time_integrals(double dt, double tau, double *c)
 }
 
 template <int D>
-__global__ __launch_bounds__(128) void k_face_eq(Params p)
+__device__ __forceinline__ void face_eq(const Params &p, int f)
 {
     constexpr int NW = D + 2;
-    const int f = blockIdx.x * 128 + threadIdx.x;
     if (f >= p.nf) return;
     const FaceGeo<D> &F = static_cast<const FaceGeo<D> *>(p.fgeo)[f];
     FaceEq<D> &e = static_cast<FaceEq<D> *>(p.feq)[f];
@@ -638,6 +642,12 @@ __global__ __launch_bounds__(128) void k_face_eq(Params p)
     time_integrals(p.dt, tau0, e.c);
 }
 
+template <int D>
+__global__ __launch_bounds__(128) void k_face_eq(Params p)
+{
+    face_eq<D>(p, blockIdx.x * 128 + threadIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // Alg. 1 lines 4-11, fused: the sweep over one cell's velocity slab
 // ------------------------------------------------------------------------
@@ -690,18 +700,23 @@ template <int D, bool TENSOR> struct Gauss {
 #endif
 // S1L: the stage-1 values of the cell are kept in LDS (when the slab fits
 // beside the tables without costing occupancy), else in f_out until stage 2.
+// Workgroups are dealt to the XCDs round-robin; hand each XCD runs of
+// UGKS_XCD_RUN consecutive cells, so that mesh neighbours (whose slabs every
+// workgroup re-reads) mostly meet in the same L2 while the runs, interleaved
+// over the XCDs, keep the load balanced.  b is the workgroup's index within
+// its case's grid, which starts at a multiple of UGKS_XCDS * UGKS_XCD_RUN.
+__device__ __forceinline__ int xcd_cell(int b)
+{
+    const int t = b / UGKS_XCDS;
+    return ((t / UGKS_XCD_RUN) * UGKS_XCDS + b % UGKS_XCDS) * UGKS_XCD_RUN + t % UGKS_XCD_RUN;
+}
+
 template <int D, typename FT, int BS, bool TENSOR, bool S1L>
-__global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
+__device__ __forceinline__ void sweep_cell(const Params &p, int i, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
     constexpr int NT = MF + 1;  // Gaussian tables: one per face slot, one for the cell
     extern __shared__ double smem[];
-    // Workgroups are dealt to the XCDs round-robin; hand each XCD runs of
-    // UGKS_XCD_RUN consecutive cells, so that mesh neighbours (whose slabs
-    // every workgroup re-reads) mostly meet in the same L2 while the runs,
-    // interleaved over the XCDs, keep the load balanced.
-    const int t = blockIdx.x / UGKS_XCDS;
-    const int i = ((t / UGKS_XCD_RUN) * UGKS_XCDS + blockIdx.x % UGKS_XCDS) * UGKS_XCD_RUN + t % UGKS_XCD_RUN;
     if (i >= p.nc) return;
     const int tid = threadIdx.x;
     const CellGeo<D> *cg = static_cast<const CellGeo<D> *>(p.cgeo);
@@ -985,6 +1000,12 @@ __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ f
     }
 }
 
+template <int D, typename FT, int BS, bool TENSOR, bool S1L>
+__global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
+{
+    sweep_cell<D, FT, BS, TENSOR, S1L>(p, xcd_cell(blockIdx.x), fin, fout);
+}
+
 // ------------------------------------------------------------------------
 // Surface quantities (Section 2.5): the macroscopic flux through each wall
 // face in a step, from the f that started the step.  One workgroup per wall
@@ -1072,7 +1093,7 @@ __global__ __launch_bounds__(BS) void k_wall_flux(Params p, const FT *__restrict
 // L2 norm over cells of the last step's change of W (fixed order)
 // ------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(256) void k_residual(Params p, double *out)
+__device__ __forceinline__ void residual(const Params &p, double *out)
 {
     constexpr int NW = D + 2;
     __shared__ double lds[4 * NW];
@@ -1083,6 +1104,63 @@ __global__ __launch_bounds__(256) void k_residual(Params p, double *out)
     block_reduce<256>(s, lds, OpAdd{});
     if (threadIdx.x == 0)
         for (int m = 0; m < NW; ++m) out[m] = sqrt(s[m]);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_residual(Params p, double *out)
+{
+    residual<D>(p, out);
+}
+
+// ------------------------------------------------------------------------
+// Batched launches: the cases of a batch are laid end to end in one grid;
+// off[c] is the first workgroup of case c.  Every workgroup finds its case
+// by a binary search over off (wave-uniform, scalar) and runs the same
+// per-cell or per-face code as the single-case kernels, on that case's
+// parameters and buffers, so a case's result does not depend on the batch.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int batch_case(const int *__restrict__ off, int n, int b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_cell_grad_batch(const BatchItem *__restrict__ items, const int *__restrict__ off,
+                                                         int n)
+{
+    const int c = batch_case(off, n, blockIdx.x);
+    cell_grad<D>(items[c].p, (blockIdx.x - off[c]) * 256 + threadIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(128) void k_face_eq_batch(const BatchItem *__restrict__ items, const int *__restrict__ off,
+                                                       int n)
+{
+    const int c = batch_case(off, n, blockIdx.x);
+    face_eq<D>(items[c].p, (blockIdx.x - off[c]) * 128 + threadIdx.x);
+}
+
+template <int D, typename FT, int BS, bool TENSOR, bool S1L>
+__global__ __launch_bounds__(BS) void k_sweep_batch(const BatchItem *__restrict__ items, const int *__restrict__ off,
+                                                    int n, int step)
+{
+    const int c = batch_case(off, n, blockIdx.x);
+    const BatchItem &it = items[c];
+    const int cur = (it.cur + step) & 1;
+    sweep_cell<D, FT, BS, TENSOR, S1L>(it.p, xcd_cell(blockIdx.x - off[c]), static_cast<const FT *>(it.f[cur]),
+                                       static_cast<FT *>(const_cast<void *>(it.f[1 - cur])));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_residual_batch(const BatchItem *__restrict__ items)
+{
+    residual<D>(items[blockIdx.x].p, items[blockIdx.x].res);
 }
 
 // ------------------------------------------------------------------------
@@ -1140,17 +1218,31 @@ hipError_t launch_prologue(const Params &p, hipStream_t s)
 // LDS a workgroup may take while four of them still fit on a CU (160 KB)
 constexpr size_t kLdsPerWorkgroup = 40 * 1024;
 
+size_t sweep_lds_bytes(const Params &p, bool *s1l)
+{
+    const int MF = p.dim == 2 ? Dim<2>::MF : Dim<3>::MF, NW = p.dim + 2, NC = p.dim == 2 ? Dim<2>::NC : Dim<3>::NC;
+    const int NRED = NW > 2 * MF ? NW : 2 * MF;
+    const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (size_t)p.ntab + (256 / 64) * (size_t)NRED);
+    const size_t fv = p.fstore == 2 ? 2 : (p.fstore == 1 ? 4 : 8);
+    const size_t slab = fv * NC * (size_t)p.nv;
+    *s1l = lds + slab <= kLdsPerWorkgroup;
+    return *s1l ? lds + slab : lds;
+}
+
+int sweep_grid(int nc)
+{
+    constexpr int span = UGKS_XCDS * UGKS_XCD_RUN;
+    return ((nc + span - 1) / span) * span;
+}
+
 template <int D, typename FT, int BS, bool TENSOR>
 void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
 {
-    constexpr int NW = D + 2, MF = Dim<D>::MF;
-    constexpr int NRED = (NW > 2 * MF) ? NW : 2 * MF;
-    const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (TENSOR ? p.ntab : 0) + (BS / 64) * NRED);
-    const size_t slab = sizeof(FT) * Dim<D>::NC * (size_t)p.nv;
-    constexpr int span = UGKS_XCDS * UGKS_XCD_RUN;
-    const unsigned grid = (unsigned)(((p.nc + span - 1) / span) * span);
-    if (lds + slab <= kLdsPerWorkgroup)
-        hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, true>), dim3(grid), dim3(BS), lds + slab, s, p,
+    bool s1l = false;
+    const size_t lds = sweep_lds_bytes(p, &s1l);
+    const unsigned grid = (unsigned)sweep_grid(p.nc);
+    if (s1l)
+        hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, true>), dim3(grid), dim3(BS), lds, s, p,
                            static_cast<const FT *>(fi), static_cast<FT *>(fo));
     else
         hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, false>), dim3(grid), dim3(BS), lds, s, p,
@@ -1188,6 +1280,55 @@ hipError_t launch_wall_flux(const Params &p, const void *f, const int *faces, in
     return p.fstore == 2 ? wall_flux_d<3, bf16s>(p, f, faces, n, out, s)
                          : (p.fstore ? wall_flux_d<3, float>(p, f, faces, n, out, s)
                                      : wall_flux_d<3, double>(p, f, faces, n, out, s));
+}
+
+hipError_t launch_batch_prologue(const BatchItem *items, int n, const int *off_grad, int grid_grad,
+                                 const int *off_face, int grid_face, int dim, hipStream_t s)
+{
+    if (dim == 2) {
+        hipLaunchKernelGGL(k_cell_grad_batch<2>, dim3(grid_grad), dim3(256), 0, s, items, off_grad, n);
+        hipLaunchKernelGGL(k_face_eq_batch<2>, dim3(grid_face), dim3(128), 0, s, items, off_face, n);
+    } else {
+        hipLaunchKernelGGL(k_cell_grad_batch<3>, dim3(grid_grad), dim3(256), 0, s, items, off_grad, n);
+        hipLaunchKernelGGL(k_face_eq_batch<3>, dim3(grid_face), dim3(128), 0, s, items, off_face, n);
+    }
+    return hipGetLastError();
+}
+
+template <int D, typename FT, bool TENSOR>
+void batch_sweep_t(const BatchItem *items, int n, const int *off, int grid, int step, bool s1l, size_t lds, hipStream_t s)
+{
+    if (s1l) hipLaunchKernelGGL((k_sweep_batch<D, FT, 256, TENSOR, true>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+    else hipLaunchKernelGGL((k_sweep_batch<D, FT, 256, TENSOR, false>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+}
+template <int D, typename FT>
+void batch_sweep_f(const BatchItem *items, int n, const int *off, int grid, int step, bool tensor, bool s1l, size_t lds,
+                   hipStream_t s)
+{
+    if (tensor) batch_sweep_t<D, FT, true>(items, n, off, grid, step, s1l, lds, s);
+    else batch_sweep_t<D, FT, false>(items, n, off, grid, step, s1l, lds, s);
+}
+template <int D>
+void batch_sweep_d(const BatchItem *items, int n, const int *off, int grid, int step, int fstore, bool tensor, bool s1l,
+                   size_t lds, hipStream_t s)
+{
+    if (fstore == 2) batch_sweep_f<D, bf16s>(items, n, off, grid, step, tensor, s1l, lds, s);
+    else if (fstore == 1) batch_sweep_f<D, float>(items, n, off, grid, step, tensor, s1l, lds, s);
+    else batch_sweep_f<D, double>(items, n, off, grid, step, tensor, s1l, lds, s);
+}
+hipError_t launch_batch_sweep(const BatchItem *items, int n, const int *off, int grid, int step, int dim, int fstore,
+                              bool tensor, bool s1l, size_t lds, hipStream_t s)
+{
+    if (dim == 2) batch_sweep_d<2>(items, n, off, grid, step, fstore, tensor, s1l, lds, s);
+    else batch_sweep_d<3>(items, n, off, grid, step, fstore, tensor, s1l, lds, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_residual(const BatchItem *items, int n, int dim, hipStream_t s)
+{
+    if (dim == 2) hipLaunchKernelGGL(k_residual_batch<2>, dim3(n), dim3(256), 0, s, items);
+    else hipLaunchKernelGGL(k_residual_batch<3>, dim3(n), dim3(256), 0, s, items);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s)

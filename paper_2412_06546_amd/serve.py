@@ -3,18 +3,23 @@
 Requests (a case, an arrival time, a residual tolerance and a step cap)
 arrive over time.  A request is admitted, in arrival order, as soon as a slot
 is free and its device footprint (ugks_footprint_estimate, the bytes
-ugks_create will allocate) fits in what is left of the HBM budget.  Every
-admitted case owns a HIP stream; the server keeps a batch of steps enqueued
-on each (ugks_step_async), so the kernels of all active cases overlap on the
-device, polls them without blocking (ugks_poll), retires a case when its
-residual -- the L2 change of W over one step, relative to that of its first
-step -- falls below the tolerance or the step cap is reached, frees its
-memory and admits the next.  Each case's computation is independent of the
-others (own buffers, own stream, deterministic kernels), so its result in the
-mix equals its result alone.
+ugks_create will allocate) fits in what is left of the HBM budget.  The
+server then advances the admitted cases in rounds: every case that is not
+running gets its next chunk of steps, and all of them are enqueued together
+as one batched step (ugks_batch_step: each kernel is launched once for all
+these cases, its grid holding their cells end to end), so small cases fill
+the GPU together and a request that arrives while others run joins the next
+round.  Cases are polled without blocking (ugks_poll); a case retires when
+its residual -- the L2 change of W over one step, relative to that of its
+first step -- falls below the tolerance, when it reaches its step cap or
+when it turns non-physical; its memory is freed and the next request
+admitted.  Each case keeps its own buffers and the kernels are
+deterministic, so its result in the mix equals its result alone.
 
-The backend is pluggable so that the scheduling logic can be exercised
-without a GPU (tests use a fake backend); GpuBackend is the product path.
+A backend without step_batch gets per-case asynchronous steps instead (each
+case on its own stream).  The backend is pluggable so that the scheduling
+logic can be exercised without a GPU (tests use fake backends); GpuBackend
+is the product path.
 """
 from __future__ import annotations
 
@@ -56,24 +61,33 @@ class Result:
 
 
 class GpuBackend:
-    """Runs each admitted case through the HIP library on its own stream."""
+    """Runs the admitted cases through the HIP library: all on one stream,
+    advanced by batched steps (batched=True), or each on its own stream."""
 
-    def __init__(self):
+    def __init__(self, batched: bool = True, max_cases: int = 64):
+        import ctypes
         import torch
         from . import ugks
         if not torch.cuda.is_available():
             raise RuntimeError("GpuBackend needs the GPU")
-        self._torch, self._ugks = torch, ugks
+        self._torch, self._ugks, self._ctypes = torch, ugks, ctypes
+        self.batched = batched
+        self._stream = torch.cuda.Stream()  # default priority
+        self._batch = ugks.Batch(max_cases, ctypes.c_void_p(self._stream.cuda_stream)) if batched else None
 
     def footprint(self, req: Request) -> int:
         return self._ugks.footprint_estimate(req.case, req.fstore)
 
     def start(self, req: Request):
-        import ctypes
-        stream = self._torch.cuda.Stream()  # default priority
-        s = self._ugks.Solver(req.case, fstore=req.fstore, stream=ctypes.c_void_p(stream.cuda_stream))
+        stream = self._stream if self.batched else self._torch.cuda.Stream()
+        s = self._ugks.Solver(req.case, fstore=req.fstore, stream=self._ctypes.c_void_p(stream.cuda_stream))
         s._serve_stream = stream            # keep the stream alive with the solver
         return s
+
+    def step_batch(self, solvers, n: int):
+        """n steps of every solver in batched launches (one per dimension)."""
+        for dim in sorted({s.dim for s in solvers}):
+            self._batch.step([s for s in solvers if s.dim == dim], n)
 
 
 class Server:
@@ -91,7 +105,9 @@ class Server:
     def run(self, requests: List[Request]) -> List[Result]:
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         results = {r.rid: Result(r.rid, r.arrival) for r in requests}
-        active = {}  # rid -> [request, solver, footprint, first residual, steps queued]
+        batched = hasattr(self.backend, "step_batch") and getattr(self.backend, "batched", True)
+        # rid -> [request, solver, footprint, first residual, steps queued, running]
+        active = {}
         used = 0
         t0 = self.clock()
         while pending or active:
@@ -114,8 +130,9 @@ class Server:
                 pending.pop(0)
                 try:
                     solver = self.backend.start(req)
-                    solver.step_async(1)   # the first step's residual normalises the rest
-                except Exception as exc:   # creation failure is reported, not fatal
+                    if not batched:
+                        solver.step_async(1)   # the first step's residual normalises the rest
+                except Exception as exc:       # creation failure is reported, not fatal
                     res.error = str(exc)
                     res.finished = self.clock() - t0
                     progressed = True
@@ -123,12 +140,14 @@ class Server:
                 used += fp
                 self.peak_used = max(self.peak_used, used)
                 res.admitted = now
-                active[req.rid] = [req, solver, fp, None, 1]
+                active[req.rid] = [req, solver, fp, None, 0 if batched else 1, not batched]
                 self.log.append((now, "admit", req.rid, used))
                 progressed = True
-            # progress of the active cases
+            # progress of the running cases
             for rid in list(active):
-                req, solver, fp, r0, queued = active[rid]
+                req, solver, fp, r0, queued, running = active[rid]
+                if not running:
+                    continue
                 res = results[rid]
                 try:
                     r = solver.poll()
@@ -137,6 +156,7 @@ class Server:
                 if r is None and not res.error:
                     continue
                 progressed = True
+                active[rid][5] = False
                 res.steps = queued
                 done = bool(res.error)
                 if not done:
@@ -155,10 +175,32 @@ class Server:
                     used -= fp
                     res.finished = self.clock() - t0
                     self.log.append((res.finished, "retire", rid, used))
-                else:
+                elif not batched:
                     n = min(self.chunk, req.max_steps - queued)
                     solver.step_async(n)
                     active[rid][4] = queued + n
+                    active[rid][5] = True
+            # batched: every case not running gets its next chunk, in one
+            # batched step per chunk length (1 for a case's first step)
+            if batched:
+                groups = {}
+                for rid, (req, solver, fp, r0, queued, running) in active.items():
+                    if not running:
+                        n = 1 if queued == 0 else min(self.chunk, req.max_steps - queued)
+                        groups.setdefault(n, []).append(rid)
+                for n, rids in sorted(groups.items()):
+                    try:
+                        self.backend.step_batch([active[rid][1] for rid in rids], n)
+                    except Exception as exc:
+                        for rid in rids:
+                            results[rid].error = str(exc)
+                            active[rid][5] = True     # retired by the next poll
+                        continue
+                    for rid in rids:
+                        active[rid][4] += n
+                        active[rid][5] = True
+                    self.log.append((self.clock() - t0, "batch", tuple(rids), n))
+                    progressed = True
             if not progressed:
                 self.idle()
         return [results[r.rid] for r in requests]

@@ -101,6 +101,14 @@ def load_library(path: str = LIB_PATH):
     L.ugks_cell_order.argtypes = [C.c_void_p, _ip]
     L.ugks_device_f.restype = C.c_void_p
     L.ugks_device_f.argtypes = [C.c_void_p]
+    L.ugks_batch_create.restype = C.c_int
+    L.ugks_batch_create.argtypes = [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
+    L.ugks_batch_step.restype = C.c_int
+    L.ugks_batch_step.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int]
+    L.ugks_batch_last_error.restype = C.c_char_p
+    L.ugks_batch_last_error.argtypes = [C.c_void_p]
+    L.ugks_batch_destroy.restype = None
+    L.ugks_batch_destroy.argtypes = [C.c_void_p]
     L.ugks_destroy.restype = None
     L.ugks_destroy.argtypes = [C.c_void_p]
     L.ugks_last_error.restype = C.c_char_p
@@ -284,3 +292,35 @@ class Solver:
         a = np.ascontiguousarray(f, dtype=np.float64)
         assert a.shape == (self.nc, self.ncomp, self.nv)
         _check(self._L, self._h, self._L.ugks_set_f(self._h, a.ctypes.data_as(_dp)))
+
+
+class Batch:
+    """Several cases advanced by the same launches (ugks_batch_*).  Every
+    Solver passed to step() must have been created on the batch's stream."""
+
+    def __init__(self, max_cases: int, stream=None):
+        L = self._L = load_library()
+        if stream is None:
+            stream = current_stream_handle()
+        self.stream = stream
+        h = C.c_void_p()
+        code = L.ugks_batch_create(int(max_cases), stream, C.byref(h))
+        if code != UGKS_OK:
+            raise UgksError(code, L.ugks_batch_last_error(None).decode())
+        self._h = h
+        self.max_cases = int(max_cases)
+
+    def step(self, solvers, nsteps: int):
+        """Enqueue nsteps steps of every solver; each is then pending (poll)."""
+        arr = (C.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
+        code = self._L.ugks_batch_step(self._h, arr, len(solvers), int(nsteps))
+        if code != UGKS_OK:
+            raise UgksError(code, self._L.ugks_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ugks_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

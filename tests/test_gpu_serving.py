@@ -45,16 +45,17 @@ def test_footprint_estimate_matches_allocation():
             s.close()
 
 
-def test_each_result_in_the_mix_equals_the_result_alone():
+@pytest.mark.parametrize("batched", [True, False])
+def test_each_result_in_the_mix_equals_the_result_alone(batched):
     ugks = _gpu()
-    from paper_2412_06546_amd.serve import Request, Server
+    from paper_2412_06546_amd.serve import GpuBackend, Request, Server
     cs = _mix()
     steps = 25
     fps = [ugks.footprint_estimate(c) for c in cs]
     budget = sorted(fps)[-1] + sorted(fps)[-2]           # at most about two at a time
     reqs = [Request(i, c, arrival=0.002 * i, tol=0.0, max_steps=steps) for i, c in enumerate(cs)]
     print(f"serving {len(cs)} cases, budget {budget} B", flush=True)
-    srv = Server(budget, max_active=4, chunk=7)
+    srv = Server(budget, max_active=4, chunk=7, backend=GpuBackend(batched=batched))
     res = srv.run(reqs)
     s = Server.summary(res)
     print(s, flush=True)
@@ -87,3 +88,51 @@ def test_async_steps_match_synchronous_steps():
     with pytest.raises(ugks.UgksError):
         b.step_async(1)
         b.step_async(1)    # a second batch before the first was polled
+
+
+def _scattered(c, seed):
+    u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+    rng = np.random.default_rng(seed)
+    c["vgrid"] = dict(dim=c["mesh"]["dim"], u=np.ascontiguousarray(u + rng.uniform(-1e-3, 1e-3, u.shape)),
+                      w=np.ascontiguousarray(w))
+    return c
+
+
+def test_batched_steps_are_bitwise_those_of_each_case_alone():
+    """Cases of different sizes, velocity sets (Cartesian tables, scattered
+    points), storage precisions and stage-1 placement (LDS or f_out) stepped
+    together by ugks_batch_step, twice, against each stepped alone."""
+    import ctypes
+    import torch
+    ugks = _gpu()
+    mix = [(cases.case_periodic_wave(nx=10, ny=6, nv=20, seed=1), "f64"),
+           (cases.case_cylinder_small(n_theta=32, n_r=10, nv=60), "f64"),     # slab too big for LDS
+           (cases.case_cylinder_small(n_theta=24, n_r=8, nv=24), "f32"),
+           (_scattered(cases.case_periodic_wave(nx=6, ny=6, nv=26, seed=4), 9), "f64"),     # too many axis values for tables
+           (cases.case_periodic_wave(nx=12, ny=4, nv=16, seed=5), "bf16")]
+    stream = torch.cuda.Stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    batch = ugks.Batch(8, sh)
+    solvers = [ugks.Solver(c, fstore=fs, stream=sh) for c, fs in mix]
+    assert not solvers[3].tensor_grid and solvers[0].tensor_grid
+    print(f"batch of {len(solvers)} cases", flush=True)
+    for n in (3, 4):
+        batch.step(solvers, n)
+        for s in solvers:
+            r = None
+            while r is None:
+                r = s.poll()
+    for (c, fs), s in zip(mix, solvers):
+        alone = ugks.Solver(c, fstore=fs)
+        alone.step(7)
+        Wa, qa = alone.macros()
+        Wb, qb = s.macros()
+        assert np.array_equal(Wa, Wb) and np.array_equal(qa, qb), c["name"]
+        assert np.array_equal(alone.f(), s.f()), c["name"]
+        assert s.step_count == 7
+        alone.close()
+    with pytest.raises(ugks.UgksError):
+        batch.step([solvers[0], ugks.Solver(mix[0][0])], 1)       # not on the batch's stream
+    for s in solvers:
+        s.close()
+    batch.close()

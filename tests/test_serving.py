@@ -119,3 +119,37 @@ def test_poisson_stream_recipe():
         assert du <= 0.7 + 1e-12 and n1 > 24
         assert 1500 <= len(r.case["mesh"]["cell_volume"]) <= 3500
         assert r.max_steps == 7 and "_ma" in r.case["name"]
+
+
+class FakeBatchBackend(FakeBackend):
+    """A backend with batched steps: every call advances several jobs."""
+
+    def __init__(self, *a):
+        super().__init__(*a)
+        self.calls = []
+
+    def step_batch(self, jobs, n):
+        self.calls.append((len(jobs), n))
+        for j in jobs:
+            j.step_async(n)
+
+
+def test_batched_rounds_respect_budget_and_step_counts():
+    clock = FakeClock()
+    n = 8
+    sizes = [30, 40, 25, 60, 35, 20, 45, 50]
+    be = FakeBatchBackend(clock, sizes, [0.01] * n, [0.5, 0.6, 0.7, 0.8, 0.5, 0.9, 0.6, 0.95])
+    reqs = [Request(i, None, arrival=0.01 * i, tol=1e-3, max_steps=40) for i in range(n)]
+    srv = Server(120, max_active=4, chunk=5, backend=be, clock=clock, idle=clock.tick)
+    res = srv.run(reqs)
+    assert all(not r.error for r in res)
+    assert srv.peak_used <= 120
+    assert max(k for k, _ in be.calls) > 1                      # several cases per batched step
+    assert all(nn == 1 or nn <= 5 for _, nn in be.calls)          # a first single step, then chunks
+    for r, d in zip(res, [0.5, 0.6, 0.7, 0.8, 0.5, 0.9, 0.6, 0.95]):
+        assert r.steps <= 40
+        assert r.converged == (d ** (r.steps - 1) <= 1e-3)
+        if not r.converged:
+            assert r.steps == 40
+    admitted = sorted(res, key=lambda r: r.admitted)
+    assert [r.rid for r in admitted] == sorted(r.rid for r in res)  # arrival order
