@@ -128,7 +128,8 @@ def run_serving(args):
     t0 = time.perf_counter()
     reqs = serve.poisson_stream(n_cases=args.serving, rate=4.0, max_steps=args.serving_steps, fstore="f32")
     print(f"# generated {len(reqs)} cases in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    srv = serve.Server(int(args.serving_budget_gb * 1e9), max_active=16, chunk=20)
+    backend = serve.GpuBackend(batched=args.serving_mode == "batched")
+    srv = serve.Server(int(args.serving_budget_gb * 1e9), max_active=16, chunk=20, backend=backend)
     res = srv.run(reqs)
     summ = serve.Server.summary(res)
     for r in res:
@@ -138,6 +139,8 @@ def run_serving(args):
             "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
             "config": {"workload": f"Poisson stream (4/s) of {len(reqs)} cylinder cases, 2k-50k triangles, "
                                    f"20^2-64^2 velocities, tol 1e-6, cap {args.serving_steps} steps, f32",
+                       "mode": args.serving_mode + (" (one batched launch per kernel per round)" if
+                                                    args.serving_mode == "batched" else " (a stream per case)"),
                        "budget_bytes": srv.budget, "peak_bytes": srv.peak_used},
             "serving": summ}
     print(json.dumps(line), flush=True)
@@ -159,6 +162,7 @@ def main():
                     help="instead: serve a Poisson stream (4/s) of N cylinder cases and report p50/p99")
     ap.add_argument("--serving-steps", type=int, default=400, help="step cap per served case")
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serving-mode", choices=["batched", "streams"], default="batched")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_moments(Params p, const FT *__restrict_
 // Alg. 1 line 2: limited gradients of the conservative variables
 // ------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ void cell_grad(const Params &p, int i)
+__device__ __forceinline__ void cell_grad(const Params p, int i)
 {
     constexpr int NW = D + 2, MF = Dim<D>::MF;
     if (i >= p.nc) return;
@@ -553,7 +553,7 @@ __device__ void time_integrals(double dt, double tau, double *c)
 }
 
 template <int D>
-__device__ __forceinline__ void face_eq(const Params &p, int f)
+__device__ __forceinline__ void face_eq(const Params p, int f)
 {
     constexpr int NW = D + 2;
     if (f >= p.nf) return;
@@ -712,7 +712,7 @@ __device__ __forceinline__ int xcd_cell(int b)
 }
 
 template <int D, typename FT, int BS, bool TENSOR, bool S1L>
-__device__ __forceinline__ void sweep_cell(const Params &p, int i, const FT *__restrict__ fin, FT *__restrict__ fout)
+__device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
     constexpr int NT = MF + 1;  // Gaussian tables: one per face slot, one for the cell
@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(BS) void k_wall_flux(Params p, const FT *__restrict
 // L2 norm over cells of the last step's change of W (fixed order)
 // ------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ void residual(const Params &p, double *out)
+__device__ __forceinline__ void residual(const Params p, double *out)
 {
     constexpr int NW = D + 2;
     __shared__ double lds[4 * NW];
@@ -1119,6 +1119,15 @@ __global__ __launch_bounds__(256) void k_residual(Params p, double *out)
 // per-cell or per-face code as the single-case kernels, on that case's
 // parameters and buffers, so a case's result does not depend on the batch.
 // ------------------------------------------------------------------------
+// The descriptors are read-only for a launch: they are read through the
+// constant address space, as kernel arguments are, so that the compiler may
+// reload a case's parameters instead of holding them all in registers.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) BatchItem *ConstItems;
+#else
+typedef const BatchItem *ConstItems;  // the host pass only parses the kernels
+#endif
+
 __device__ __forceinline__ int batch_case(const int *__restrict__ off, int n, int b)
 {
     int lo = 0, hi = n - 1;
@@ -1135,7 +1144,7 @@ __global__ __launch_bounds__(256) void k_cell_grad_batch(const BatchItem *__rest
                                                          int n)
 {
     const int c = batch_case(off, n, blockIdx.x);
-    cell_grad<D>(items[c].p, (blockIdx.x - off[c]) * 256 + threadIdx.x);
+    cell_grad<D>(((ConstItems)items)[c].p, (blockIdx.x - off[c]) * 256 + threadIdx.x);
 }
 
 template <int D>
@@ -1143,7 +1152,7 @@ __global__ __launch_bounds__(128) void k_face_eq_batch(const BatchItem *__restri
                                                        int n)
 {
     const int c = batch_case(off, n, blockIdx.x);
-    face_eq<D>(items[c].p, (blockIdx.x - off[c]) * 128 + threadIdx.x);
+    face_eq<D>(((ConstItems)items)[c].p, (blockIdx.x - off[c]) * 128 + threadIdx.x);
 }
 
 template <int D, typename FT, int BS, bool TENSOR, bool S1L>
@@ -1151,16 +1160,17 @@ __global__ __launch_bounds__(BS) void k_sweep_batch(const BatchItem *__restrict_
                                                     int n, int step)
 {
     const int c = batch_case(off, n, blockIdx.x);
-    const BatchItem &it = items[c];
-    const int cur = (it.cur + step) & 1;
-    sweep_cell<D, FT, BS, TENSOR, S1L>(it.p, xcd_cell(blockIdx.x - off[c]), static_cast<const FT *>(it.f[cur]),
-                                       static_cast<FT *>(const_cast<void *>(it.f[1 - cur])));
+    ConstItems ci = (ConstItems)(items);
+    const int cur = (ci[c].cur + step) & 1;
+    sweep_cell<D, FT, BS, TENSOR, S1L>(ci[c].p, xcd_cell(blockIdx.x - off[c]), static_cast<const FT *>(ci[c].f[cur]),
+                                       static_cast<FT *>(const_cast<void *>(ci[c].f[1 - cur])));
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_residual_batch(const BatchItem *__restrict__ items)
 {
-    residual<D>(items[blockIdx.x].p, items[blockIdx.x].res);
+    ConstItems ci = (ConstItems)(items);
+    residual<D>(ci[blockIdx.x].p, ci[blockIdx.x].res);
 }
 
 // ------------------------------------------------------------------------
