@@ -161,16 +161,38 @@ __device__ __forceinline__ double rcp_nr(double x)
     return r;
 }
 
+// The stencil of cell c at velocity k (its own value, then its face
+// neighbours', zero for boundary slots: every load is issued, none behind a
+// branch), and the limited slope built from it; limited_slope = both.  The
+// sweep loads the next velocity's stencil while it works on the current one.
 template <int D, typename FT>
-__device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const FT *__restrict__ f, int nv, int k,
-                                              int limiter, double (&fc)[Dim<D>::NC], double (&gr)[Dim<D>::NC][D])
+__device__ __forceinline__ void load_stencil(const CellGeo<D> &g, int c, const FT *__restrict__ f, int nv, int k,
+                                             double (&v0)[Dim<D>::NC], double (&vn)[Dim<D>::MF][Dim<D>::NC])
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
+    const FT *fcell = f + (size_t)c * NC * nv;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) v0[m] = to_f64(fcell[m * nv + k]);
+    const int nf = g.nf;
+#pragma unroll
+    for (int j = 0; j < MF; ++j) {
+        const int n = j < nf ? g.nb[j] : -1;
+        const FT *fnb = f + (size_t)(n < 0 ? c : n) * NC * nv;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) vn[j][m] = n < 0 ? 0.0 : to_f64(fnb[m * nv + k]);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void slope_from(const CellGeo<D> &g, int limiter, const double (&v0)[Dim<D>::NC],
+                                           const double (&vn)[Dim<D>::MF][Dim<D>::NC], double (&fc)[Dim<D>::NC],
+                                           double (&gr)[Dim<D>::NC][D])
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
     double fmx[NC], fmn[NC];
-    const FT *fcell = f + (size_t)c * NC * nv;  // wave-uniform base of the cell's slab
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-        fc[m] = to_f64(fcell[m * nv + k]);
+        fc[m] = v0[m];
         fmx[m] = fmn[m] = fc[m];
 #pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
@@ -181,10 +203,9 @@ __device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const 
         if (j >= nf) break;
         const int n = g.nb[j];
         if (n < 0) continue;
-        const FT *fnb = f + (size_t)n * NC * nv;
 #pragma unroll
         for (int m = 0; m < NC; ++m) {
-            const double fj = to_f64(fnb[m * nv + k]);
+            const double fj = vn[j][m];
             const double df = fj - fc[m];
 #pragma unroll
             for (int d = 0; d < D; ++d) gr[m][d] = fma(g.lsq[j][d], df, gr[m][d]);
@@ -218,6 +239,15 @@ __device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const 
 #pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] *= phi;
     }
+}
+
+template <int D, typename FT>
+__device__ __forceinline__ void limited_slope(const CellGeo<D> &g, int c, const FT *__restrict__ f, int nv, int k,
+                                              int limiter, double (&fc)[Dim<D>::NC], double (&gr)[Dim<D>::NC][D])
+{
+    double v0[Dim<D>::NC], vn[Dim<D>::MF][Dim<D>::NC];
+    load_stencil<D, FT>(g, c, f, nv, k, v0, vn);
+    slope_from<D>(g, limiter, v0, vn, fc, gr);
 }
 
 // Shakhov equilibrium f+ = H + H+ (and B + B+) at u, given the reduced
@@ -711,7 +741,9 @@ __device__ __forceinline__ int xcd_cell(int b)
     return ((t / UGKS_XCD_RUN) * UGKS_XCDS + b % UGKS_XCDS) * UGKS_XCD_RUN + t % UGKS_XCD_RUN;
 }
 
-template <int D, typename FT, int BS, bool TENSOR, bool S1L>
+// PF: the own cell's stencil of the next velocity is loaded one iteration
+// ahead (20 more registers: used where they fit in the four-wave budget).
+template <int D, typename FT, int BS, bool TENSOR, bool S1L, bool PF>
 __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
@@ -825,7 +857,19 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     double mom[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+    double pv0[NC], pvn[MF][NC];
+    if (PF && tid < nv) load_stencil<D, FT>(gi, i, fin, nv, tid, pv0, pvn);
     for (int k = tid; k < nv; k += BS) {
+        double v0[NC], vn[MF][NC];
+        if constexpr (PF) {
+#pragma unroll
+            for (int m = 0; m < NC; ++m) {
+                v0[m] = pv0[m];
+#pragma unroll
+                for (int j = 0; j < MF; ++j) vn[j][m] = pvn[j][m];
+            }
+            if (k + BS < nv) load_stencil<D, FT>(gi, i, fin, nv, k + BS, pv0, pvn);
+        }
         double u[D], u2 = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -834,7 +878,8 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
         }
         const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
         double fi[NC], gri[NC][D];
-        limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+        if constexpr (PF) slope_from<D>(gi, p.limiter, v0, vn, fi, gri);
+        else limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
         double out[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) out[c] = 0.0;
@@ -1003,7 +1048,15 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
 template <int D, typename FT, int BS, bool TENSOR, bool S1L>
 __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
-    sweep_cell<D, FT, BS, TENSOR, S1L>(p, xcd_cell(blockIdx.x), fin, fout);
+    sweep_cell<D, FT, BS, TENSOR, S1L, false>(p, xcd_cell(blockIdx.x), fin, fout);
+}
+
+// Cartesian (tabulated) velocity sets: the same with the stencil prefetch,
+// held to four waves per SIMD.
+template <int D, typename FT, int BS, bool S1L>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep_pf(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
+{
+    sweep_cell<D, FT, BS, true, S1L, true>(p, xcd_cell(blockIdx.x), fin, fout);
 }
 
 // ------------------------------------------------------------------------
@@ -1156,14 +1209,27 @@ __global__ __launch_bounds__(128) void k_face_eq_batch(const BatchItem *__restri
 }
 
 template <int D, typename FT, int BS, bool TENSOR, bool S1L>
-__global__ __launch_bounds__(BS) void k_sweep_batch(const BatchItem *__restrict__ items, const int *__restrict__ off,
-                                                    int n, int step)
+__device__ __forceinline__ void sweep_batch(const BatchItem *__restrict__ items, const int *__restrict__ off, int n,
+                                            int step)
 {
     const int c = batch_case(off, n, blockIdx.x);
     ConstItems ci = (ConstItems)(items);
     const int cur = (ci[c].cur + step) & 1;
-    sweep_cell<D, FT, BS, TENSOR, S1L>(ci[c].p, xcd_cell(blockIdx.x - off[c]), static_cast<const FT *>(ci[c].f[cur]),
-                                       static_cast<FT *>(const_cast<void *>(ci[c].f[1 - cur])));
+    sweep_cell<D, FT, BS, TENSOR, S1L, TENSOR>(ci[c].p, xcd_cell(blockIdx.x - off[c]),
+                                               static_cast<const FT *>(ci[c].f[cur]),
+                                               static_cast<FT *>(const_cast<void *>(ci[c].f[1 - cur])));
+}
+template <int D, typename FT, int BS, bool S1L>
+__global__ __launch_bounds__(BS) void k_sweep_batch(const BatchItem *__restrict__ items, const int *__restrict__ off,
+                                                    int n, int step)
+{
+    sweep_batch<D, FT, BS, false, S1L>(items, off, n, step);
+}
+template <int D, typename FT, int BS, bool S1L>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep_batch_pf(
+    const BatchItem *__restrict__ items, const int *__restrict__ off, int n, int step)
+{
+    sweep_batch<D, FT, BS, true, S1L>(items, off, n, step);
 }
 
 template <int D>
@@ -1251,12 +1317,15 @@ void sweep_launch(const Params &p, const void *fi, void *fo, hipStream_t s)
     bool s1l = false;
     const size_t lds = sweep_lds_bytes(p, &s1l);
     const unsigned grid = (unsigned)sweep_grid(p.nc);
-    if (s1l)
-        hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, true>), dim3(grid), dim3(BS), lds, s, p,
-                           static_cast<const FT *>(fi), static_cast<FT *>(fo));
-    else
-        hipLaunchKernelGGL((k_sweep<D, FT, BS, TENSOR, false>), dim3(grid), dim3(BS), lds, s, p,
-                           static_cast<const FT *>(fi), static_cast<FT *>(fo));
+    const FT *in = static_cast<const FT *>(fi);
+    FT *out = static_cast<FT *>(fo);
+    if constexpr (TENSOR) {
+        if (s1l) hipLaunchKernelGGL((k_sweep_pf<D, FT, BS, true>), dim3(grid), dim3(BS), lds, s, p, in, out);
+        else hipLaunchKernelGGL((k_sweep_pf<D, FT, BS, false>), dim3(grid), dim3(BS), lds, s, p, in, out);
+    } else {
+        if (s1l) hipLaunchKernelGGL((k_sweep<D, FT, BS, false, true>), dim3(grid), dim3(BS), lds, s, p, in, out);
+        else hipLaunchKernelGGL((k_sweep<D, FT, BS, false, false>), dim3(grid), dim3(BS), lds, s, p, in, out);
+    }
 }
 
 template <int D, typename FT> hipError_t sweep_d(const Params &p, const void *fi, void *fo, hipStream_t s)
@@ -1308,8 +1377,13 @@ hipError_t launch_batch_prologue(const BatchItem *items, int n, const int *off_g
 template <int D, typename FT, bool TENSOR>
 void batch_sweep_t(const BatchItem *items, int n, const int *off, int grid, int step, bool s1l, size_t lds, hipStream_t s)
 {
-    if (s1l) hipLaunchKernelGGL((k_sweep_batch<D, FT, 256, TENSOR, true>), dim3(grid), dim3(256), lds, s, items, off, n, step);
-    else hipLaunchKernelGGL((k_sweep_batch<D, FT, 256, TENSOR, false>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+    if constexpr (TENSOR) {
+        if (s1l) hipLaunchKernelGGL((k_sweep_batch_pf<D, FT, 256, true>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+        else hipLaunchKernelGGL((k_sweep_batch_pf<D, FT, 256, false>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+    } else {
+        if (s1l) hipLaunchKernelGGL((k_sweep_batch<D, FT, 256, true>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+        else hipLaunchKernelGGL((k_sweep_batch<D, FT, 256, false>), dim3(grid), dim3(256), lds, s, items, off, n, step);
+    }
 }
 template <int D, typename FT>
 void batch_sweep_f(const BatchItem *items, int n, const int *off, int grid, int step, bool tensor, bool s1l, size_t lds,
