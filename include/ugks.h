@@ -171,6 +171,19 @@ int ugks_get_f(ugks_t *h, double *f_out);
  * discrete moments (checkpoint restart or a non-equilibrium start). */
 int ugks_set_f(ugks_t *h, const double *f_in);
 
+/* Checkpoint and restart, exact: the state blob holds W, q, f in its
+ * storage precision and the library's order, and the step count.
+ * ugks_state_bytes gives its size; ugks_get_state writes it to a host
+ * buffer of at least that size; ugks_set_state restores it into a handle
+ * created from the same inputs (sizes, storage and the library's cell and
+ * velocity orders are checked: UGKS_ERR_ARG otherwise), after which the
+ * steps continue bit for bit as the saved run would have.  Unlike
+ * ugks_set_f, W and q are restored, not recomputed as moments of f.  The
+ * blob is in host byte order. */
+size_t ugks_state_bytes(const ugks_t *h);
+int ugks_get_state(ugks_t *h, void *buf, size_t bytes);
+int ugks_set_state(ugks_t *h, const void *buf, size_t bytes);
+
 double ugks_dt(const ugks_t *h);            /* time step, or -1 for a NULL handle */
 int ugks_n_comp(const ugks_t *h);           /* stored components per (cell, velocity) */
 long ugks_step_count(const ugks_t *h);      /* steps taken since creation */

@@ -829,6 +829,102 @@ extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
     return UGKS_OK;
 }
 
+// ------------------------------------------------------------------------
+// checkpoint: the exact state of a handle (W, q, f in its storage precision
+// and the library's order, step count), restorable into a handle created
+// from the same inputs
+// ------------------------------------------------------------------------
+namespace {
+struct StateHeader {
+    char magic[8];  // "UGKSST01"
+    int dim, nc, nv, ncomp, fstore, pad;
+    long nstep;
+    unsigned long long order_hash;  // of the library's cell and velocity orders
+};
+
+unsigned long long order_hash(const ugks_t *h)
+{
+    unsigned long long x = 1469598103934665603ull;  // FNV-1a over both permutations
+    auto mix = [&](int v) {
+        for (int b = 0; b < 4; ++b) {
+            x ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+            x *= 1099511628211ull;
+        }
+    };
+    for (int v : h->cell_of) mix(v);
+    for (int v : h->perm) mix(v);
+    return x;
+}
+
+size_t state_bytes(const ugks_t *h)
+{
+    const size_t nc = h->nc, NW = h->dim + 2;
+    return sizeof(StateHeader) + sizeof(double) * nc * (NW + h->dim) + nc * h->ncomp * h->nv * fvalue_bytes(h->fstore);
+}
+}  // namespace
+
+extern "C" size_t ugks_state_bytes(const ugks_t *h) { return h ? state_bytes(h) : 0; }
+
+extern "C" int ugks_get_state(ugks_t *h, void *buf, size_t bytes)
+{
+    if (!h || !buf) return UGKS_ERR_ARG;
+    if (bytes < state_bytes(h)) return fail(h, Fail{UGKS_ERR_ARG, "state buffer too small (see ugks_state_bytes)"});
+    if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
+    try {
+        StateHeader hd{};
+        std::memcpy(hd.magic, "UGKSST01", 8);
+        hd.dim = h->dim;
+        hd.nc = h->nc;
+        hd.nv = h->nv;
+        hd.ncomp = h->ncomp;
+        hd.fstore = h->fstore;
+        hd.nstep = h->nstep;
+        hd.order_hash = order_hash(h);
+        char *p = static_cast<char *>(buf);
+        std::memcpy(p, &hd, sizeof(hd));
+        p += sizeof(hd);
+        const size_t nW = sizeof(double) * h->nc * (h->dim + 2), nq = sizeof(double) * h->nc * h->dim;
+        const size_t nf = (size_t)h->nc * h->ncomp * h->nv * fvalue_bytes(h->fstore);
+        hip_check(hipMemcpyAsync(p, h->W, nW, hipMemcpyDeviceToHost, h->stream), "copy W");
+        hip_check(hipMemcpyAsync(p + nW, h->q, nq, hipMemcpyDeviceToHost, h->stream), "copy q");
+        hip_check(hipMemcpyAsync(p + nW + nq, h->f[h->cur], nf, hipMemcpyDeviceToHost, h->stream), "copy f");
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_set_state(ugks_t *h, const void *buf, size_t bytes)
+{
+    if (!h || !buf) return UGKS_ERR_ARG;
+    if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
+    if (bytes < sizeof(StateHeader)) return fail(h, Fail{UGKS_ERR_ARG, "state buffer too small"});
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, "UGKSST01", 8) != 0) return fail(h, Fail{UGKS_ERR_ARG, "not a UGKS state"});
+    if (hd.dim != h->dim || hd.nc != h->nc || hd.nv != h->nv || hd.ncomp != h->ncomp || hd.fstore != h->fstore ||
+        hd.order_hash != order_hash(h))
+        return fail(h, Fail{UGKS_ERR_ARG, "state of a different case (sizes, storage or orders differ)"});
+    if (bytes < state_bytes(h)) return fail(h, Fail{UGKS_ERR_ARG, "state buffer truncated"});
+    try {
+        const char *p = static_cast<const char *>(buf) + sizeof(hd);
+        const size_t nW = sizeof(double) * h->nc * (h->dim + 2), nq = sizeof(double) * h->nc * h->dim;
+        const size_t nf = (size_t)h->nc * h->ncomp * h->nv * fvalue_bytes(h->fstore);
+        upload(h->W, p, nW, h->stream);
+        upload(h->q, p + nW, nq, h->stream);
+        upload(h->f[h->cur], p + nW + nq, nf, h->stream);
+        const int err0[2] = {0, 0x7fffffff};
+        upload(h->err, err0, sizeof(err0), h->stream);
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        h->nstep = hd.nstep;
+        h->stepped = 0;
+    } catch (const Fail &e) {
+        return fail(h, e);
+    }
+    return UGKS_OK;
+}
+
 extern "C" int ugks_n_wall_faces(const ugks_t *h) { return h ? h->n_wallf : 0; }
 
 extern "C" int ugks_wall_flux(ugks_t *h, double *out)

@@ -93,6 +93,12 @@ def load_library(path: str = LIB_PATH):
     L.ugks_profile_read.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_long)]
     L.ugks_velocity_order.restype = C.c_int
     L.ugks_velocity_order.argtypes = [C.c_void_p, _ip]
+    L.ugks_state_bytes.restype = C.c_size_t
+    L.ugks_state_bytes.argtypes = [C.c_void_p]
+    L.ugks_get_state.restype = C.c_int
+    L.ugks_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    L.ugks_set_state.restype = C.c_int
+    L.ugks_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     L.ugks_n_wall_faces.restype = C.c_int
     L.ugks_n_wall_faces.argtypes = [C.c_void_p]
     L.ugks_wall_flux.restype = C.c_int
@@ -249,6 +255,18 @@ class Solver:
         perm = np.zeros(self.nv, dtype=np.int32)
         _check(self._L, self._h, self._L.ugks_velocity_order(self._h, perm.ctypes.data_as(_ip)))
         return perm
+
+    def get_state(self) -> bytes:
+        """Exact checkpoint (W, q, f in storage precision, step count)."""
+        n = self._L.ugks_state_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        _check(self._L, self._h, self._L.ugks_get_state(self._h, buf, n))
+        return buf.raw
+
+    def set_state(self, state: bytes):
+        """Restore a checkpoint taken from a solver of the same case."""
+        buf = C.create_string_buffer(bytes(state), len(state))
+        _check(self._L, self._h, self._L.ugks_set_state(self._h, buf, len(state)))
 
     def wall_flux(self):
         """Macroscopic flux through every wall face in the last step, per unit

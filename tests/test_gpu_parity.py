@@ -193,6 +193,32 @@ def test_set_f_restart_is_bitwise():
     assert np.array_equal(b.f(), c2.f())
 
 
+@pytest.mark.parametrize("fstore", ["f64", "f32", "bf16"])
+def test_checkpoint_restart_is_exact(fstore):
+    """ugks_get_state / ugks_set_state: a run saved after 6 steps and
+    restarted in a fresh handle continues bit for bit as the run that was
+    never interrupted (W, q and f); a state of another case is refused."""
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    _say(f"case {c['name']}: {fstore} checkpoint after 6 of 12 steps")
+    a = ugks.Solver(c, fstore=fstore)
+    a.step(6)
+    st = a.get_state()
+    a.step(6)
+    b = ugks.Solver(c, fstore=fstore)
+    b.set_state(st)
+    assert b.step_count == 6
+    b.step(6)
+    Wa, qa = a.macros()
+    Wb, qb = b.macros()
+    assert np.array_equal(Wa, Wb) and np.array_equal(qa, qb)
+    assert np.array_equal(a.f(), b.f())
+    other = ugks.Solver(cases.case_cylinder_small(n_theta=24, n_r=8, nv=20), fstore=fstore)
+    with pytest.raises(ugks.UgksError) as e:
+        other.set_state(st)
+    assert e.value.code == ugks.UGKS_ERR_ARG
+
+
 def test_fp32_storage_error_is_small():
     ugks = _gpu()
     c = cases.case_cylinder_small()
