@@ -81,8 +81,11 @@ typedef struct {
 } ugks_mesh_t;
 
 /* Discrete velocity space (Section 2.3): points u_k with weights V_k, so that
- * int Q du = sum_k Q_k V_k.  A Cartesian (tensor-product) point set, with the
- * last axis contiguous, is detected and uses separable exponentials. */
+ * int Q du = sum_k Q_k V_k -- a Cartesian grid with trapezoid weights, or an
+ * unstructured velocity mesh (cell centres, cell volumes as weights).  When
+ * the points take at most 1023 distinct values per axis (Cartesian, octree
+ * or ball-restricted sets) the Gaussians are tabulated per axis in LDS
+ * (ugks_is_tensor_grid); otherwise they are evaluated directly. */
 typedef struct {
     int dim;           /* must equal the mesh's */
     int n_vel;
