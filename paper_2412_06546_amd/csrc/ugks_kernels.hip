@@ -161,10 +161,19 @@ __device__ __forceinline__ double rcp_nr(double x)
     return r;
 }
 
-// The stencil of cell c at velocity k (its own value, then its face
-// neighbours', zero for boundary slots: every load is issued, none behind a
-// branch), and the limited slope built from it; limited_slope = both.  The
-// sweep loads the next velocity's stencil while it works on the current one.
+// The stencil of cell c at velocity k: its own value, then one value per face
+// slot.  A slot without a neighbour (boundary face, or no face: nb = -1) reads
+// the cell's own value, whose difference from it is exactly zero and whose
+// least-squares weight is zero, so every load is issued and none sits behind a
+// branch.  Loads take a uniform base and a 32-bit byte offset (a cell's slab
+// is far below 4 GiB).  The sweep loads the next velocity's stencil while it
+// works on the current one; limited_slope = load_stencil + slope_from.
+template <typename FT>
+__device__ __forceinline__ double load_at(const FT *__restrict__ base, unsigned idx)
+{
+    return to_f64(*reinterpret_cast<const FT *>(reinterpret_cast<const char *>(base) + idx * (unsigned)sizeof(FT)));
+}
+
 template <int D, typename FT>
 __device__ __forceinline__ void load_stencil(const CellGeo<D> &g, int c, const FT *__restrict__ f, int nv, int k,
                                              double (&v0)[Dim<D>::NC], double (&vn)[Dim<D>::MF][Dim<D>::NC])
@@ -172,14 +181,13 @@ __device__ __forceinline__ void load_stencil(const CellGeo<D> &g, int c, const F
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
     const FT *fcell = f + (size_t)c * NC * nv;
 #pragma unroll
-    for (int m = 0; m < NC; ++m) v0[m] = to_f64(fcell[m * nv + k]);
-    const int nf = g.nf;
+    for (int m = 0; m < NC; ++m) v0[m] = load_at(fcell, (unsigned)(m * nv + k));
 #pragma unroll
     for (int j = 0; j < MF; ++j) {
-        const int n = j < nf ? g.nb[j] : -1;
+        const int n = g.nb[j];
         const FT *fnb = f + (size_t)(n < 0 ? c : n) * NC * nv;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) vn[j][m] = n < 0 ? 0.0 : to_f64(fnb[m * nv + k]);
+        for (int m = 0; m < NC; ++m) vn[j][m] = load_at(fnb, (unsigned)(m * nv + k));
     }
 }
 
@@ -189,28 +197,28 @@ __device__ __forceinline__ void slope_from(const CellGeo<D> &g, int limiter, con
                                            double (&gr)[Dim<D>::NC][D])
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
-    double fmx[NC], fmn[NC];
+    // extremes of the differences f_j - f_i (0 for the cell itself): equal to
+    // max_j f_j - f_i and min_j f_j - f_i, as rounding is monotone
+    double up[NC], dn[NC];
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
         fc[m] = v0[m];
-        fmx[m] = fmn[m] = fc[m];
+        up[m] = dn[m] = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
     }
     const int nf = g.nf;
+    // a cell has at least D + 1 faces; the slots beyond are skipped
 #pragma unroll
     for (int j = 0; j < MF; ++j) {
-        if (j >= nf) break;
-        const int n = g.nb[j];
-        if (n < 0) continue;
+        if (j > D && j >= nf) break;
 #pragma unroll
         for (int m = 0; m < NC; ++m) {
-            const double fj = vn[j][m];
-            const double df = fj - fc[m];
+            const double df = vn[j][m] - fc[m];
 #pragma unroll
             for (int d = 0; d < D; ++d) gr[m][d] = fma(g.lsq[j][d], df, gr[m][d]);
-            fmx[m] = fmax(fmx[m], fj);
-            fmn[m] = fmin(fmn[m], fj);
+            up[m] = fmax(up[m], df);
+            dn[m] = fmin(dn[m], df);
         }
     }
     if (!limiter) return;
@@ -219,7 +227,6 @@ __device__ __forceinline__ void slope_from(const CellGeo<D> &g, int limiter, con
     // a face with no increment gives num = den and never wins
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-        const double up = fmx[m] - fc[m], dn = fmn[m] - fc[m];
         double bn = 1.0, bd = 1.0;
 #pragma unroll
         for (int j = 0; j < MF; ++j) {
@@ -227,7 +234,7 @@ __device__ __forceinline__ void slope_from(const CellGeo<D> &g, int limiter, con
             double dm = 0.0;
 #pragma unroll
             for (int d = 0; d < D; ++d) dm = fma(gr[m][d], g.dvec[j][d], dm);
-            const double dp = dm > 0.0 ? up : dn;
+            const double dp = dm > 0.0 ? up[m] : dn[m];
             const double dp2e = fma(dp, dp, g.eps2);
             const double num = fma(2.0 * dm, dp, dp2e);
             const double den = fma(dm, fma(2.0, dm, dp), dp2e);
