@@ -129,6 +129,23 @@ def test_cylinder_small_fp64(limiter, steps):
     _compare(s, o)
 
 
+@pytest.mark.parametrize("nv,half_width", [(3, 3.0), (8, 5.0), (16, 6.0)])
+def test_velocity_sets_below_and_at_the_block_size(nv, half_width):
+    """9 velocities (fewer than one wavefront's 64 lanes), 64 (one
+    wavefront) and 256 (one 256-thread block, no ragged tail): parity with the
+    oracle after 10 steps; a call for zero steps changes nothing."""
+    ugks = _gpu()
+    c = cases.case_periodic_wave(nx=6, ny=4, nv=nv, half_width=half_width)
+    _say(f"case {c['name']}: fp64, 0 then 10 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    f0, W0 = s.f(), s.macros()[0]
+    s.step(0)
+    assert np.array_equal(s.f(), f0) and np.array_equal(s.macros()[0], W0) and s.step_count == 0
+    s.step(10)
+    o.step(10)
+    _compare(s, o)
+
+
 def test_periodic_wave_unlimited_fp64():
     ugks = _gpu()
     c = cases.case_periodic_wave(limiter=0)

@@ -45,3 +45,50 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             ugks.load_library(str(tmp_path / "missing.so"))
         finally:
             ugks._lib = None
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libugks.so not built")
+@pytest.mark.parametrize("what", ["no velocities", "no cells", "too many velocities", "dim 4",
+                                  "bad storage", "Pr 0", "face out of range", "negative density"])
+def test_create_rejects_degenerate_inputs_on_the_host(what):
+    """ugks_create validates its arguments before any device call: each of
+    these returns UGKS_ERR_ARG with a message, and no handle."""
+    import ctypes
+    import numpy as np
+    from paper_2412_06546_amd import cases, ugks
+    c = cases.case_periodic_wave(nx=4, ny=3, nv=6)
+    m, vg, gas = c["mesh"], c["vgrid"], c["gas"]
+    fstore = "f64"
+    if what == "no velocities":
+        c["vgrid"] = dict(dim=2, u=np.zeros((0, 2)), w=np.zeros(0))
+    elif what == "no cells":
+        c["mesh"] = dict(m, cell_volume=np.zeros(0), cell_centroid=np.zeros((0, 2)))
+        c["prim0"] = np.zeros((0, 4))
+    elif what == "too many velocities":
+        c["vgrid"] = cases.tensor_vgrid(129, 6.0, 2)
+    elif what == "dim 4":
+        c["mesh"] = dict(m, dim=4)
+    elif what == "bad storage":
+        fstore = "f16"
+    elif what == "Pr 0":
+        c["gas"] = dict(gas, Pr=0.0)
+    elif what == "face out of range":
+        fc = m["face_cells"].copy()
+        fc[3, 0] = len(m["cell_volume"])
+        c["mesh"] = dict(m, face_cells=fc)
+    elif what == "negative density":
+        c["prim0"] = c["prim0"].copy()
+        c["prim0"][5, 0] = -1.0
+    L = ugks.load_library()
+    keep = []
+    if fstore == "f16":
+        ugks._FSTORE["f16"] = 7
+    try:
+        mesh, vgrid, g, prim0 = ugks._structs(c, fstore, keep)
+    finally:
+        ugks._FSTORE.pop("f16", None)
+    h = ctypes.c_void_p(1)
+    code = L.ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), ctypes.byref(g), prim0, None, ctypes.byref(h))
+    assert code == ugks.UGKS_ERR_ARG, (what, code)
+    assert not h.value
+    assert L.ugks_last_error(None).decode()
