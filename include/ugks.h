@@ -29,8 +29,10 @@
  *     handle owns every device allocation, and ugks_destroy frees them.
  *   - Status codes: 0 = success, negative = UGKS_ERR_*; no C++ exception
  *     crosses the ABI.  ugks_last_error() returns the text of the last
- *     failure on that handle (or of the last failed ugks_create when the
- *     handle is NULL).
+ *     failure on that handle (or, when the handle is NULL, of the last
+ *     failed ugks_create / ugks_batch_create of the calling thread).
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ *     Distinct handles may be used from distinct threads.
  *   - All work of a handle is queued on the HIP stream given at creation;
  *     entry points that return host data synchronise that stream.
  */
@@ -116,6 +118,14 @@ typedef struct ugks ugks_t;
  * dt = cfl * min over cells and velocities of
  *      |Omega_i| / sum_faces S max(0, u_k . n_outward).
  * Limits: at most 16,000,000 cells and 16,384 velocities (UGKS_ERR_ARG).
+ * The inputs are checked on the host before any device call; UGKS_ERR_ARG
+ * names the first offending item: empty mesh or velocity set, dim not 2 or
+ * 3, a face whose cell index is out of range or whose boundary type does
+ * not match its cells, a non-positive area or volume, a normal that is not
+ * a unit vector (|n|^2 off 1 by 1e-6 or more), a non-finite centroid or
+ * periodic shift, a cell with fewer than dim + 1 or more than 4 (2D) / 6
+ * (3D) faces, a non-positive initial density or temperature, a storage type
+ * or gas constant out of range.
  * Returns UGKS_OK and *out, or an error code (*out = NULL). */
 int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas,
                 const double *prim0, void *stream, ugks_t **out);

@@ -52,7 +52,8 @@ struct ugks {
     int pending = 0;
 };
 
-static std::string g_create_error;
+// text of the last failed create call, per calling thread
+static thread_local std::string g_create_error;
 
 namespace {
 
@@ -188,7 +189,21 @@ void validate_faces(const ugks_mesh_t *m, int nbc)
         if (bc != UGKS_BC_INTERIOR && bc != UGKS_BC_OUTFLOW && (bid < 0 || bid >= nbc))
             throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": boundary state index out of range"};
         if (!(m->face_area[f] > 0.0)) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": non-positive area"};
+        double n2 = 0.0;
+        bool finite = true;
+        for (int d = 0; d < m->dim; ++d) {
+            const double nd = m->face_normal[(size_t)f * m->dim + d];
+            n2 += nd * nd;
+            finite = finite && std::isfinite(m->face_centroid[(size_t)f * m->dim + d]) &&
+                     (!m->face_shift || std::isfinite(m->face_shift[(size_t)f * m->dim + d]));
+        }
+        if (!(std::fabs(n2 - 1.0) < 1e-6)) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": normal is not a unit vector"};
+        if (!finite) throw Fail{UGKS_ERR_ARG, "face " + std::to_string(f) + ": non-finite centroid or periodic shift"};
     }
+    for (int c = 0; c < nc; ++c)
+        for (int d = 0; d < m->dim; ++d)
+            if (!std::isfinite(m->cell_centroid[(size_t)c * m->dim + d]))
+                throw Fail{UGKS_ERR_ARG, "cell " + std::to_string(c) + ": non-finite centroid"};
 }
 
 // The library stores cells along a Morton (Z-order) curve through their

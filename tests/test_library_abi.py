@@ -49,7 +49,8 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libugks.so not built")
 @pytest.mark.parametrize("what", ["no velocities", "no cells", "too many velocities", "dim 4",
-                                  "bad storage", "Pr 0", "face out of range", "negative density"])
+                                  "bad storage", "Pr 0", "face out of range", "negative density",
+                                  "normal not unit", "centroid not finite"])
 def test_create_rejects_degenerate_inputs_on_the_host(what):
     """ugks_create validates its arguments before any device call: each of
     these returns UGKS_ERR_ARG with a message, and no handle."""
@@ -76,6 +77,12 @@ def test_create_rejects_degenerate_inputs_on_the_host(what):
         fc = m["face_cells"].copy()
         fc[3, 0] = len(m["cell_volume"])
         c["mesh"] = dict(m, face_cells=fc)
+    elif what == "normal not unit":
+        c["mesh"] = dict(m, face_normal=m["face_normal"] * 1.01)
+    elif what == "centroid not finite":
+        cc = m["cell_centroid"].copy()
+        cc[2, 1] = np.nan
+        c["mesh"] = dict(m, cell_centroid=cc)
     elif what == "negative density":
         c["prim0"] = c["prim0"].copy()
         c["prim0"][5, 0] = -1.0
