@@ -119,7 +119,8 @@ typedef struct ugks ugks_t;
  *      |Omega_i| / sum_faces S max(0, u_k . n_outward).
  * Limits: at most 16,000,000 cells and 16,384 velocities (UGKS_ERR_ARG).
  * The inputs are checked on the host before any device call; UGKS_ERR_ARG
- * names the first offending item: empty mesh or velocity set, dim not 2 or
+ * names the first offending item: empty mesh or velocity set, a velocity
+ * that is not finite or whose weight is not positive, dim not 2 or
  * 3, a face whose cell index is out of range or whose boundary type does
  * not match its cells, a non-positive area or volume, a normal that is not
  * a unit vector (|n|^2 off 1 by 1e-6 or more), a non-finite centroid or

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
 #include <vector>
@@ -500,6 +501,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         g_create_error = "host allocation failed";
         return UGKS_ERR_ALLOC;
     }
+    double *prim_d = nullptr;  // initial state on the device, freed before returning
     try {
         if (!mesh || !vgrid || !gas || !prim0) throw Fail{UGKS_ERR_ARG, "NULL argument"};
         const int D = mesh->dim;
@@ -518,6 +520,11 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (!(gas->Pr > 0.0) || !(gas->mu_ref > 0.0) || !(gas->cfl > 0.0) || gas->limiter_k < 0.0)
             throw Fail{UGKS_ERR_ARG, "Pr, mu_ref and cfl must be positive, limiter_k non-negative"};
         if (gas->n_bc < 0 || (gas->n_bc > 0 && !gas->bc_prim)) throw Fail{UGKS_ERR_ARG, "bc_prim missing"};
+        for (int k = 0; k < vgrid->n_vel; ++k) {
+            bool ok = vgrid->w[k] > 0.0 && std::isfinite(vgrid->w[k]);
+            for (int d = 0; d < D; ++d) ok = ok && std::isfinite(vgrid->u[(size_t)k * D + d]);
+            if (!ok) throw Fail{UGKS_ERR_ARG, "velocity " + std::to_string(k) + ": non-finite point or non-positive weight"};
+        }
         h->dim = D;
         h->nc = mesh->n_cells;
         h->nf = mesh->n_faces;
@@ -584,7 +591,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             upload(h->u1d, axes.data(), sizeof(double) * axes.size(), h->stream);
             upload(h->kidx, kidx.data(), sizeof(int) * kidx.size(), h->stream);
         }
-        double *prim_d = dev_alloc<double>(h, nc * (D + 2));
+        prim_d = dev_alloc<double>(h, nc * (D + 2));
         const size_t fbytes = nc * h->ncomp * nv * fvalue_bytes(h->fstore);
         for (int b = 0; b < 2; ++b) {
             hip_check(hipMalloc(&h->f[b], fbytes), "hipMalloc of f");
@@ -641,12 +648,18 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         hip_check(launch_moments(P, h->f[0], h->stream), "k_moments launch");
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         (void)hipFree(prim_d);
+        prim_d = nullptr;
         h->bytes -= sizeof(double) * nc * (D + 2);
     } catch (const Fail &e) {
-        int code = fail(nullptr, e);
+        if (prim_d) (void)hipFree(prim_d);
         release(h);
         delete h;
-        return code;
+        return fail(nullptr, e);
+    } catch (const std::exception &e) {
+        if (prim_d) (void)hipFree(prim_d);
+        release(h);
+        delete h;
+        return fail(nullptr, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     *out = h;
     return UGKS_OK;
@@ -692,6 +705,8 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
         if (err[0]) return fail(h, Fail{UGKS_ERR_NONPHYSICAL, nonphysical_message(h, err[1])});
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -714,6 +729,8 @@ extern "C" int ugks_step_async(ugks_t *h, int nsteps)
         finish_async(h);
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -773,6 +790,8 @@ extern "C" int ugks_macros(ugks_t *h, double *W_out, double *q_out)
         }
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -804,6 +823,8 @@ extern "C" int ugks_get_f(ugks_t *h, double *f_out)
         }
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -840,6 +861,8 @@ extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
         }
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -906,6 +929,8 @@ extern "C" int ugks_get_state(ugks_t *h, void *buf, size_t bytes)
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -936,6 +961,8 @@ extern "C" int ugks_set_state(ugks_t *h, const void *buf, size_t bytes)
         h->stepped = 0;
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -956,6 +983,8 @@ extern "C" int ugks_wall_flux(ugks_t *h, double *out)
         }
     } catch (const Fail &e) {
         return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
     }
     return UGKS_OK;
 }
@@ -1137,6 +1166,8 @@ extern "C" int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int ns
         }
     } catch (const Fail &e) {
         return bad(e.code, e.msg);
+    } catch (const std::exception &e) {
+        return bad(UGKS_ERR_ALLOC, std::string("host: ") + e.what());
     }
     return UGKS_OK;
 }

@@ -50,7 +50,7 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libugks.so not built")
 @pytest.mark.parametrize("what", ["no velocities", "no cells", "too many velocities", "dim 4",
                                   "bad storage", "Pr 0", "face out of range", "negative density",
-                                  "normal not unit", "centroid not finite"])
+                                  "normal not unit", "centroid not finite", "zero velocity weight"])
 def test_create_rejects_degenerate_inputs_on_the_host(what):
     """ugks_create validates its arguments before any device call: each of
     these returns UGKS_ERR_ARG with a message, and no handle."""
@@ -83,6 +83,10 @@ def test_create_rejects_degenerate_inputs_on_the_host(what):
         cc = m["cell_centroid"].copy()
         cc[2, 1] = np.nan
         c["mesh"] = dict(m, cell_centroid=cc)
+    elif what == "zero velocity weight":
+        w = vg["w"].copy()
+        w[7] = 0.0
+        c["vgrid"] = dict(vg, w=w)
     elif what == "negative density":
         c["prim0"] = c["prim0"].copy()
         c["prim0"][5, 0] = -1.0
