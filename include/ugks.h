@@ -182,7 +182,8 @@ int ugks_macros(ugks_t *h, double *W_out, double *q_out);
 int ugks_get_f(ugks_t *h, double *f_out);
 
 /* Replace f with a host array laid out as in ugks_get_f; W and q become its
- * discrete moments (checkpoint restart or a non-equilibrium start). */
+ * discrete moments (checkpoint restart or a non-equilibrium start), and a
+ * non-physical flag left by an earlier step is cleared. */
 int ugks_set_f(ugks_t *h, const double *f_in);
 
 /* Checkpoint and restart, exact: the state blob holds W, q, f in its

@@ -838,6 +838,8 @@ extern "C" int ugks_set_f(ugks_t *h, const double *f_in)
         const size_t nv = h->nv, rows = (size_t)h->nc * h->ncomp, n = rows * nv;
         std::vector<double> tmp(n);
         const size_t nk = h->ncomp;
+        const int err0[2] = {0, 0x7fffffff};  // a new state: clear the non-physical flag
+        upload(h->err, err0, sizeof(err0), h->stream);
         for (size_t r = 0; r < rows; ++r) {
             const double *src = f_in + ((size_t)h->cell_of[r / nk] * nk + r % nk) * nv;
             for (size_t k = 0; k < nv; ++k) tmp[r * nv + k] = src[h->perm[k]];
