@@ -349,6 +349,14 @@ def test_nonphysical_state_is_reported():
     fc = c["mesh"]["face_cells"]
     near = {3} | set(fc[fc[:, 0] == 3, 1]) | set(fc[fc[:, 1] == 3, 0])
     assert named in near, (named, near)
+    # restarting from a physical f clears the flag: the case steps again and
+    # matches a fresh run from the same f
+    s.set_f(f0 := ugks.Solver(c).f())
+    s.step(3)
+    fresh = ugks.Solver(c)
+    fresh.set_f(f0)
+    fresh.step(3)
+    assert np.array_equal(s.f(), fresh.f())
 
 
 def test_invalid_mesh_is_rejected():
