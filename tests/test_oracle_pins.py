@@ -403,6 +403,48 @@ def test_boundary_outgoing_flux_is_exact_for_linear_data(wall):
         np.testing.assert_allclose(g[cells][:, 0][:, sel], ex, rtol=1e-13)
 
 
+@pytest.mark.parametrize("kind", ["inflow", "outflow"])
+def test_far_field_incoming_particles_carry_the_ghost_maxwellian(kind):
+    """Pins the far-field ghost (Section 2.5): uniform, non-equilibrium data
+    A_k in a channel bounded by far-field faces, free-molecular (tau -> oo,
+    no limiter).  Interior and outgoing fluxes cancel for uniform data, so
+    after one step a boundary cell changes only at the velocities entering
+    through its far-field face: f + (dt S / V) |u_n| (G_k - A_k), G the
+    reduced Maxwellian of the ghost state -- the free stream on inflow faces,
+    the cell's own state (the moments of A) on outflow faces."""
+    nx = ny = 6
+    bc = (cases.BC_INFLOW, 0) if kind == "inflow" else (cases.BC_OUTFLOW, 0)
+    mesh = cases.channel_quads(nx, ny, 1.0, 1.0, y_bc=bc)
+    nc = len(mesh["cell_volume"])
+    ghost = np.array([1.3, 0.4, -0.2, 1.2])                   # rho, U, T
+    c = _small_case(mesh, nv=8, L=3.0, mu_ref=1e30, limiter=0, bc_prim=ghost[None, :])
+    o = oracle.Oracle(c)
+    u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+    k = np.arange(len(u))
+    A = np.stack([1.0 + 0.3 * np.cos(0.7 * k), 0.6 + 0.2 * np.sin(1.3 * k)])   # h_k, b_k > 0
+    f = np.broadcast_to(A, (nc, 2, len(u))).copy()
+    o.set_f(f)
+    o.step(1)
+    g = o.f()
+    if kind == "inflow":
+        rho, U, T = ghost[0], ghost[1:3], ghost[3]
+    else:                      # the moments of A: rho, U and T (lambda = 1/T, 3 dof)
+        rho = (w * A[0]).sum()
+        U = (w[:, None] * u * A[0][:, None]).sum(0) / rho
+        E = 0.5 * (w * ((u ** 2).sum(1) * A[0] + A[1])).sum()
+        T = (4.0 / 3.0) * (E - 0.5 * rho * (U ** 2).sum()) / rho
+    G = rho / (math.pi * T) * np.exp(-((u - U) ** 2).sum(1) / T)
+    G = np.stack([G, 0.5 * T * G])                            # b = int xi^2 g dxi = T/2 h
+    x = mesh["cell_centroid"]
+    h = 1.0 / ny
+    coef = o.dt / h                                           # S / V = 1 / dy
+    for cells, inc in ((np.where(x[:, 1] > 1 - h)[0], u[:, 1] < 0), (np.where(x[:, 1] < h)[0], u[:, 1] > 0)):
+        ex = A + coef * np.abs(u[:, 1])[None, :] * (G - A) * inc[None, :]
+        np.testing.assert_allclose(g[cells], np.broadcast_to(ex, (len(cells),) + ex.shape), rtol=1e-12, atol=0)
+    inner = np.where((x[:, 1] > h) & (x[:, 1] < 1 - h))[0]
+    np.testing.assert_allclose(g[inner], f[inner], rtol=1e-12, atol=0)
+
+
 def test_wall_in_equilibrium_with_the_gas_stays_steady():
     """Gas at rest at the wall temperature between two walls: the wall density
     equals the gas density and nothing moves (zero net mass flux)."""
