@@ -105,8 +105,14 @@ def cpu_baseline(case, target_s: float, max_steps: int):
     o.step(1)
     t1 = time.perf_counter() - t0
     o.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": nc * nv * steps / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
-            "single_core_value": nc * nv / t1,
+            "single_core_value": nc * nv / t1, "host_cpu": model, "host_logical_cpus": os.cpu_count(),
             "sample": f"{steps} full steps of the same {nc}-cell x {nv}-velocity workload on {cores} threads "
                       f"({t:.1f} s, OpenMP over cells, gcc -O2), then 1 step on 1 thread ({t1:.1f} s)"}
 
