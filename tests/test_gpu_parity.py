@@ -146,6 +146,33 @@ def test_velocity_sets_below_and_at_the_block_size(nv, half_width):
     _compare(s, o)
 
 
+def test_largest_velocity_set():
+    """16,384 velocities (128 x 128), the most ugks_create accepts: 64
+    velocities per thread of a 256-thread block, per-axis tables of 256
+    values, stage-1 values in f_out."""
+    ugks = _gpu()
+    c = cases.case_periodic_wave(nx=6, ny=4, nv=128, half_width=8.0)
+    _say(f"case {c['name']}: fp64, 3 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert s.nv == 16384 and s.tensor_grid
+    s.step(3)
+    o.step(3)
+    _compare(s, o)
+
+
+@pytest.mark.parametrize("kn", [1e-5, 1e3])
+def test_collision_time_extremes(kn):
+    """dt / tau = 300 (near continuum: the time integrals' exponentials
+    vanish) and 3e-6 (free molecular: their Taylor-series branch)."""
+    ugks = _gpu()
+    c = cases.case_periodic_wave(kn=kn)
+    _say(f"case {c['name']} Kn={kn}: fp64, 10 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    s.step(10)
+    o.step(10)
+    _compare(s, o)
+
+
 def test_periodic_wave_unlimited_fp64():
     ugks = _gpu()
     c = cases.case_periodic_wave(limiter=0)
