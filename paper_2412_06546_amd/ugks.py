@@ -59,6 +59,14 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built: run paper_2412_06546_amd/build.py (or __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime.  Loaded first, it is the runtime the
+    # library binds to (same soname); loaded after the library, a second HIP
+    # and HSA runtime would enter the process and the two would not share
+    # devices, memory or streams.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     L.ugks_create.restype = C.c_int
     L.ugks_create.argtypes = [C.POINTER(ugks_mesh_t), C.POINTER(ugks_vgrid_t), C.POINTER(ugks_gas_t), _dp,

@@ -103,3 +103,20 @@ def test_create_rejects_degenerate_inputs_on_the_host(what):
     assert code == ugks.UGKS_ERR_ARG, (what, code)
     assert not h.value
     assert L.ugks_last_error(None).decode()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libugks.so not built")
+def test_binding_leaves_one_hip_runtime_in_the_process():
+    """load_library() before any import of torch still leaves a single HIP
+    runtime (and HSA runtime) mapped: the library binds to torch's."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2412_06546_amd import ugks\n"
+            "ugks.load_library()\n"
+            "import torch\n"
+            "maps = [l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l or 'libhsa-runtime64' in l]\n"
+            "print(len({m for m in maps if 'amdhip64' in m}), len({m for m in maps if 'hsa-runtime64' in m}))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split() == ["1", "1"], out.stdout
