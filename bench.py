@@ -181,8 +181,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fstore", choices=["f64", "f32", "bf16"], default="f64")
-    ap.add_argument("--workload", choices=["cylinder", "sphere", "liftingbody"], default="cylinder",
+    ap.add_argument("--workload", choices=["cylinder", "sphere", "spherehex", "liftingbody"], default="cylinder",
                     help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities); "
+                         "spherehex: the same shell as 50,688 hexahedra; "
                          "liftingbody: the X38-sized case (1,058,685 cells x 4,548 velocities, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
@@ -213,6 +214,7 @@ def main():
 
     from paper_2412_06546_amd import cases
     case = {"cylinder": cases.case_cylinder, "sphere": cases.case_sphere,
+            "spherehex": lambda: cases.case_sphere(n=16, n_r=33, kind="hex"),
             "liftingbody": cases.case_lifting_body}[args.workload]()
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
@@ -260,6 +262,7 @@ def main():
         "config": {"workload": f"{case['name']}: " + {
                        "cylinder": "2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall",
                        "sphere": "3D sphere Ma 4 Kn 0.05 Shakhov, isothermal wall",
+                       "spherehex": "3D sphere (hexahedra) Ma 4 Kn 0.05 Shakhov, isothermal wall",
                        "liftingbody": "3D X38-sized lifting body Ma 8 AoA 20 Kn 0.01 Shakhov, wall 5.39 T_inf, "
                                       "unstructured velocity set"}[args.workload],
                    "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64",

@@ -625,17 +625,25 @@ def cubed_sphere_shell(n, n_r, r_wall=1.0, r_far=6.0, h_first=5e-3):
 
 
 def case_sphere(n=8, n_r=22, nv=24, half_width=10.0, ma=4.0, kn=0.05, Pr=0.72, omega=0.81, t_wall=1.0,
-                r_far=6.0, h_first=5e-3, wall_layer=0.2):
+                r_far=6.0, h_first=5e-3, wall_layer=0.2, kind="tet"):
     """3D sphere: a cubed-sphere shell around the unit sphere out to radius
     6, n x n points per cube face, n_r layers from a 5e-3 first layer, each
     prism cut into three tetrahedra (36 n^2 n_r cells: 50,688 by default);
     Shakhov Pr = 0.72, Ma = 4, Kn = 0.05 on the diameter, isothermal wall at
     T_inf; 24^3 trapezoid grid on [-10,10]^3.  Start: rho = T = 1 with the
-    potential flow around the sphere brought to rest over a wall layer."""
+    potential flow around the sphere brought to rest over a wall layer.
+    kind='hex': the same shell as hexahedra (6 n^2 n_r cells; n=16, n_r=33
+    also gives 50,688), the paper's own cell type for its sphere."""
     u_inf = ma * sound_speed(1.0)
-    X, prisms = cubed_sphere_shell(n, n_r, 1.0, r_far, h_first)
-    T = prisms_to_tets(prisms)
     r_mid = 0.5 * (1.0 + r_far)
+    if kind == "hex":
+        # straight lines from the sphere to the far field, first layer
+        # h_first (the shell builder takes it relative to the line length)
+        X, hexes, _ = lifting_body_shell(n, n_r, 0, axes=(1.0, 1.0, 1.0), z_lower=1.0, r_far=r_far,
+                                         h_first=h_first / (r_far - 1.0))
+    else:
+        X, prisms = cubed_sphere_shell(n, n_r, 1.0, r_far, h_first)
+        T = prisms_to_tets(prisms)
     uvec = np.array([u_inf, 0.0, 0.0])
 
     def classify(xc, nrm):
@@ -643,7 +651,7 @@ def case_sphere(n=8, n_r=22, nv=24, half_width=10.0, ma=4.0, kn=0.05, Pr=0.72, o
         bc = np.where(wall, BC_WALL, np.where(nrm @ uvec < 0.0, BC_INFLOW, BC_OUTFLOW)).astype(np.int32)
         return bc, np.where(wall, 1, 0).astype(np.int32)
 
-    mesh = mesh_from_tets(X, T, classify)
+    mesh = mesh_from_cells(X, classify, hexes=hexes) if kind == "hex" else mesh_from_tets(X, T, classify)
     vg = tensor_vgrid(nv, half_width, 3)
     bc = np.array([[1.0, u_inf, 0.0, 0.0, 1.0],
                    [1.0, 0.0, 0.0, 0.0, t_wall]])
@@ -657,7 +665,7 @@ def case_sphere(n=8, n_r=22, nv=24, half_width=10.0, ma=4.0, kn=0.05, Pr=0.72, o
     damp = 1.0 - np.exp(-(r - 1.0) / wall_layer)
     prim0 = np.tile(bc[0], (len(x), 1))
     prim0[:, 1:4] = vel * damp[:, None]
-    return dict(name=f"sphere_{len(x)}tet_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
+    return dict(name=f"sphere_{len(x)}{kind}_v{nv}^3", mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
 
 
 def mesh_from_cells(X, classify_boundary, tets=None, prisms=None, hexes=None):

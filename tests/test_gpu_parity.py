@@ -173,6 +173,18 @@ def test_collision_time_extremes(kn):
     _compare(s, o)
 
 
+def test_hexahedral_sphere_shell_fp64():
+    """The sphere's shell as hexahedra (curved wall, far field, Ma 4):
+    768 cells, 12^3 velocities, 20 steps against the oracle."""
+    ugks = _gpu()
+    c = cases.case_sphere(n=4, n_r=8, nv=12, half_width=8.0, kind="hex")
+    _say(f"case {c['name']}: fp64, 20 steps")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    s.step(20)
+    o.step(20)
+    _compare(s, o)
+
+
 def test_periodic_wave_unlimited_fp64():
     ugks = _gpu()
     c = cases.case_periodic_wave(limiter=0)
