@@ -469,15 +469,15 @@ def test_wall_flux_matches_oracle(which):
 
 def test_full_size_cylinder_fp64():
     """20,000 cells x 3,600 velocities, the benchmark's launch configuration:
-    two steps against the oracle on every cell."""
+    ten steps against the oracle on every cell."""
     ugks = _gpu()
     c = cases.case_cylinder()
-    _say(f"case {c['name']}: fp64 full size, 2 steps")
+    _say(f"case {c['name']}: fp64 full size, 10 steps")
     s = ugks.Solver(c)
     o = oracle.Oracle(c)
     assert s.dt == pytest.approx(o.dt, rel=1e-15)
-    s.step(2)
-    o.step(2)
+    s.step(10)
+    o.step(10)
     _compare(s, o, f_too=False)
     # f on a sample of cells (wall, interior, far field)
     idx = np.array([0, 1, 199, 200, 5000, 12345, 19999])
