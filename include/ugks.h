@@ -107,7 +107,22 @@ typedef struct {
     int fstore;         /* UGKS_F64, UGKS_F32 or UGKS_BF16 storage of f */
     int n_bc;
     const double *bc_prim; /* [n_bc][dim+2]: (rho, U, T); walls use (U_w, T_w) */
+    int mem_mode;       /* UGKS_MEM_TWO_BUFFERS or UGKS_MEM_IN_PLACE (below) */
+    int chunk;          /* in-place mode: velocities per chunk, 0 = 512 */
 } ugks_gas_t;
+
+/* Storage of f.  UGKS_MEM_TWO_BUFFERS: f^n is read from one buffer and
+ * f^{n+1} written to the other (2 f of memory; the fastest form).
+ * UGKS_MEM_IN_PLACE: one buffer, updated in place as in the paper's
+ * two-stage form (Section 3.2): the velocities are swept in chunks, the
+ * stage-1 values of a chunk wait in a ring of n_cells x n_comp x chunk
+ * values until no cell reads that chunk's f^n any more, and stage 2 is
+ * applied in place; memory 1 f + the ring.  Both forms give the same
+ * results up to the order of the sums over velocities.  In-place handles
+ * cannot be batched (ugks_batch_step) and keep no copy of the f that started
+ * a step (ugks_wall_flux returns UGKS_ERR_STATE). */
+#define UGKS_MEM_TWO_BUFFERS 0
+#define UGKS_MEM_IN_PLACE 1
 
 typedef struct ugks ugks_t;
 

@@ -29,6 +29,10 @@ struct ugks {
     // surface quantities: stored indices of the wall faces (in the caller's
     // face order), their flux in the last step, and whether a step has run
     // since creation or set_f (f[1 - cur] then holds the f that started it)
+    int mem_mode = UGKS_MEM_TWO_BUFFERS;
+    void *ring = nullptr;          // in-place mode: one chunk of stage-1 values per cell
+    double *mom_part = nullptr;    // in-place mode: per-chunk moments
+    double *rho_w = nullptr;       // in-place mode: wall densities
     int n_wallf = 0;
     int *wallf = nullptr;
     double *wallF = nullptr;
@@ -425,7 +429,12 @@ template <int D> void create_d(ugks_t *h, const StoredMesh &S, const ugks_gas_t 
 // Device bytes a handle owns once created (the same sizes ugks_create
 // allocates; the temporary initial-state buffer is not counted).
 template <typename T> size_t nbytes(size_t n) { return sizeof(T) * (n ? n : 1); }
-size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab, size_t nwallf)
+// in-place mode: velocities per chunk (0 asks for the default) and chunk count
+int chunk_of(int chunk, int nv) { return std::min(chunk > 0 ? chunk : 512, nv); }
+int nchunk_of(int chunk, int nv) { return (nv + chunk - 1) / chunk; }
+
+size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab, size_t nwallf,
+                  int mem_mode = UGKS_MEM_TWO_BUFFERS, int chunk = 0)
 {
     const size_t NW = D + 2, ncomp = D == 2 ? 2 : 1;
     size_t b = D == 2 ? nbytes<CellGeo<2>>(nc) + nbytes<FaceGeo<2>>(nf) + nbytes<FaceEq<2>>(nf)
@@ -434,7 +443,14 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
     b += nbytes<double>(nc * NW) + nbytes<double>(nc * D) + nbytes<double>(nc * NW * D) + nbytes<double>(nc * NW);
     b += nbytes<double>(nc) + nbytes<double>(NW) + nbytes<int>(2);
     if (ntab) b += nbytes<double>(ntab) + nbytes<int>(nv);
-    b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
+    if (mem_mode == UGKS_MEM_IN_PLACE) {
+        const int ch = chunk_of(chunk, (int)nv), nq = nchunk_of(ch, (int)nv);
+        b += nc * ncomp * nv * fvalue_bytes(fstore);                      // f
+        b += nbytes<char>(nc * ncomp * (size_t)ch * fvalue_bytes(fstore));  // ring
+        b += nbytes<double>(nc * (size_t)nq * NW) + nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
+    } else {
+        b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
+    }
     b += nbytes<int>(nwallf) + nbytes<double>(nwallf * NW);
     return b;
 }
@@ -481,7 +497,7 @@ void release(ugks_t *h)
     if (h->h_res) (void)hipHostFree(h->h_res);
     if (h->done_ev) (void)hipEventDestroy(h->done_ev);
     void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
-                    h->cell_dt, h->res, h->err, h->u1d, h->kidx, h->wallf, h->wallF};
+                    h->cell_dt, h->res, h->err, h->u1d, h->kidx, h->wallf, h->wallF, h->ring, h->mom_part, h->rho_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -520,6 +536,9 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (!(gas->Pr > 0.0) || !(gas->mu_ref > 0.0) || !(gas->cfl > 0.0) || gas->limiter_k < 0.0)
             throw Fail{UGKS_ERR_ARG, "Pr, mu_ref and cfl must be positive, limiter_k non-negative"};
         if (gas->n_bc < 0 || (gas->n_bc > 0 && !gas->bc_prim)) throw Fail{UGKS_ERR_ARG, "bc_prim missing"};
+        if (gas->mem_mode != UGKS_MEM_TWO_BUFFERS && gas->mem_mode != UGKS_MEM_IN_PLACE)
+            throw Fail{UGKS_ERR_ARG, "mem_mode must be UGKS_MEM_TWO_BUFFERS or UGKS_MEM_IN_PLACE"};
+        if (gas->chunk < 0) throw Fail{UGKS_ERR_ARG, "chunk must be >= 0"};
         for (int k = 0; k < vgrid->n_vel; ++k) {
             bool ok = vgrid->w[k] > 0.0 && std::isfinite(vgrid->w[k]);
             for (int d = 0; d < D; ++d) ok = ok && std::isfinite(vgrid->u[(size_t)k * D + d]);
@@ -593,9 +612,21 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         }
         prim_d = dev_alloc<double>(h, nc * (D + 2));
         const size_t fbytes = nc * h->ncomp * nv * fvalue_bytes(h->fstore);
-        for (int b = 0; b < 2; ++b) {
-            hip_check(hipMalloc(&h->f[b], fbytes), "hipMalloc of f");
+        h->mem_mode = gas->mem_mode;
+        for (int b = 0; b < (h->mem_mode == UGKS_MEM_IN_PLACE ? 1 : 2); ++b) {
+            if (hipMalloc(&h->f[b], fbytes) != hipSuccess)
+                throw Fail{UGKS_ERR_ALLOC, "hipMalloc of f (" + std::to_string(fbytes) + " bytes) failed"};
             h->bytes += fbytes;
+        }
+        int chunk = 0, nchunk = 0;
+        if (h->mem_mode == UGKS_MEM_IN_PLACE) {
+            chunk = chunk_of(gas->chunk, h->nv);
+            nchunk = nchunk_of(chunk, h->nv);
+            h->ring = dev_alloc<char>(h, nc * h->ncomp * (size_t)chunk * fvalue_bytes(h->fstore));
+            h->mom_part = dev_alloc<double>(h, nc * (size_t)nchunk * (D + 2));
+            h->rho_w = dev_alloc<double>(h, nc * (size_t)(D == 2 ? Dim<2>::MF : Dim<3>::MF));
+            hip_check(hipMemsetAsync(h->rho_w, 0, sizeof(double) * nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF),
+                                     h->stream), "hipMemsetAsync");
         }
         upload(h->u, uT.data(), sizeof(double) * uT.size(), h->stream);
         upload(h->w, wP.data(), sizeof(double) * nv, h->stream);
@@ -632,6 +663,11 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         P.kidx = h->kidx;
         for (int d = 0; d < 3; ++d) P.n1d[d] = h->tensor ? n1d[d] : 0;
         P.ntab = h->tensor ? (int)axes.size() : 0;
+        P.ring = h->ring;
+        P.chunk = chunk;
+        P.nchunk = nchunk;
+        P.mom_part = h->mom_part;
+        P.rho_w = h->rho_w;
 
         // time step (Alg. 1 line 1), fixed for the run
         hip_check(launch_cfl(P, h->cell_dt, h->stream), "k_cfl launch");
@@ -665,6 +701,20 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
     return UGKS_OK;
 }
 
+namespace {
+// one step's sweep: into the other buffer (then it becomes the current one),
+// or in place
+void sweep(ugks_t *h)
+{
+    if (h->mem_mode == UGKS_MEM_IN_PLACE) {
+        hip_check(launch_sweep_inplace(h->P, h->f[0], h->n_wallf > 0, h->stream), "in-place sweep launch");
+    } else {
+        hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
+        h->cur ^= 1;
+    }
+}
+}  // namespace
+
 extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
 {
     if (!h) return UGKS_ERR_ARG;
@@ -679,9 +729,8 @@ extern "C" int ugks_step(ugks_t *h, int nsteps, double *residual_out)
             if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s], h->stream), "hipEventRecord");
             hip_check(launch_prologue(h->P, h->stream), "prologue launch");
             if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s + 1], h->stream), "hipEventRecord");
-            hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
+            sweep(h);
             if (h->profiling) hip_check(hipEventRecord(h->ev[3 * s + 2], h->stream), "hipEventRecord");
-            h->cur ^= 1;
             h->nstep++;
             h->stepped = 1;
         }
@@ -720,8 +769,7 @@ extern "C" int ugks_step_async(ugks_t *h, int nsteps)
         ensure_async(h);
         for (int s = 0; s < nsteps; ++s) {
             hip_check(launch_prologue(h->P, h->stream), "prologue launch");
-            hip_check(launch_sweep(h->P, h->f[h->cur], h->f[1 - h->cur], h->stream), "sweep launch");
-            h->cur ^= 1;
+            sweep(h);
             h->nstep++;
             h->stepped = 1;
         }
@@ -771,7 +819,8 @@ extern "C" size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vg
     size_t nwallf = 0;
     if (mesh->face_bc)
         for (int f = 0; f < mesh->n_faces; ++f) nwallf += mesh->face_bc[f] == UGKS_BC_WALL;
-    return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab, nwallf);
+    return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab, nwallf,
+                      gas->mem_mode, gas->chunk);
 }
 
 extern "C" int ugks_macros(ugks_t *h, double *W_out, double *q_out)
@@ -976,6 +1025,8 @@ extern "C" int ugks_wall_flux(ugks_t *h, double *out)
     if (!h || !out) return UGKS_ERR_ARG;
     if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
     if (!h->stepped) return fail(h, Fail{UGKS_ERR_STATE, "no step since creation or ugks_set_f"});
+    if (h->mem_mode == UGKS_MEM_IN_PLACE)
+        return fail(h, Fail{UGKS_ERR_STATE, "an in-place handle keeps no copy of the f that started the step"});
     try {
         if (h->n_wallf) {
             hip_check(launch_wall_flux(h->P, h->f[1 - h->cur], h->wallf, h->n_wallf, h->wallF, h->stream), "wall flux launch");
@@ -1099,6 +1150,7 @@ extern "C" int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int ns
         if (h->stream != b->stream) return bad(UGKS_ERR_ARG, "every handle of a batch must use the batch's stream");
         if (h->dim != D) return bad(UGKS_ERR_ARG, "cases of one batch must have the same dimension");
         if (h->pending) return bad(UGKS_ERR_STATE, "a handle still has asynchronous steps outstanding");
+        if (h->mem_mode == UGKS_MEM_IN_PLACE) return bad(UGKS_ERR_ARG, "in-place handles cannot be batched");
         for (int e = 0; e < c; ++e)
             if (hs[e] == h) return bad(UGKS_ERR_ARG, "a handle appears twice in the batch");
     }

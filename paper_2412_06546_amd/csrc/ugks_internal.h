@@ -82,6 +82,12 @@ struct Params {
     double *gW;        // [nc][dim+2][dim] limited gradients of W
     double *dW2;       // [nc][dim+2] squared change of W in the last step
     int *err;          // [2]: flag, first bad cell
+    // in-place mode (one f buffer): stage-1 values of the current velocity
+    // chunk [cell][component][chunk], each chunk's moments of the net outflow
+    // [cell][nchunk][dim+2], wall densities [cell][MF]
+    void *ring;
+    int chunk, nchunk;
+    double *mom_part, *rho_w;
 };
 
 // One case of a batched launch (several cases advanced by the same kernels):
@@ -112,6 +118,9 @@ hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_
 hipError_t launch_moments(const Params &p, const void *f, hipStream_t s);
 hipError_t launch_prologue(const Params &p, hipStream_t s);  // k_cell_grad + k_face_eq
 hipError_t launch_sweep(const Params &p, const void *f_in, void *f_out, hipStream_t s);
+// the in-place step's sweep: wall densities (if walls), one kernel per
+// velocity chunk, the final kernel; f is read and updated in place
+hipError_t launch_sweep_inplace(const Params &p, void *f, bool walls, hipStream_t s);
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s);
 // macroscopic flux [n][dim+2] through the wall faces faces[0..n) in the step that started from f
 hipError_t launch_wall_flux(const Params &p, const void *f, const int *faces, int n, double *out, hipStream_t s);

@@ -23,6 +23,8 @@
 // ever reaches memory.
 #include "ugks_internal.h"
 
+#include <algorithm>
+
 #include <cfloat>
 #include <cmath>
 
@@ -748,6 +750,324 @@ __device__ __forceinline__ int xcd_cell(int b)
     return ((t / UGKS_XCD_RUN) * UGKS_XCDS + b % UGKS_XCDS) * UGKS_XCD_RUN + t % UGKS_XCD_RUN;
 }
 
+// Per-cell constants of a step (uniform in the workgroup): W^n, the
+// primitive state, tau^n, q^n and the coefficients of f+^n and of the source.
+template <int D> struct CellStep {
+    static constexpr int NW = D + 2;
+    double Wn[NW];
+    Prim<D> pn;
+    double qn[D];
+    double pref_n, shk_n, hdt_tau, bh_n;
+};
+
+template <int D> __device__ __forceinline__ CellStep<D> cell_step(const Params &p, int i)
+{
+    constexpr int NW = D + 2;
+    CellStep<D> s;
+#pragma unroll
+    for (int m = 0; m < NW; ++m) s.Wn[m] = p.W[(size_t)i * NW + m];
+    s.pn = to_prim<D>(s.Wn);
+    const double tau_n = collision_time(s.pn.rho, s.pn.lam, p.mu_ref, p.omega);
+#pragma unroll
+    for (int d = 0; d < D; ++d) s.qn[d] = p.q[(size_t)i * D + d];
+    s.pref_n = s.pn.rho * pow_lam_pi<D>(s.pn.lam);
+    s.shk_n = 4.0 * (1.0 - p.Pr) * s.pn.lam * s.pn.lam / (5.0 * s.pn.rho);
+    s.hdt_tau = 0.5 * p.dt / tau_n;
+    s.bh_n = Dim<D>::M / (2.0 * s.pn.lam);
+    return s;
+}
+
+// One-dimensional Gaussian factors of every face's Maxwellian and of f+^n
+// (tables 0..MF-1: the face slots, table MF: the cell); no barrier inside.
+template <int D, int BS>
+__device__ __forceinline__ void fill_tables(const Params &p, const CellGeo<D> &gi, const Prim<D> &pn, double *tab)
+{
+    constexpr int NT = Dim<D>::MF + 1;
+    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
+    const int ntab = p.ntab, nf = gi.nf;
+    for (int t = threadIdx.x; t < NT * ntab; t += BS) {
+        const int which = t / ntab, idx = t - which * ntab;
+        const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+        double lam, Ud;
+        if (which < nf) {
+            const FaceEq<D> &e = fe[gi.face[which]];
+            lam = e.lam;
+            Ud = e.U[0];
+            if (ax == 1) Ud = e.U[1];
+            if (D == 3 && ax == 2) Ud = e.U[D - 1];
+        } else {
+            lam = pn.lam;
+            Ud = pn.U[0];
+            if (ax == 1) Ud = pn.U[1];
+            if (D == 3 && ax == 2) Ud = pn.U[D - 1];
+        }
+        const double c = p.u1d[idx] - Ud;
+        tab[t] = exp(-lam * c * c);
+    }
+}
+
+template <int D> __device__ __forceinline__ int has_wall_face(const Params &p, const CellGeo<D> &gi)
+{
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    int w = 0;
+    for (int j = 0; j < gi.nf; ++j) w |= (fg[gi.face[j]].bc == 3);
+    return w;
+}
+
+// Alg. 1 line 9 (wall density), for a cell with a wall face: the incident
+// particles' mass flux and the unit-density reflected flux, summed over
+// velocities; rho_w makes the net mass flux through the wall vanish
+// (Eq. maxWalldes).  Knowing rho_w up front, the sweep adds the reflected
+// particles directly.  Workgroup-wide (contains barriers).
+template <int D, typename FT, int BS, bool TENSOR>
+__device__ __forceinline__ void wall_density(const Params &p, const CellGeo<D> &gi, int i, const FT *__restrict__ fin,
+                                             const Gauss<D, TENSOR> &gauss, double *red, double (&rho_w)[Dim<D>::MF])
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF;
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
+    const int nv = p.nv, nf = gi.nf;
+    const double dt = p.dt;
+    double wsum[2 * MF];
+#pragma unroll
+    for (int j = 0; j < 2 * MF; ++j) wsum[j] = 0.0;
+    for (int k = threadIdx.x; k < nv; k += BS) {
+        double u[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) u[d] = p.u[d * nv + k];
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        const double wk = p.w[k];
+        double fi[NC], gri[NC][D];
+        limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+#pragma unroll
+        for (int j = 0; j < MF; ++j) {
+            if (j >= nf) break;
+            const FaceGeo<D> &F = fg[gi.face[j]];
+            if (F.bc != 3) continue;
+            double un = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+            if (un > 0.0) {
+                double v = fi[0], ug = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    v += gri[0][d] * gi.dvec[j][d];
+                    ug += u[d] * gri[0][d];
+                }
+                wsum[2 * j] += wk * un * (dt * v - 0.5 * dt * dt * ug);
+            } else {
+                const FaceEq<D> &e = fe[gi.face[j]];
+                wsum[2 * j + 1] += wk * un * dt * e.pref * gauss(j, kx, u, e.lam, e.U);
+            }
+        }
+    }
+    block_reduce<BS>(wsum, red, OpAdd{});
+#pragma unroll
+    for (int j = 0; j < MF; ++j) rho_w[j] = (j < nf && wsum[2 * j + 1] != 0.0) ? -wsum[2 * j] / wsum[2 * j + 1] : 0.0;
+}
+
+// Time-integrated distribution through face slot j of cell i at velocity k
+// (Eq. fullSolution on interior faces, free transport out of and the wall or
+// ghost Maxwellian into the domain on boundary faces); fi, gri: the cell's
+// own value and limited slope.  When the neighbour is upwind of an interior
+// face its limited slope is built here from its own stencil -- bit-identical
+// to what the neighbour computes for itself -- and returned in fn, grn
+// (nb_up = true).  The flux through the face is (side ? -S : S) un I.
+template <int D, typename FT, bool TENSOR>
+__device__ __forceinline__ void face_integral(const Params &p, const CellGeo<D> &gi, int j, int k, unsigned kx,
+                                              const double (&u)[D], double u2, const double (&fi)[Dim<D>::NC],
+                                              const double (&gri)[Dim<D>::NC][D], double rho_wj,
+                                              const Gauss<D, TENSOR> &gauss, const FT *__restrict__ fin, double &un,
+                                              double (&I)[Dim<D>::NC], double (&fn)[Dim<D>::NC],
+                                              double (&grn)[Dim<D>::NC][D], bool &nb_up)
+{
+    constexpr int NC = Dim<D>::NC;
+    const CellGeo<D> *cg = static_cast<const CellGeo<D> *>(p.cgeo);
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
+    const double dt = p.dt;
+    const int f = gi.face[j];
+    const FaceGeo<D> &F = fg[f];
+    const FaceEq<D> &e = fe[f];
+    un = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
+    nb_up = false;
+    if (F.bc == 0) {
+        const bool self_up = (un > 0.0) == (gi.side[j] == 0);
+        double val[NC], ug[NC];
+        if (self_up) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                val[c] = fi[c];
+                ug[c] = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    val[c] += gri[c][d] * gi.dvec[j][d];
+                    ug[c] += u[d] * gri[c][d];
+                }
+            }
+        } else {
+            const int n = gi.nb[j];
+            const CellGeo<D> &gn = cg[n];
+            const int bj = gi.back[j];
+            limited_slope<D, FT>(gn, n, fin, p.nv, k, p.limiter, fn, grn);
+            nb_up = true;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                val[c] = fn[c];
+                ug[c] = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    val[c] += grn[c][d] * gn.dvec[bj][d];
+                    ug[c] += u[d] * grn[c][d];
+                }
+            }
+        }
+        const double H0 = e.pref * gauss(j, kx, u, e.lam, e.U);
+        interface_integral<D>(e, u, u2, H0, val, ug, I);
+    } else if (un > 0.0) {
+        // outgoing through a wall or far-field face: free transport
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double v = fi[c], ug = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                v += gri[c][d] * gi.dvec[j][d];
+                ug += u[d] * gri[c][d];
+            }
+            I[c] = dt * v - 0.5 * dt * dt * ug;
+        }
+    } else {
+        // incoming from the wall (density rho_w) or the ghost Maxwellian
+        const double H = (F.bc == 3 ? rho_wj : 1.0) * e.pref * gauss(j, kx, u, e.lam, e.U);
+        I[0] = dt * H;
+        if constexpr (NC > 1) I[1] = dt * e.bh * H;
+    }
+}
+
+// Eq. microS1 for cell i at velocity k (source at t^n) into s1[c stride + ks]
+// for component c, and the moments of the net outflow (Eq. macroscopicFlux
+// summed over faces).
+template <int D, typename FT, bool TENSOR>
+__device__ __forceinline__ void stage1(const Params &p, const CellGeo<D> &gi, const CellStep<D> &cs, int k,
+                                       unsigned kx, const double (&u)[D], double u2, const double (&fi)[Dim<D>::NC],
+                                       const double (&out)[Dim<D>::NC], const Gauss<D, TENSOR> &gauss, FT *s1,
+                                       size_t stride, int ks, double (&mom)[D + 2])
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2;
+    double fpn[2];
+    {
+        const double H = cs.pref_n * gauss(MF, kx, u, cs.pn.lam, cs.pn.U);
+        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fpn[0], fpn[1]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        s1[(size_t)c * stride + ks] = from_f64<FT>(fi[c] - out[c] * gi.inv_vol + cs.hdt_tau * (fpn[c] - fi[c]));
+    const double wk = p.w[k];
+    mom[0] += wk * out[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
+    mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
+}
+
+// After pass 1 of cell i: W^{n+1} (Eq. macroscopicUpdata) from the reduced
+// moments, tau^{n+1}, q^{n+1} from the stage-1 values re-read, then stage 2
+// (Eq. microS2) and the single store of f^{n+1}; tab holds the cell's tables
+// (its own f+ table is refreshed for t^{n+1}).  Workgroup-wide.
+template <int D, typename FT, int BS, bool TENSOR>
+__device__ __forceinline__ void finish_cell(const Params &p, int i, const CellStep<D> &cs, double (&mom)[D + 2],
+                                            const FT *s1, double *red, double *tab, const Gauss<D, TENSOR> &gauss,
+                                            FT *__restrict__ fout)
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const int tid = threadIdx.x, nv = p.nv;
+    const double dt = p.dt, Pr = p.Pr;
+    const size_t base = (size_t)i * NC * nv;
+
+    // Alg. 1 line 10: Eq. macroscopicUpdata, then tau at t^{n+1}
+    block_reduce<BS>(mom, red, OpAdd{});
+    double W1[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) W1[m] = cs.Wn[m] - mom[m] * gi.inv_vol;
+    const Prim<D> p1 = to_prim<D>(W1);
+    const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
+
+    // heat flux of the stage-1 distribution about U^{n+1} (each thread
+    // re-reads the values it wrote)
+    double qt[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qt[d] = 0.0;
+    for (int k = tid; k < nv; k += BS) {
+        double c[D], c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            c[d] = p.u[d * nv + k] - p1.U[d];
+            c2 += c[d] * c[d];
+        }
+        const double h = to_f64(s1[k]);
+        const double b = NC > 1 ? to_f64(s1[(size_t)(NC - 1) * nv + k]) : 0.0;
+        const double wt = 0.5 * p.w[k] * (c2 * h + b);
+#pragma unroll
+        for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
+    }
+    block_reduce<BS>(qt, red, OpAdd{});
+    double q1[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q1[d] = qt[d] / (1.0 + Pr * dt / (2.0 * tau1));
+
+    if constexpr (TENSOR) {
+        // the cell's table now holds the factors of f+^{n+1}
+        const int ntab = p.ntab;
+        for (int idx = tid; idx < ntab; idx += BS) {
+            const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+            double Ud = p1.U[0];
+            if (ax == 1) Ud = p1.U[1];
+            if (D == 3 && ax == 2) Ud = p1.U[D - 1];
+            const double c = p.u1d[idx] - Ud;
+            tab[MF * ntab + idx] = exp(-p1.lam * c * c);
+        }
+        __syncthreads();
+    }
+
+    // Alg. 1 line 11: Eq. microS2
+    const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
+    const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
+    const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
+    const double bh_1 = Dim<D>::M / (2.0 * p1.lam);
+    for (int k = tid; k < nv; k += BS) {
+        double u[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) u[d] = p.u[d * nv + k];
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fp[2];
+        const double H = pref_1 * gauss(MF, kx, u, p1.lam, p1.U);
+        shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            fout[base + (size_t)c * nv + k] = from_f64<FT>((to_f64(s1[(size_t)c * nv + k]) + a1 * fp[c]) * inv1);
+        }
+    }
+    if (tid == 0) {
+        bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            ok = ok && isfinite(W1[m]);
+            p.W[(size_t)i * NW + m] = W1[m];
+            const double dw = W1[m] - cs.Wn[m];
+            p.dW2[(size_t)i * NW + m] = dw * dw;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.q[(size_t)i * D + d] = q1[d];
+        if (!ok) {
+            atomicOr(p.err, 1);
+            atomicMin(p.err + 1, i);
+        }
+    }
+}
+
+
 // PF: the own cell's stencil of the next velocity is loaded one iteration
 // ahead (20 more registers: used where they fit in the four-wave budget).
 template <int D, typename FT, int BS, bool TENSOR, bool S1L, bool PF>
@@ -1052,6 +1372,139 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     }
 }
 
+// ------------------------------------------------------------------------
+// In-place mode (one f buffer): the velocities are swept in chunks.  A chunk
+// kernel reads f^n of its velocities only (the cell's two-ring stencil),
+// parks the stage-1 values in a ring buffer of one chunk per cell and the
+// chunk's moments of the net outflow in a per-chunk record; the next chunk
+// kernel first writes its cell's ring back into f (no workgroup reads those
+// velocities any more), and a final kernel writes the last chunk, sums the
+// chunk moments in order (W^{n+1}), forms q^{n+1} from the stage-1 values
+// now in f, and applies stage 2 in place.  This is the paper's in-place
+// update of f (Section 3.2) with the ring as the only extra storage.  The
+// wall density of every wall cell is reduced over all velocities first.
+// ------------------------------------------------------------------------
+template <int D, typename FT, int BS, bool TENSOR>
+__global__ __launch_bounds__(BS) void k_wall_density(Params p, const FT *__restrict__ f)
+{
+    constexpr int MF = Dim<D>::MF, NT = MF + 1;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    if (!has_wall_face<D>(p, gi)) return;  // uniform: the whole workgroup leaves
+    const int ntab = TENSOR ? p.ntab : 0;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
+    __syncthreads();
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    double rho_w[MF];
+    wall_density<D, FT, BS, TENSOR>(p, gi, i, f, gauss, smem + NT * ntab, rho_w);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < MF; ++j) p.rho_w[(size_t)i * MF + j] = rho_w[j];
+}
+
+template <int D, typename FT, int BS, bool TENSOR>
+__global__ __launch_bounds__(BS) void k_sweep_chunk(Params p, FT *__restrict__ f, int c0, int cn, int prev0,
+                                                    int prevn, int ichunk)
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2, NT = MF + 1;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int tid = threadIdx.x, nv = p.nv;
+    const size_t ch = p.chunk;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    FT *ring = static_cast<FT *>(p.ring) + (size_t)i * NC * ch;
+    FT *fc = f + (size_t)i * NC * nv;
+    // the previous chunk's stage-1 values go back into f: every workgroup
+    // has finished reading those velocities
+    for (int t = tid; t < prevn; t += BS)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fc[(size_t)c * nv + prev0 + t] = ring[(size_t)c * ch + t];
+    const int ntab = TENSOR ? p.ntab : 0;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
+    __syncthreads();
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    double *red = smem + NT * ntab;
+    double rho_w[MF];
+#pragma unroll
+    for (int j = 0; j < MF; ++j) rho_w[j] = p.rho_w[(size_t)i * MF + j];
+
+    double mom[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+    for (int k = c0 + tid; k < c0 + cn; k += BS) {
+        double u[D], u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 += u[d] * u[d];
+        }
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fi[NC], gri[NC][D];
+        limited_slope<D, FT>(gi, i, f, nv, k, p.limiter, fi, gri);
+        double out[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c] = 0.0;
+#pragma unroll
+        for (int j = 0; j < MF; ++j) {
+            if (j >= gi.nf) break;
+            double un, I[NC], fn[NC], grn[NC][D];
+            bool nb_up;
+            face_integral<D, FT, TENSOR>(p, gi, j, k, kx, u, u2, fi, gri, rho_w[j], gauss, f, un, I, fn, grn, nb_up);
+            const double area = static_cast<const FaceGeo<D> *>(p.fgeo)[gi.face[j]].area;
+            const double sa = (gi.side[j] ? -area : area) * un;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) out[c] += sa * I[c];
+        }
+        // stage 1 into the ring (column k - c0 of the cell's chunk)
+        stage1<D, FT, TENSOR>(p, gi, cs, k, kx, u, u2, fi, out, gauss, ring, ch, k - c0, mom);
+    }
+    block_reduce<BS>(mom, red, OpAdd{});
+    if (tid == 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) p.mom_part[((size_t)i * p.nchunk + ichunk) * NW + m] = mom[m];
+}
+
+template <int D, typename FT, int BS, bool TENSOR>
+__global__ __launch_bounds__(BS) void k_sweep_finish(Params p, FT *__restrict__ f, int last0, int lastn)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int tid = threadIdx.x, nv = p.nv, ch = p.chunk;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const FT *ring = static_cast<const FT *>(p.ring) + (size_t)i * NC * ch;
+    FT *fc = f + (size_t)i * NC * nv;
+    for (int t = tid; t < lastn; t += BS)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fc[(size_t)c * nv + last0 + t] = ring[(size_t)c * ch + t];
+    const int ntab = TENSOR ? p.ntab : 0;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
+    // the chunks' moments, summed in velocity order (the same on every call)
+    double mom[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) {
+        double s = 0.0;
+        for (int q = 0; q < p.nchunk; ++q) s += p.mom_part[((size_t)i * p.nchunk + q) * NW + m];
+        mom[m] = s;
+    }
+    // block_reduce in finish_cell sums over the workgroup: only thread 0
+    // carries the moments
+    if (tid != 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+    __syncthreads();
+    constexpr int NT = Dim<D>::MF + 1;
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    finish_cell<D, FT, BS, TENSOR>(p, i, cs, mom, fc, smem + NT * ntab, smem, gauss, f);
+}
+
 template <int D, typename FT, int BS, bool TENSOR, bool S1L>
 __global__ __launch_bounds__(BS) void k_sweep(Params p, const FT *__restrict__ fin, FT *__restrict__ fout)
 {
@@ -1341,6 +1794,37 @@ template <int D, typename FT> hipError_t sweep_d(const Params &p, const void *fi
     else sweep_launch<D, FT, 256, false>(p, fi, fo, s);
     return hipGetLastError();
 }
+template <int D, typename FT, bool TENSOR> hipError_t inplace_d(const Params &p, void *fv, bool walls, hipStream_t s)
+{
+    constexpr int MF = Dim<D>::MF, NW = D + 2, NRED = (NW > 2 * MF) ? NW : 2 * MF;
+    const size_t lds = sizeof(double) * ((size_t)(MF + 1) * (TENSOR ? p.ntab : 0) + (256 / 64) * NRED);
+    const unsigned grid = (unsigned)sweep_grid(p.nc);
+    FT *f = static_cast<FT *>(fv);
+    if (walls) hipLaunchKernelGGL((k_wall_density<D, FT, 256, TENSOR>), dim3(grid), dim3(256), lds, s, p, f);
+    for (int q = 0; q < p.nchunk; ++q) {
+        const int c0 = q * p.chunk, cn = std::min(p.chunk, p.nv - c0);
+        const int prev0 = (q - 1) * p.chunk, prevn = q > 0 ? p.chunk : 0;
+        hipLaunchKernelGGL((k_sweep_chunk<D, FT, 256, TENSOR>), dim3(grid), dim3(256), lds, s, p, f, c0, cn, prev0,
+                           prevn, q);
+    }
+    const int last0 = (p.nchunk - 1) * p.chunk;
+    hipLaunchKernelGGL((k_sweep_finish<D, FT, 256, TENSOR>), dim3(grid), dim3(256), lds, s, p, f, last0,
+                       p.nv - last0);
+    return hipGetLastError();
+}
+template <int D, typename FT> hipError_t inplace_t(const Params &p, void *f, bool walls, hipStream_t s)
+{
+    return p.ntab > 0 ? inplace_d<D, FT, true>(p, f, walls, s) : inplace_d<D, FT, false>(p, f, walls, s);
+}
+hipError_t launch_sweep_inplace(const Params &p, void *f, bool walls, hipStream_t s)
+{
+    if (p.dim == 2)
+        return p.fstore == 2 ? inplace_t<2, bf16s>(p, f, walls, s)
+                             : (p.fstore ? inplace_t<2, float>(p, f, walls, s) : inplace_t<2, double>(p, f, walls, s));
+    return p.fstore == 2 ? inplace_t<3, bf16s>(p, f, walls, s)
+                         : (p.fstore ? inplace_t<3, float>(p, f, walls, s) : inplace_t<3, double>(p, f, walls, s));
+}
+
 hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s)
 {
     if (p.dim == 2)

@@ -19,6 +19,8 @@ UGKS_OK, UGKS_ERR_ARG, UGKS_ERR_ALLOC, UGKS_ERR_HIP, UGKS_ERR_NONPHYSICAL, UGKS_
 UGKS_F64, UGKS_F32, UGKS_BF16 = 0, 1, 2
 UGKS_BC_WALL = 3
 _FSTORE = {"f64": UGKS_F64, "f32": UGKS_F32, "bf16": UGKS_BF16}
+UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE = 0, 1
+_MEM = {"two-buffers": UGKS_MEM_TWO_BUFFERS, "in-place": UGKS_MEM_IN_PLACE}
 _ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
              -5: "UGKS_ERR_STATE"}
 
@@ -40,7 +42,8 @@ class ugks_vgrid_t(C.Structure):
 class ugks_gas_t(C.Structure):
     _fields_ = [("Pr", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double), ("cfl", C.c_double),
                 ("dt_override", C.c_double), ("limiter_k", C.c_double), ("limiter", C.c_int),
-                ("fstore", C.c_int), ("n_bc", C.c_int), ("bc_prim", _dp)]
+                ("fstore", C.c_int), ("n_bc", C.c_int), ("bc_prim", _dp), ("mem_mode", C.c_int),
+                ("chunk", C.c_int)]
 
 
 class UgksError(RuntimeError):
@@ -147,7 +150,7 @@ def current_stream_handle():
     return None
 
 
-def _structs(case, fstore, keep):
+def _structs(case, fstore, keep, mem="two-buffers", chunk=0):
     """ugks_mesh_t, ugks_vgrid_t, ugks_gas_t and prim0 for a case dict; the
     numpy buffers they point to are appended to keep."""
     m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
@@ -170,28 +173,30 @@ def _structs(case, fstore, keep):
     vgrid = ugks_vgrid_t(dim, len(vg["w"]), d(vg["u"]), d(vg["w"]))
     bc = np.asarray(gas["bc_prim"], dtype=np.float64)
     g = ugks_gas_t(gas["Pr"], gas["omega"], gas["mu_ref"], gas["cfl"], gas["dt_override"], gas["limiter_k"],
-                   int(gas["limiter"]), _FSTORE[fstore], bc.shape[0], d(bc))
+                   int(gas["limiter"]), _FSTORE[fstore], bc.shape[0], d(bc), _MEM[mem], int(chunk))
     return mesh, vgrid, g, d(case["prim0"])
 
 
-def footprint_estimate(case, fstore: str = "f64") -> int:
+def footprint_estimate(case, fstore: str = "f64", mem: str = "two-buffers", chunk: int = 0) -> int:
     """Device bytes ugks_create would allocate for this case (host only)."""
     L = load_library()
     keep = []
-    mesh, vgrid, g, _ = _structs(case, fstore, keep)
+    mesh, vgrid, g, _ = _structs(case, fstore, keep, mem, chunk)
     return int(L.ugks_footprint_estimate(C.byref(mesh), C.byref(vgrid), C.byref(g)))
 
 
 class Solver:
     """A flow case on the GPU: ugks_create ... ugks_destroy."""
 
-    def __init__(self, case, fstore: str = "f64", stream=None):
+    def __init__(self, case, fstore: str = "f64", stream=None, mem: str = "two-buffers", chunk: int = 0):
+        """mem: 'two-buffers' (f^n and f^{n+1} in separate buffers) or
+        'in-place' (one f buffer plus a ring of `chunk` velocities per cell)."""
         L = self._L = load_library()
         self.dim = int(case["mesh"]["dim"])
         self.nc = len(case["mesh"]["cell_volume"])
         self.nv = len(case["vgrid"]["w"])
         keep = []
-        mesh, vgrid, g, prim0 = _structs(case, fstore, keep)
+        mesh, vgrid, g, prim0 = _structs(case, fstore, keep, mem, chunk)
         if stream is None:
             stream = current_stream_handle()
         self.stream = stream

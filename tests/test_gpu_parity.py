@@ -621,3 +621,62 @@ def test_2d_unstructured_velocity_set_fp64():
     s.step(20)
     o.step(20)
     _compare(s, o)
+
+
+@pytest.mark.parametrize("name,chunk", [("periodic wave", 0), ("periodic wave", 100), ("periodic wave", 5000),
+                                        ("cylinder cut-down", 0), ("cylinder cut-down", 96), ("3D channel", 64),
+                                        ("scattered velocities", 10)])
+def test_in_place_mode_matches_the_oracle(name, chunk):
+    """UGKS_MEM_IN_PLACE: one f buffer updated in place, velocities swept in
+    chunks (two ragged chunks, several, one), walls and far field, Cartesian
+    and scattered velocity sets: parity with the oracle, and a footprint
+    that is the estimate's and, with a ring smaller than f, below the
+    two-buffer one."""
+    ugks = _gpu()
+    if name == "periodic wave":
+        c = cases.case_periodic_wave()
+    elif name == "cylinder cut-down":
+        c = cases.case_cylinder_small()
+    elif name == "3D channel":
+        c = cases.case_channel_3d(n=3, kind="prism", nv=8)
+    else:
+        c = cases.case_periodic_wave(nx=6, ny=6, nv=26, seed=4)
+        rng = np.random.default_rng(9)
+        u, w = c["vgrid"]["u"], c["vgrid"]["w"]
+        c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(u + rng.uniform(-1e-3, 1e-3, u.shape)), w=w)
+    _say(f"case {c['name']}: in place, chunk {chunk}, 10 steps")
+    s = ugks.Solver(c, mem="in-place", chunk=chunk)
+    two = ugks.Solver(c)
+    assert s.footprint_bytes == ugks.footprint_estimate(c, mem="in-place", chunk=chunk)
+    if min(chunk or 512, s.nv) < s.nv:     # a ring smaller than f
+        assert s.footprint_bytes < two.footprint_bytes
+    o = oracle.Oracle(c)
+    s.step(10)
+    o.step(10)
+    _compare(s, o)
+    two.close()
+
+
+def test_in_place_mode_storage_precision_and_restrictions():
+    """In place with FP32 f agrees with the two-buffer FP32 run to FP32
+    rounding; the wall flux and batching are refused for in-place handles."""
+    import ctypes
+    import torch
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    a = ugks.Solver(c, fstore="f32", mem="in-place", chunk=128)
+    b = ugks.Solver(c, fstore="f32")
+    a.step(8)
+    b.step(8)
+    eW, eq = macro_rel_err(*a.macros(), *b.macros())
+    assert eW < 1e-6 and eq < 1e-5, (eW, eq)
+    with pytest.raises(ugks.UgksError) as e:
+        a.wall_flux()
+    assert e.value.code == ugks.UGKS_ERR_STATE
+    stream = torch.cuda.Stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    batch = ugks.Batch(2, sh)
+    ip = ugks.Solver(c, mem="in-place", stream=sh)
+    with pytest.raises(ugks.UgksError):
+        batch.step([ip], 1)
+    batch.close()
