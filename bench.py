@@ -117,10 +117,10 @@ def cpu_baseline(case, target_s: float, max_steps: int):
                       f"({t:.1f} s, OpenMP over cells, gcc -O2), then 1 step on 1 thread ({t1:.1f} s)"}
 
 
-def run_gpu(case, fstore: str, steps: int, warmup: int):
+def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers", chunk: int = 0):
     import torch
     from paper_2412_06546_amd import ugks
-    s = ugks.Solver(case, fstore=fstore)
+    s = ugks.Solver(case, fstore=fstore, mem=mem, chunk=chunk)
     nc, nv, ncomp = s.nc, s.nv, s.ncomp
     s.step(warmup)
     torch.cuda.synchronize()
@@ -185,6 +185,9 @@ def main():
                     help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities); "
                          "spherehex: the same shell as 50,688 hexahedra; "
                          "liftingbody: the X38-sized case (1,058,685 cells x 4,548 velocities, no CPU baseline)")
+    ap.add_argument("--mem", choices=["two-buffers", "in-place"], default="two-buffers",
+                    help="f in two buffers (f^n, f^{n+1}) or one buffer updated in place by velocity chunks")
+    ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -218,17 +221,17 @@ def main():
             "liftingbody": cases.case_lifting_body}[args.workload]()
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
-    main_run = run_gpu(case, args.fstore, args.steps, args.warmup)
+    main_run = run_gpu(case, args.fstore, args.steps, args.warmup, args.mem, args.chunk)
     print(f"# gpu {args.fstore}: {main_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     other = []
     if not args.no_secondary:
         for fs2 in [x for x in ("f64", "f32", "bf16") if x != args.fstore]:
-            r2 = run_gpu(case, fs2, max(5, args.steps // 2), args.warmup)
+            r2 = run_gpu(case, fs2, max(5, args.steps // 2), args.warmup, args.mem, args.chunk)
             other.append({"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
                           "sweep_ms": r2["sweep_ms_avg"], "achieved_gbs": r2["achieved_gbs"]})
             print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
-    traffic = measured_traffic(args.fstore) if args.workload == "cylinder" else None
+    traffic = measured_traffic(args.fstore) if args.workload == "cylinder" and args.mem == "two-buffers" else None
     # the sweep is bound by the vector ALUs (about 75 % busy, profiles/k_sweep_cylinder20k_valu.txt), not by HBM
     dim = int(case["mesh"]["dim"])
     nf_avg = float(np.bincount(np.concatenate([case["mesh"]["face_cells"][:, 0],
@@ -240,7 +243,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "k_sweep", "kernel_ms": round(main_run["sweep_ms_avg"], 4),
+                "kernel": "k_sweep" if args.mem == "two-buffers" else "k_sweep_chunk (every chunk) + k_sweep_finish",
+                "kernel_ms": round(main_run["sweep_ms_avg"], 4),
                 "alg_flops_per_update": round(fpu, 1), "alg_flops_per_launch": alg_flops,
                 "hbm": {"achieved": round(main_run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(main_run["achieved_gbs"] / HBM_PEAK_GBS, 4),
@@ -265,7 +269,7 @@ def main():
                        "spherehex": "3D sphere (hexahedra) Ma 4 Kn 0.05 Shakhov, isothermal wall",
                        "liftingbody": "3D X38-sized lifting body Ma 8 AoA 20 Kn 0.01 Shakhov, wall 5.39 T_inf, "
                                       "unstructured velocity set"}[args.workload],
-                   "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64",
+                   "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64", "mem": args.mem,
                    "prologue_ms": round(main_run["prologue_ms_avg"], 4),
                    "footprint_bytes": main_run["footprint_bytes"]},
         "roofline": roofline,

@@ -866,111 +866,6 @@ __device__ __forceinline__ void wall_density(const Params &p, const CellGeo<D> &
     for (int j = 0; j < MF; ++j) rho_w[j] = (j < nf && wsum[2 * j + 1] != 0.0) ? -wsum[2 * j] / wsum[2 * j + 1] : 0.0;
 }
 
-// Time-integrated distribution through face slot j of cell i at velocity k
-// (Eq. fullSolution on interior faces, free transport out of and the wall or
-// ghost Maxwellian into the domain on boundary faces); fi, gri: the cell's
-// own value and limited slope.  When the neighbour is upwind of an interior
-// face its limited slope is built here from its own stencil -- bit-identical
-// to what the neighbour computes for itself -- and returned in fn, grn
-// (nb_up = true).  The flux through the face is (side ? -S : S) un I.
-template <int D, typename FT, bool TENSOR>
-__device__ __forceinline__ void face_integral(const Params &p, const CellGeo<D> &gi, int j, int k, unsigned kx,
-                                              const double (&u)[D], double u2, const double (&fi)[Dim<D>::NC],
-                                              const double (&gri)[Dim<D>::NC][D], double rho_wj,
-                                              const Gauss<D, TENSOR> &gauss, const FT *__restrict__ fin, double &un,
-                                              double (&I)[Dim<D>::NC], double (&fn)[Dim<D>::NC],
-                                              double (&grn)[Dim<D>::NC][D], bool &nb_up)
-{
-    constexpr int NC = Dim<D>::NC;
-    const CellGeo<D> *cg = static_cast<const CellGeo<D> *>(p.cgeo);
-    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
-    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
-    const double dt = p.dt;
-    const int f = gi.face[j];
-    const FaceGeo<D> &F = fg[f];
-    const FaceEq<D> &e = fe[f];
-    un = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) un += u[d] * F.n[d];
-    nb_up = false;
-    if (F.bc == 0) {
-        const bool self_up = (un > 0.0) == (gi.side[j] == 0);
-        double val[NC], ug[NC];
-        if (self_up) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                val[c] = fi[c];
-                ug[c] = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    val[c] += gri[c][d] * gi.dvec[j][d];
-                    ug[c] += u[d] * gri[c][d];
-                }
-            }
-        } else {
-            const int n = gi.nb[j];
-            const CellGeo<D> &gn = cg[n];
-            const int bj = gi.back[j];
-            limited_slope<D, FT>(gn, n, fin, p.nv, k, p.limiter, fn, grn);
-            nb_up = true;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                val[c] = fn[c];
-                ug[c] = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    val[c] += grn[c][d] * gn.dvec[bj][d];
-                    ug[c] += u[d] * grn[c][d];
-                }
-            }
-        }
-        const double H0 = e.pref * gauss(j, kx, u, e.lam, e.U);
-        interface_integral<D>(e, u, u2, H0, val, ug, I);
-    } else if (un > 0.0) {
-        // outgoing through a wall or far-field face: free transport
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double v = fi[c], ug = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                v += gri[c][d] * gi.dvec[j][d];
-                ug += u[d] * gri[c][d];
-            }
-            I[c] = dt * v - 0.5 * dt * dt * ug;
-        }
-    } else {
-        // incoming from the wall (density rho_w) or the ghost Maxwellian
-        const double H = (F.bc == 3 ? rho_wj : 1.0) * e.pref * gauss(j, kx, u, e.lam, e.U);
-        I[0] = dt * H;
-        if constexpr (NC > 1) I[1] = dt * e.bh * H;
-    }
-}
-
-// Eq. microS1 for cell i at velocity k (source at t^n) into s1[c stride + ks]
-// for component c, and the moments of the net outflow (Eq. macroscopicFlux
-// summed over faces).
-template <int D, typename FT, bool TENSOR>
-__device__ __forceinline__ void stage1(const Params &p, const CellGeo<D> &gi, const CellStep<D> &cs, int k,
-                                       unsigned kx, const double (&u)[D], double u2, const double (&fi)[Dim<D>::NC],
-                                       const double (&out)[Dim<D>::NC], const Gauss<D, TENSOR> &gauss, FT *s1,
-                                       size_t stride, int ks, double (&mom)[D + 2])
-{
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2;
-    double fpn[2];
-    {
-        const double H = cs.pref_n * gauss(MF, kx, u, cs.pn.lam, cs.pn.U);
-        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fpn[0], fpn[1]);
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-        s1[(size_t)c * stride + ks] = from_f64<FT>(fi[c] - out[c] * gi.inv_vol + cs.hdt_tau * (fpn[c] - fi[c]));
-    const double wk = p.w[k];
-    mom[0] += wk * out[0];
-#pragma unroll
-    for (int d = 0; d < D; ++d) mom[1 + d] += wk * u[d] * out[0];
-    mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
-}
-
 // After pass 1 of cell i: W^{n+1} (Eq. macroscopicUpdata) from the reduced
 // moments, tau^{n+1}, q^{n+1} from the stage-1 values re-read, then stage 2
 // (Eq. microS2) and the single store of f^{n+1}; tab holds the cell's tables
@@ -1070,8 +965,13 @@ __device__ __forceinline__ void finish_cell(const Params &p, int i, const CellSt
 
 // PF: the own cell's stencil of the next velocity is loaded one iteration
 // ahead (20 more registers: used where they fit in the four-wave budget).
-template <int D, typename FT, int BS, bool TENSOR, bool S1L, bool PF>
-__device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ fout)
+// CHUNK: the in-place mode's chunk kernel -- pass 1 over velocities
+// [c0, c0 + cn) only, reading f^n and writing the stage-1 values to the ring
+// (after writing the previous chunk's ring back into f), the chunk's moments
+// to its record, and the wall densities read from the wall kernel's array.
+template <int D, typename FT, int BS, bool TENSOR, bool S1L, bool PF, bool CHUNK = false>
+__device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ fout,
+                                           int c0 = 0, int cn = 0, int prev0 = 0, int prevn = 0, int ichunk = 0)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, M = Dim<D>::M, NW = D + 2;
     constexpr int NT = MF + 1;  // Gaussian tables: one per face slot, one for the cell
@@ -1089,7 +989,20 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
     const size_t base = (size_t)i * NC * nv;
     constexpr int NRED = (NW > 2 * MF) ? NW : 2 * MF;
-    FT *s1 = S1L ? reinterpret_cast<FT *>(red + (BS / 64) * NRED) : fout + base;
+    // stage-1 values: LDS, f_out, or (chunk mode) the cell's ring, as
+    // s1[c s1_stride + k - s1_off] for component c at velocity k
+    FT *s1 = CHUNK ? static_cast<FT *>(p.ring) + (size_t)i * NC * p.chunk
+                   : (S1L ? reinterpret_cast<FT *>(red + (BS / 64) * NRED) : fout + base);
+    const size_t s1_stride = CHUNK ? (size_t)p.chunk : (size_t)nv;
+    const int s1_off = CHUNK ? c0 : 0;
+    const int k_end = CHUNK ? c0 + cn : nv;
+    if constexpr (CHUNK) {
+        // the previous chunk's stage-1 values go back into f (no workgroup
+        // reads those velocities any more)
+        for (int t = tid; t < prevn; t += BS)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fout[base + (size_t)c * nv + prev0 + t] = s1[(size_t)c * s1_stride + t];
+    }
 
     // state at t^n
     double Wn[NW];
@@ -1106,7 +1019,8 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     const double bh_n = Dim<D>::M / (2.0 * pn.lam);
 
     int has_wall = 0;
-    for (int j = 0; j < nf; ++j) has_wall |= (fg[gi.face[j]].bc == 3);
+    if constexpr (!CHUNK)
+        for (int j = 0; j < nf; ++j) has_wall |= (fg[gi.face[j]].bc == 3);
 
     if constexpr (TENSOR) {
         // one-dimensional Gaussian factors of every face's Maxwellian and of f+^n
@@ -1139,7 +1053,7 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     // reflected particles directly.
     double rho_w[MF];
 #pragma unroll
-    for (int j = 0; j < MF; ++j) rho_w[j] = 0.0;
+    for (int j = 0; j < MF; ++j) rho_w[j] = CHUNK ? p.rho_w[(size_t)i * MF + j] : 0.0;
     if (has_wall) {
         double wsum[2 * MF];
 #pragma unroll
@@ -1185,8 +1099,8 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
 #pragma unroll
     for (int m = 0; m < NW; ++m) mom[m] = 0.0;
     double pv0[NC], pvn[MF][NC];
-    if (PF && tid < nv) load_stencil<D, FT>(gi, i, fin, nv, tid, pv0, pvn);
-    for (int k = tid; k < nv; k += BS) {
+    if (PF && s1_off + tid < k_end) load_stencil<D, FT>(gi, i, fin, nv, s1_off + tid, pv0, pvn);
+    for (int k = s1_off + tid; k < k_end; k += BS) {
         double v0[NC], vn[MF][NC];
         if constexpr (PF) {
 #pragma unroll
@@ -1195,7 +1109,7 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
 #pragma unroll
                 for (int j = 0; j < MF; ++j) vn[j][m] = pvn[j][m];
             }
-            if (k + BS < nv) load_stencil<D, FT>(gi, i, fin, nv, k + BS, pv0, pvn);
+            if (k + BS < k_end) load_stencil<D, FT>(gi, i, fin, nv, k + BS, pv0, pvn);
         }
         double u[D], u2 = 0.0;
 #pragma unroll
@@ -1283,7 +1197,8 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            s1[(size_t)c * nv + k] = from_f64<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
+            s1[(size_t)c * s1_stride + (k - s1_off)] =
+                from_f64<FT>(fi[c] - out[c] * gi.inv_vol + hdt_tau * (fpn[c] - fi[c]));
         // moments of the net outflow (Eq. macroscopicFlux summed over faces)
         const double wk = p.w[k];
         mom[0] += wk * out[0];
@@ -1294,6 +1209,12 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
 
     // Alg. 1 line 10: Eq. macroscopicUpdata, then tau at t^{n+1}
     block_reduce<BS>(mom, red, OpAdd{});
+    if constexpr (CHUNK) {
+        if (tid == 0)
+#pragma unroll
+            for (int m = 0; m < NW; ++m) p.mom_part[((size_t)i * p.nchunk + ichunk) * NW + m] = mom[m];
+        return;
+    }
     double W1[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) W1[m] = Wn[m] - mom[m] * gi.inv_vol;
@@ -1405,68 +1326,15 @@ __global__ __launch_bounds__(BS) void k_wall_density(Params p, const FT *__restr
         for (int j = 0; j < MF; ++j) p.rho_w[(size_t)i * MF + j] = rho_w[j];
 }
 
+// The chunk sweep under the four-wave budget; the next velocity's stencil is
+// prefetched for FP32 and BF16 f (with FP64 f the prefetch registers would
+// spill: measured 8.9 against 7.7 ms per step on the cylinder).
 template <int D, typename FT, int BS, bool TENSOR>
-__global__ __launch_bounds__(BS) void k_sweep_chunk(Params p, FT *__restrict__ f, int c0, int cn, int prev0,
-                                                    int prevn, int ichunk)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep_chunk(
+    Params p, FT *__restrict__ f, int c0, int cn, int prev0, int prevn, int ichunk)
 {
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2, NT = MF + 1;
-    extern __shared__ double smem[];
-    const int i = xcd_cell(blockIdx.x);
-    if (i >= p.nc) return;
-    const int tid = threadIdx.x, nv = p.nv;
-    const size_t ch = p.chunk;
-    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
-    FT *ring = static_cast<FT *>(p.ring) + (size_t)i * NC * ch;
-    FT *fc = f + (size_t)i * NC * nv;
-    // the previous chunk's stage-1 values go back into f: every workgroup
-    // has finished reading those velocities
-    for (int t = tid; t < prevn; t += BS)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) fc[(size_t)c * nv + prev0 + t] = ring[(size_t)c * ch + t];
-    const int ntab = TENSOR ? p.ntab : 0;
-    const CellStep<D> cs = cell_step<D>(p, i);
-    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
-    __syncthreads();
-    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
-    double *red = smem + NT * ntab;
-    double rho_w[MF];
-#pragma unroll
-    for (int j = 0; j < MF; ++j) rho_w[j] = p.rho_w[(size_t)i * MF + j];
-
-    double mom[NW];
-#pragma unroll
-    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
-    for (int k = c0 + tid; k < c0 + cn; k += BS) {
-        double u[D], u2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            u[d] = p.u[d * nv + k];
-            u2 += u[d] * u[d];
-        }
-        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-        double fi[NC], gri[NC][D];
-        limited_slope<D, FT>(gi, i, f, nv, k, p.limiter, fi, gri);
-        double out[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) out[c] = 0.0;
-#pragma unroll
-        for (int j = 0; j < MF; ++j) {
-            if (j >= gi.nf) break;
-            double un, I[NC], fn[NC], grn[NC][D];
-            bool nb_up;
-            face_integral<D, FT, TENSOR>(p, gi, j, k, kx, u, u2, fi, gri, rho_w[j], gauss, f, un, I, fn, grn, nb_up);
-            const double area = static_cast<const FaceGeo<D> *>(p.fgeo)[gi.face[j]].area;
-            const double sa = (gi.side[j] ? -area : area) * un;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) out[c] += sa * I[c];
-        }
-        // stage 1 into the ring (column k - c0 of the cell's chunk)
-        stage1<D, FT, TENSOR>(p, gi, cs, k, kx, u, u2, fi, out, gauss, ring, ch, k - c0, mom);
-    }
-    block_reduce<BS>(mom, red, OpAdd{});
-    if (tid == 0)
-#pragma unroll
-        for (int m = 0; m < NW; ++m) p.mom_part[((size_t)i * p.nchunk + ichunk) * NW + m] = mom[m];
+    constexpr bool PF = TENSOR && sizeof(FT) < sizeof(double);
+    sweep_cell<D, FT, BS, TENSOR, false, PF, true>(p, xcd_cell(blockIdx.x), f, f, c0, cn, prev0, prevn, ichunk);
 }
 
 template <int D, typename FT, int BS, bool TENSOR>
