@@ -680,3 +680,30 @@ def test_in_place_mode_storage_precision_and_restrictions():
     with pytest.raises(ugks.UgksError):
         batch.step([ip], 1)
     batch.close()
+
+
+def test_in_place_mode_async_steps_and_checkpoint():
+    """In place: asynchronous steps equal synchronous ones bit for bit; a
+    checkpoint taken after 4 steps and restored in a fresh in-place handle
+    continues exactly, and in a two-buffer handle (the state does not depend
+    on the memory mode) to the rounding of the velocity sums."""
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    a = ugks.Solver(c, mem="in-place", chunk=200)
+    b = ugks.Solver(c, mem="in-place", chunk=200)
+    a.step(4)
+    b.step_async(4)
+    while b.poll() is None:
+        pass
+    assert np.array_equal(a.f(), b.f())
+    blob = a.get_state()
+    a.step(3)
+    r = ugks.Solver(c, mem="in-place", chunk=200)
+    r.set_state(blob)
+    r.step(3)
+    assert np.array_equal(a.f(), r.f()) and np.array_equal(a.macros()[0], r.macros()[0])
+    t = ugks.Solver(c)
+    t.set_state(blob)
+    t.step(3)
+    eW, eq = macro_rel_err(*t.macros(), *a.macros())
+    assert eW <= TOL and eq <= TOL, (eW, eq)
