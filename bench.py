@@ -187,7 +187,7 @@ def main():
                          "liftingbody: the X38-sized case (1,058,685 cells x 4,548 velocities, no CPU baseline)")
     ap.add_argument("--mem", choices=["two-buffers", "in-place"], default="two-buffers",
                     help="f in two buffers (f^n, f^{n+1}) or one buffer updated in place by velocity chunks")
-    ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = 512)")
+    ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = the library default, 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -274,6 +274,9 @@ def main():
                    "footprint_bytes": main_run["footprint_bytes"]},
         "roofline": roofline,
     }
+    if args.mem == "in-place":
+        from paper_2412_06546_amd.ugks import UGKS_DEFAULT_CHUNK
+        line["config"]["chunk"] = min(args.chunk if args.chunk > 0 else UGKS_DEFAULT_CHUNK, nv)
     if other:
         line["other_precision"] = other
     if not args.no_cpu_baseline and args.workload != "liftingbody":

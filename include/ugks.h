@@ -108,7 +108,7 @@ typedef struct {
     int n_bc;
     const double *bc_prim; /* [n_bc][dim+2]: (rho, U, T); walls use (U_w, T_w) */
     int mem_mode;       /* UGKS_MEM_TWO_BUFFERS or UGKS_MEM_IN_PLACE (below) */
-    int chunk;          /* in-place mode: velocities per chunk, 0 = 512 */
+    int chunk;          /* in-place mode: velocities per chunk, 0 = UGKS_DEFAULT_CHUNK */
 } ugks_gas_t;
 
 /* Storage of f.  UGKS_MEM_TWO_BUFFERS: f^n is read from one buffer and
@@ -123,6 +123,10 @@ typedef struct {
  * a step (ugks_wall_flux returns UGKS_ERR_STATE). */
 #define UGKS_MEM_TWO_BUFFERS 0
 #define UGKS_MEM_IN_PLACE 1
+/* Velocities per chunk when gas.chunk is 0 (capped at n_vel).  Every chunk
+ * launch repeats the per-cell set-up, so fewer, larger chunks are faster and
+ * cost a larger ring (n_cells x n_comp x chunk values of f). */
+#define UGKS_DEFAULT_CHUNK 512
 
 typedef struct ugks ugks_t;
 

@@ -430,7 +430,7 @@ template <int D> void create_d(ugks_t *h, const StoredMesh &S, const ugks_gas_t 
 // allocates; the temporary initial-state buffer is not counted).
 template <typename T> size_t nbytes(size_t n) { return sizeof(T) * (n ? n : 1); }
 // in-place mode: velocities per chunk (0 asks for the default) and chunk count
-int chunk_of(int chunk, int nv) { return std::min(chunk > 0 ? chunk : 512, nv); }
+int chunk_of(int chunk, int nv) { return std::min(chunk > 0 ? chunk : UGKS_DEFAULT_CHUNK, nv); }
 int nchunk_of(int chunk, int nv) { return (nv + chunk - 1) / chunk; }
 
 size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab, size_t nwallf,

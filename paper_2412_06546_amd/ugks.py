@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(HERE, "libugks.so")
 
 UGKS_OK, UGKS_ERR_ARG, UGKS_ERR_ALLOC, UGKS_ERR_HIP, UGKS_ERR_NONPHYSICAL, UGKS_ERR_STATE = 0, -1, -2, -3, -4, -5
 UGKS_F64, UGKS_F32, UGKS_BF16 = 0, 1, 2
-UGKS_BC_WALL = 3
+UGKS_BC_INTERIOR, UGKS_BC_INFLOW, UGKS_BC_OUTFLOW, UGKS_BC_WALL = 0, 1, 2, 3
 _FSTORE = {"f64": UGKS_F64, "f32": UGKS_F32, "bf16": UGKS_BF16}
 UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE = 0, 1
 _MEM = {"two-buffers": UGKS_MEM_TWO_BUFFERS, "in-place": UGKS_MEM_IN_PLACE}
+UGKS_DEFAULT_CHUNK = 512
 _ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
              -5: "UGKS_ERR_STATE"}
 

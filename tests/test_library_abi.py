@@ -21,6 +21,18 @@ def test_header_declares_the_core_entry_points():
         assert n in names
 
 
+def test_binding_constants_are_the_headers():
+    """Every integer constant the header defines has the same value in the
+    Python binding (status codes, storage and memory modes, boundary types,
+    the default chunk)."""
+    from paper_2412_06546_amd import ugks
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "ugks.h")).read(), flags=re.S)
+    defs = dict(re.findall(r"^#define\s+(UGKS_[A-Z0-9_]+)\s+\(?(-?\d+)\)?\s*$", text, flags=re.M))
+    assert len(defs) >= 16 and "UGKS_DEFAULT_CHUNK" in defs and "UGKS_ERR_STATE" in defs
+    mismatched = {k: (v, getattr(ugks, k, None)) for k, v in defs.items() if getattr(ugks, k, None) != int(v)}
+    assert not mismatched, mismatched
+
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libugks.so not built")
 def test_library_exports_every_declared_symbol():
     import ctypes
