@@ -232,7 +232,7 @@ def main():
             print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     traffic = measured_traffic(args.fstore) if args.workload == "cylinder" and args.mem == "two-buffers" else None
-    # the sweep is bound by the vector ALUs (about 75 % busy, profiles/k_sweep_cylinder20k_valu.txt), not by HBM
+    # the sweep is bound by the vector ALUs (about 73 % busy, profiles/k_sweep_cylinder20k_valu.txt), not by HBM
     dim = int(case["mesh"]["dim"])
     nf_avg = float(np.bincount(np.concatenate([case["mesh"]["face_cells"][:, 0],
                                                case["mesh"]["face_cells"][:, 1][case["mesh"]["face_cells"][:, 1] >= 0]]),

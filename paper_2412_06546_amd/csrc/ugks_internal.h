@@ -59,6 +59,10 @@ template <int D> struct alignas(16) FaceEq {
     double A[NW];         // time slope of g0
     double q[D];          // interface heat flux
     double c[5];          // time integrals of c1..c5 over the step
+    // the step and (dt / 2) dt for the free-transport and boundary fluxes; the
+    // sweep reads them with the face's other scalars, as the kernel argument
+    // kept live across the velocity loop costs scalar-register spill reloads
+    double dt, hdt2;
 };
 
 struct Params {

@@ -598,6 +598,8 @@ __device__ __forceinline__ void face_eq(const Params p, int f)
     if (f >= p.nf) return;
     const FaceGeo<D> &F = static_cast<const FaceGeo<D> *>(p.fgeo)[f];
     FaceEq<D> &e = static_cast<FaceEq<D> *>(p.feq)[f];
+    e.dt = p.dt;
+    e.hdt2 = 0.5 * p.dt * p.dt;
     if (F.bc != 0) {
         // boundary: store the Maxwellian the incoming particles come from
         double rho, U[D], lam;
@@ -1177,13 +1179,13 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
                         v += gri[c][d] * gi.dvec[j][d];
                         ug += u[d] * gri[c][d];
                     }
-                    I[c] = dt * v - 0.5 * dt * dt * ug;
+                    I[c] = e.dt * v - e.hdt2 * ug;
                 }
             } else {
                 // incoming from the wall (density rho_w) or the ghost Maxwellian
                 const double H = (F.bc == 3 ? rho_w[j] : 1.0) * e.pref * gauss(j, kx, u, e.lam, e.U);
-                I[0] = dt * H;
-                if constexpr (NC > 1) I[1] = dt * e.bh * H;
+                I[0] = e.dt * H;
+                if constexpr (NC > 1) I[1] = e.dt * e.bh * H;
             }
             const double sa = (gi.side[j] ? -F.area : F.area) * un;
 #pragma unroll
