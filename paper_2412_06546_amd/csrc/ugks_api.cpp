@@ -31,7 +31,7 @@ struct ugks {
     // since creation or set_f (f[1 - cur] then holds the f that started it)
     int mem_mode = UGKS_MEM_TWO_BUFFERS;
     void *ring = nullptr;          // in-place mode: one chunk of stage-1 values per cell
-    double *mom_part = nullptr;    // in-place mode: per-chunk moments
+    double *mom_part = nullptr;    // in-place mode: moments of the chunks swept so far
     double *rho_w = nullptr;       // in-place mode: wall densities
     int n_wallf = 0;
     int *wallf = nullptr;
@@ -444,10 +444,10 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
     b += nbytes<double>(nc) + nbytes<double>(NW) + nbytes<int>(2);
     if (ntab) b += nbytes<double>(ntab) + nbytes<int>(nv);
     if (mem_mode == UGKS_MEM_IN_PLACE) {
-        const int ch = chunk_of(chunk, (int)nv), nq = nchunk_of(ch, (int)nv);
+        const int ch = chunk_of(chunk, (int)nv);
         b += nc * ncomp * nv * fvalue_bytes(fstore);                      // f
         b += nbytes<char>(nc * ncomp * (size_t)ch * fvalue_bytes(fstore));  // ring
-        b += nbytes<double>(nc * (size_t)nq * NW) + nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
+        b += nbytes<double>(nc * (size_t)NW) + nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
     } else {
         b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
     }
@@ -623,7 +623,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             chunk = chunk_of(gas->chunk, h->nv);
             nchunk = nchunk_of(chunk, h->nv);
             h->ring = dev_alloc<char>(h, nc * h->ncomp * (size_t)chunk * fvalue_bytes(h->fstore));
-            h->mom_part = dev_alloc<double>(h, nc * (size_t)nchunk * (D + 2));
+            h->mom_part = dev_alloc<double>(h, nc * (size_t)(D + 2));
             h->rho_w = dev_alloc<double>(h, nc * (size_t)(D == 2 ? Dim<2>::MF : Dim<3>::MF));
             hip_check(hipMemsetAsync(h->rho_w, 0, sizeof(double) * nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF),
                                      h->stream), "hipMemsetAsync");

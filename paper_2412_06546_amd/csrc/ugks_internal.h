@@ -87,8 +87,9 @@ struct Params {
     double *dW2;       // [nc][dim+2] squared change of W in the last step
     int *err;          // [2]: flag, first bad cell
     // in-place mode (one f buffer): stage-1 values of the current velocity
-    // chunk [cell][component][chunk], each chunk's moments of the net outflow
-    // [cell][nchunk][dim+2], wall densities [cell][MF]
+    // chunk [cell][component][chunk], the moments of the net outflow of the
+    // chunks swept so far, summed in chunk order [cell][dim+2], wall densities
+    // [cell][MF]
     void *ring;
     int chunk, nchunk;
     double *mom_part, *rho_w;

@@ -1212,9 +1212,13 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     // Alg. 1 line 10: Eq. macroscopicUpdata, then tau at t^{n+1}
     block_reduce<BS>(mom, red, OpAdd{});
     if constexpr (CHUNK) {
-        if (tid == 0)
+        // add this chunk's moments to the cell's sum; the chunks run one
+        // launch after another, so the sum is taken in chunk order
+        if (tid == 0) {
+            double *acc = p.mom_part + (size_t)i * NW;
 #pragma unroll
-            for (int m = 0; m < NW; ++m) p.mom_part[((size_t)i * p.nchunk + ichunk) * NW + m] = mom[m];
+            for (int m = 0; m < NW; ++m) acc[m] = (ichunk == 0 ? 0.0 : acc[m]) + mom[m];
+        }
         return;
     }
     double W1[NW];
@@ -1356,14 +1360,10 @@ __global__ __launch_bounds__(BS) void k_sweep_finish(Params p, FT *__restrict__ 
     const int ntab = TENSOR ? p.ntab : 0;
     const CellStep<D> cs = cell_step<D>(p, i);
     if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
-    // the chunks' moments, summed in velocity order (the same on every call)
+    // the chunks' moments, summed in chunk order by the chunk kernels
     double mom[NW];
 #pragma unroll
-    for (int m = 0; m < NW; ++m) {
-        double s = 0.0;
-        for (int q = 0; q < p.nchunk; ++q) s += p.mom_part[((size_t)i * p.nchunk + q) * NW + m];
-        mom[m] = s;
-    }
+    for (int m = 0; m < NW; ++m) mom[m] = p.mom_part[(size_t)i * NW + m];
     // block_reduce in finish_cell sums over the workgroup: only thread 0
     // carries the moments
     if (tid != 0)

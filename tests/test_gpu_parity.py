@@ -624,14 +624,14 @@ def test_2d_unstructured_velocity_set_fp64():
 
 
 @pytest.mark.parametrize("name,chunk", [("periodic wave", 0), ("periodic wave", 100), ("periodic wave", 5000),
-                                        ("cylinder cut-down", 0), ("cylinder cut-down", 96), ("3D channel", 64),
-                                        ("scattered velocities", 10)])
+                                        ("periodic wave", 1), ("cylinder cut-down", 0), ("cylinder cut-down", 96),
+                                        ("3D channel", 64), ("3D channel", 1), ("scattered velocities", 10)])
 def test_in_place_mode_matches_the_oracle(name, chunk):
     """UGKS_MEM_IN_PLACE: one f buffer updated in place, velocities swept in
-    chunks (two ragged chunks, several, one), walls and far field, Cartesian
-    and scattered velocity sets: parity with the oracle, and a footprint
-    that is the estimate's and, with a ring smaller than f, below the
-    two-buffer one."""
+    chunks (two ragged chunks, several, one, one velocity per chunk), walls
+    and far field, Cartesian and scattered velocity sets: parity with the
+    oracle, and a footprint that is the estimate's and, with a ring smaller
+    than f, below the two-buffer one."""
     ugks = _gpu()
     if name == "periodic wave":
         c = cases.case_periodic_wave()
