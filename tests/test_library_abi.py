@@ -132,3 +132,28 @@ def test_binding_leaves_one_hip_runtime_in_the_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.split() == ["1", "1"], out.stdout
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libugks.so not built")
+@pytest.mark.parametrize("dim", [2, 3])
+def test_in_place_footprint_is_one_f_plus_the_ring(dim):
+    """Host-side estimate (exactly what ugks_create allocates): the in-place
+    form needs one f plus a ring of `chunk` velocities per cell, and nothing
+    that grows with the number of chunks, so even one velocity per chunk
+    stays below the two-buffer form; chunks beyond n_vel are capped."""
+    from paper_2412_06546_amd import cases, ugks
+    c = cases.case_periodic_wave() if dim == 2 else cases.case_channel_3d(n=3, kind="prism", nv=8)
+    nc, nv = len(c["mesh"]["cell_volume"]), len(c["vgrid"]["w"])
+    ncomp = 2 if dim == 2 else 1
+    two = ugks.footprint_estimate(c, "f64", "two-buffers")
+    one = {ch: ugks.footprint_estimate(c, "f64", "in-place", ch) for ch in (1, 2, nv, 10 * nv)}
+    f_bytes = nc * ncomp * nv * 8
+    assert one[1] < one[2] < one[nv] == one[10 * nv]
+    assert one[1] < two
+    # beyond one f and the ring: the moment sum and the wall densities,
+    # a few doubles per cell (plus allocation rounding)
+    extra = one[1] - (two - f_bytes) - nc * ncomp * 8
+    assert 0 < extra <= nc * 16 * 8 + 4096
+    # the ring is the only part that grows with the chunk
+    ring_growth = nc * ncomp * (nv - 1) * 8
+    assert ring_growth <= one[nv] - one[1] <= ring_growth + 4096
