@@ -117,7 +117,8 @@ typedef struct {
  * two-stage form (Section 3.2): the velocities are swept in chunks, the
  * stage-1 values of a chunk wait in a ring of n_cells x n_comp x chunk
  * values until no cell reads that chunk's f^n any more, and stage 2 is
- * applied in place; memory 1 f + the ring.  Both forms give the same
+ * applied in place; memory 1 f + the ring + a few doubles per cell (the
+ * chunks' moment sum and the wall densities).  Both forms give the same
  * results up to the order of the sums over velocities.  In-place handles
  * cannot be batched (ugks_batch_step) and keep no copy of the f that started
  * a step (ugks_wall_flux returns UGKS_ERR_STATE). */
