@@ -80,7 +80,9 @@ def lib():
         L.orc_time_slope_of_g0.argtypes = [C.c_int, _dp, _dp, _dp]
         L.orc_venkat.restype = C.c_double
         L.orc_venkat.argtypes = [C.c_double, C.c_double, C.c_double]
-        L.orc_gauss_hermite.argtypes = [C.c_int, _dp, _dp]
+        L.orc_gauss_hermite.restype = C.c_int
+        L.orc_gauss_hermite.argtypes = [_dp, _dp]
+        L.orc_macro_gradients.argtypes = [C.c_void_p, _dp, _ip]
         _lib = L
     return _lib
 
@@ -171,7 +173,18 @@ class Oracle:
         assert a.shape == (self.nc, self.ncomp, self.nv)
         self._L.orc_set_f(self._h, p)
 
+    def macro_gradients(self):
+        """Limited gradients of W for the current state (Alg. 1 line 2),
+        [nc][dim + 2][dim], and per cell whether it fell back to first
+        order (a reconstructed face state not physical)."""
+        g = np.zeros((self.nc, self.dim + 2, self.dim))
+        bad = np.zeros(self.nc, dtype=np.int32)
+        self._L.orc_macro_gradients(self._h, g.ctypes.data_as(_dp), bad.ctypes.data_as(_ip))
+        return g, bad.astype(bool)
+
     def residual(self):
+        """Per conservative component, the L2 norm over cells of W^{n+1} - W^n
+        in the last step."""
         r = np.zeros(self.dim + 2)
         self._L.orc_residual(self._h, r.ctypes.data_as(_dp))
         return r
@@ -251,7 +264,9 @@ def venkat(dm, dp, eps2):
     return lib().orc_venkat(float(dm), float(dp), float(eps2))
 
 
-def gauss_hermite(n):
-    x, w = np.zeros(n), np.zeros(n)
-    lib().orc_gauss_hermite(int(n), x.ctypes.data_as(_dp), w.ctypes.data_as(_dp))
+def gauss_hermite():
+    """The oracle's 4-point Gauss-Hermite rule (weight e^{-x^2})."""
+    x, w = np.zeros(4), np.zeros(4)
+    n = lib().orc_gauss_hermite(x.ctypes.data_as(_dp), w.ctypes.data_as(_dp))
+    assert n == 4
     return x, w

@@ -159,39 +159,22 @@ static void reduced_eq(int D, const double *p, const double *q, double Pr, const
 }
 
 /* ------------------------------------------------------------------------ */
-/* Gaussian moments by product Gauss-Hermite quadrature (exact for the      */
-/* polynomial degrees used here).  Nodes by Newton iteration on the         */
-/* orthonormal Hermite recurrence.                                          */
+/* Gaussian moments by product Gauss-Hermite quadrature with weight e^{-x^2} */
+/* and 4 nodes per dimension, exact for polynomials of degree 7 (the        */
+/* moments used here reach degree 5).  The nodes are the roots of the       */
+/* Hermite polynomial H_4(x) = 16x^4 - 48x^2 + 12, i.e. x^2 = (3 -+ sqrt 6)/2, */
+/* and the weights are sqrt(pi) 2^{n-1} n! / (n^2 H_{n-1}(x)^2) with n = 4,  */
+/* which simplifies to sqrt(pi) / (4 (3 -+ sqrt 6)).  Nodes ascending.       */
 /* ------------------------------------------------------------------------ */
-static void gauss_hermite(int n, double *x, double *wt)
+static void gauss_hermite4(double *x, double *wt)
 {
-    const double pim4 = pow(M_PI, -0.25);
-    int m = (n + 1) / 2;
-    double z = 0.0;
-    for (int i = 0; i < m; ++i) {
-        if (i == 0) z = sqrt(2.0 * n + 1.0) - 1.85575 * pow(2.0 * n + 1.0, -0.16667);
-        else if (i == 1) z -= 1.14 * pow((double)n, 0.426) / z;
-        else if (i == 2) z = 1.86 * z - 0.86 * x[0];
-        else if (i == 3) z = 1.91 * z - 0.91 * x[1];
-        else z = 2.0 * z - x[i - 2];
-        double pp = 0.0;
-        for (int it = 0; it < 100; ++it) {
-            double p1 = pim4, p2 = 0.0;
-            for (int j = 0; j < n; ++j) {
-                double p3 = p2;
-                p2 = p1;
-                p1 = z * sqrt(2.0 / (j + 1)) * p2 - sqrt((double)j / (j + 1)) * p3;
-            }
-            pp = sqrt(2.0 * n) * p2;
-            double z1 = z;
-            z = z1 - p1 / pp;
-            if (fabs(z - z1) <= 1e-15 * fabs(z) + 1e-300) break;
-        }
-        x[i] = z;
-        x[n - 1 - i] = -z;
-        wt[i] = 2.0 / (pp * pp);
-        wt[n - 1 - i] = wt[i];
-    }
+    const double s6 = sqrt(6.0), sp = sqrt(M_PI);
+    const double xin = sqrt((3.0 - s6) / 2.0), xout = sqrt((3.0 + s6) / 2.0);
+    const double win = sp / (4.0 * (3.0 - s6)), wout = sp / (4.0 * (3.0 + s6));
+    x[0] = -xout; wt[0] = wout;
+    x[1] = -xin;  wt[1] = win;
+    x[2] = xin;   wt[2] = win;
+    x[3] = xout;  wt[3] = wout;
 }
 
 /* psi = (1, u, (|u|^2 + |xi|^2)/2) at a point (u, xi) */
@@ -214,7 +197,7 @@ static void maxwell_moments(int D, int M, const double *U, double lam, const dou
                             double *mat, double *rhs)
 {
     double gx[ORC_GH], gw[ORC_GH];
-    gauss_hermite(ORC_GH, gx, gw);
+    gauss_hermite4(gx, gw);
     int N = D + M, NW = D + 2, tot = 1;
     for (int d = 0; d < N; ++d) tot *= ORC_GH;
     double s = 1.0 / sqrt(lam), norm = pow(M_PI, -0.5 * N);
@@ -692,6 +675,34 @@ void orc_wall_flux(const orc_t *o, double *out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Alg. 1 line 2: limited least-squares gradients of the conservative       */
+/* variables [nc][NW][D].  A cell whose reconstructed state at any of its   */
+/* face centroids has rho <= 0 or internal energy <= 0 falls back to first  */
+/* order (zero gradient); fell_back[i] (if given) records it.               */
+/* ------------------------------------------------------------------------ */
+static void macro_gradients(const orc_t *o, double *gW, int *fell_back)
+{
+    const int D = o->D, NW = o->NW, nc = o->nc;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nc; ++i) {
+        for (int m = 0; m < NW; ++m) limited_gradient(o, i, o->W + m, NW, gW + ((size_t)i * NW + m) * D);
+        int bad = 0;
+        for (int fl = 0; fl < o->ncf[i] && !bad; ++fl) {
+            const double *r = o->dcf + ((size_t)i * ORC_MAXF + fl) * D;
+            double Wf[ORC_MAXW], ke = 0.0;
+            for (int m = 0; m < NW; ++m) {
+                Wf[m] = o->W[(size_t)i * NW + m];
+                for (int a = 0; a < D; ++a) Wf[m] += gW[((size_t)i * NW + m) * D + a] * r[a];
+            }
+            for (int d = 0; d < D; ++d) ke += Wf[1 + d] * Wf[1 + d];
+            if (!(Wf[0] > 0.0) || !(Wf[D + 1] - 0.5 * ke / Wf[0] > 0.0)) bad = 1;
+        }
+        if (bad) memset(gW + (size_t)i * NW * D, 0, sizeof(double) * NW * D);
+        if (fell_back) fell_back[i] = bad;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* one time step (Algorithm 1)                                              */
 /* ------------------------------------------------------------------------ */
 static void one_step(orc_t *o)
@@ -708,25 +719,9 @@ static void one_step(orc_t *o)
         tau[i] = tau_of_prim(o, prim + (size_t)i * NW);
     }
 
-    /* line 2: limited gradients of the conservative variables; a cell whose
-     * reconstructed face state is not physical falls back to first order */
+    /* line 2: limited gradients of the conservative variables */
     double *gW = (double *)calloc((size_t)nc * NW * D, sizeof(double));
-#pragma omp parallel for schedule(static)
-    for (int i = 0; i < nc; ++i) {
-        for (int m = 0; m < NW; ++m) limited_gradient(o, i, o->W + m, NW, gW + ((size_t)i * NW + m) * D);
-        int bad = 0;
-        for (int fl = 0; fl < o->ncf[i] && !bad; ++fl) {
-            const double *r = o->dcf + ((size_t)i * ORC_MAXF + fl) * D;
-            double Wf[ORC_MAXW], ke = 0.0;
-            for (int m = 0; m < NW; ++m) {
-                Wf[m] = o->W[(size_t)i * NW + m];
-                for (int a = 0; a < D; ++a) Wf[m] += gW[((size_t)i * NW + m) * D + a] * r[a];
-            }
-            for (int d = 0; d < D; ++d) ke += Wf[1 + d] * Wf[1 + d];
-            if (!(Wf[0] > 0.0) || !(Wf[D + 1] - 0.5 * ke / Wf[0] > 0.0)) bad = 1;
-        }
-        if (bad) memset(gW + (size_t)i * NW * D, 0, sizeof(double) * NW * D);
-    }
+    macro_gradients(o, gW, NULL);
 
     /* line 3: interface equilibrium and time coefficients */
     orc_face_eq_t *fe = (orc_face_eq_t *)calloc(nf, sizeof(orc_face_eq_t));
@@ -1029,4 +1024,12 @@ void orc_time_slope_of_g0(int D, const double *p, const double *a, double *A)
     time_slope_of_g0(D, 3 - D, p, (const double(*)[ORC_MAXW])aa, A);
 }
 double orc_venkat(double dm, double dp, double eps2) { return venkat(dm, dp, eps2); }
-void orc_gauss_hermite(int n, double *x, double *w) { gauss_hermite(n, x, w); }
+/* line 2 of Algorithm 1 for the current state: gW [nc][D+2][D], and per
+ * cell whether it fell back to first order */
+void orc_macro_gradients(const orc_t *o, double *gW, int *fell_back) { macro_gradients(o, gW, fell_back); }
+/* the 4-point rule (returns the number of nodes written: 4) */
+int orc_gauss_hermite(double *x, double *w)
+{
+    gauss_hermite4(x, w);
+    return ORC_GH;
+}

@@ -142,10 +142,18 @@ def test_prim_cons_round_trip():
 # Gauss-Hermite rule used for continuous Gaussian moments
 # --------------------------------------------------------------------------
 def test_gauss_hermite_exact_to_degree_7():
-    x, w = oracle.gauss_hermite(4)
+    x, w = oracle.gauss_hermite()
     for m in range(8):
         exact = 0.0 if m % 2 else math.gamma((m + 1) / 2)
         assert (w * x ** m).sum() == pytest.approx(exact, abs=1e-14)
+    # a 4-point rule: the degree-8 moment is not exact
+    assert abs((w * x ** 8).sum() - math.gamma(4.5)) > 1.0
+    # the nodes are the roots of the Hermite polynomial H_4 and the rule is
+    # numpy's (an independent library routine)
+    assert np.abs(np.polynomial.hermite.hermval(x, [0, 0, 0, 0, 1])).max() < 1e-12
+    xr, wr = np.polynomial.hermite.hermgauss(4)
+    np.testing.assert_allclose(x, xr, rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(w, wr, rtol=1e-14)
 
 
 # --------------------------------------------------------------------------
