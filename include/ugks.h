@@ -131,7 +131,9 @@ typedef struct {
 
 typedef struct ugks ugks_t;
 
-/* Create a case.  prim0 [n_cells][dim+2] holds the initial (rho, U, T) of
+/* Create a case: the discretised problem of Section 2.3 (finite volumes and
+ * a discrete velocity set) with the gas of Sections 2.1-2.2.
+ * prim0 [n_cells][dim+2] holds the initial (rho, U, T) of
  * each cell; f^0 is the discrete Maxwellian of it, and W^0 and q^0 are the
  * discrete moments of f^0.  stream is a hipStream_t (NULL = default stream).
  * The time step is fixed at creation (the velocity grid does not change):
@@ -151,14 +153,17 @@ typedef struct ugks ugks_t;
 int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas,
                 const double *prim0, void *stream, ugks_t **out);
 
-/* Advance nsteps time steps (Algorithm 1 each).  residual_out (nullable,
- * [dim+2]) receives the L2 norm over cells of W^{n+1} - W^n of the last
- * step, per conservative component.  Returns UGKS_ERR_NONPHYSICAL if a cell
+/* Advance nsteps time steps (Algorithm 1 each, Section 3.2).  residual_out
+ * (nullable, [dim+2]) receives the L2 norm over cells of W^{n+1} - W^n of
+ * the last step, per conservative component, W^{n+1} from
+ * Eq. macroscopicUpdata (the steady-state measure of a run to convergence).  Returns UGKS_ERR_NONPHYSICAL if a cell
  * lost positivity or finiteness (checked once at the end of the call). */
 int ugks_step(ugks_t *h, int nsteps, double *residual_out);
 
 /* Asynchronous stepping, for serving several cases at once on different
- * streams.  ugks_step_async enqueues nsteps steps (as ugks_step) plus the
+ * streams (each step is Algorithm 1, Section 3.2; the paper's concern with
+ * the memory of many large cases is Sections 3.2 and 4.3).
+ * ugks_step_async enqueues nsteps steps (as ugks_step) plus the
  * copies of the non-physical flag and of the last step's residual into
  * handle-owned pinned host memory, and returns without waiting.  Only one
  * batch may be outstanding per handle (UGKS_ERR_STATE otherwise).
@@ -168,7 +173,8 @@ int ugks_step(ugks_t *h, int nsteps, double *residual_out);
 int ugks_step_async(ugks_t *h, int nsteps);
 int ugks_poll(ugks_t *h, int *done, double *residual_out);
 
-/* Batched stepping (continuous batching of many cases on one GPU): the
+/* Batched stepping (continuous batching of many cases on one GPU; each
+ * step is Algorithm 1 of Section 3.2 for every case): the
  * steps of several handles run in the same launches -- one grid per kernel
  * holds the cells (or faces) of every case end to end, each workgroup finds
  * its case from a table of per-case offsets -- so small cases fill the GPU
@@ -189,24 +195,33 @@ const char *ugks_batch_last_error(const ugks_batch_t *b);
 void ugks_batch_destroy(ugks_batch_t *b);
 
 /* Device bytes ugks_create would allocate for these inputs (host-side
- * computation, no GPU needed): admission control against an HBM budget.
+ * computation, no GPU needed): admission control against an HBM budget
+ * (the memory of f per cell and velocity dominates, as in the accounting of
+ * Section 4.3).
  * Returns 0 for invalid arguments. */
 size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, const ugks_gas_t *gas);
 
 /* Copy the conservative variables W [n_cells][dim+2] = (rho, rho U, rho E)
- * and the heat flux q [n_cells][dim] (nullable) to host memory. */
+ * (the moments of f with psi = (1, u, (|u|^2 + |xi|^2)/2), Section 2.1) and
+ * the heat flux q [n_cells][dim] (nullable; the Shakhov heat flux of
+ * Section 2.1, carried from step to step as in Alg. 1 line 1) to host
+ * memory. */
 int ugks_macros(ugks_t *h, double *W_out, double *q_out);
 
-/* Copy f to host memory as FP64 [n_cells][n_comp][n_vel] (n_comp = 2 in 2D:
- * h then b; 1 in 3D). */
+/* Copy f to host memory as FP64 [n_cells][n_comp][n_vel]: the reduced
+ * distributions of Section 2.2 at the discrete velocities of Section 2.3
+ * (n_comp = 2 in 2D: h then b; 1 in 3D). */
 int ugks_get_f(ugks_t *h, double *f_out);
 
 /* Replace f with a host array laid out as in ugks_get_f; W and q become its
- * discrete moments (checkpoint restart or a non-equilibrium start), and a
+ * discrete moments (Sections 2.1 and 2.3: checkpoint restart or a
+ * non-equilibrium start), and a
  * non-physical flag left by an earlier step is cleared. */
 int ugks_set_f(ugks_t *h, const double *f_in);
 
-/* Checkpoint and restart, exact: the state blob holds W, q, f in its
+/* Checkpoint and restart, exact: the state blob holds what Algorithm 1
+ * carries from one step to the next (Section 3.2: f, the conservative
+ * variables W and the heat flux q), f in its
  * storage precision and the library's order, and the step count.
  * ugks_state_bytes gives its size; ugks_get_state writes it to a host
  * buffer of at least that size; ugks_set_state restores it into a handle
@@ -219,14 +234,22 @@ size_t ugks_state_bytes(const ugks_t *h);
 int ugks_get_state(ugks_t *h, void *buf, size_t bytes);
 int ugks_set_state(ugks_t *h, const void *buf, size_t bytes);
 
-double ugks_dt(const ugks_t *h);            /* time step, or -1 for a NULL handle */
-int ugks_n_comp(const ugks_t *h);           /* stored components per (cell, velocity) */
-long ugks_step_count(const ugks_t *h);      /* steps taken since creation */
-size_t ugks_footprint_bytes(const ugks_t *h); /* device bytes owned by the handle */
-int ugks_is_tensor_grid(const ugks_t *h);   /* 1 if Gaussians are tabulated per axis (few distinct
-                                               coordinate values per axis), 0 if evaluated directly */
+/* Time step of Alg. 1 line 1 (from the CFL condition, fixed for the run),
+ * or -1 for a NULL handle. */
+double ugks_dt(const ugks_t *h);
+/* Stored reduced distributions per (cell, velocity) (Section 2.2): 2 (h, b)
+ * in 2D, 1 (h) in 3D. */
+int ugks_n_comp(const ugks_t *h);
+/* Steps of Algorithm 1 taken since creation (or restored by a state). */
+long ugks_step_count(const ugks_t *h);
+/* Device bytes owned by the handle (the memory accounting of Section 4.3). */
+size_t ugks_footprint_bytes(const ugks_t *h);
+/* 1 if the Gaussians over the velocity set of Section 2.3 are tabulated per
+ * axis (few distinct coordinate values per axis), 0 if evaluated directly. */
+int ugks_is_tensor_grid(const ugks_t *h);
 
-/* Timing of the step's kernels with HIP events on the handle's stream.
+/* Timing of the step's kernels with HIP events on the handle's stream (the
+ * per-step wall time the paper reports in Table UGKSeff).
  * ugks_profile(h, 1) resets the counters and records events around every
  * launch from then on (0 stops).  ugks_profile_read gives ms_out[0] = total
  * milliseconds in the fused sweep kernel, ms_out[1] = total in the two
@@ -251,13 +274,26 @@ int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
 int ugks_n_wall_faces(const ugks_t *h);
 int ugks_wall_flux(ugks_t *h, double *out);
 
-/* The library stores velocities in its own order (by direction, so that the
- * lanes of a wavefront agree on upwind sides).  perm_out [n_vel] receives,
+/* Surface coefficients of every wall face in the last step (Section 2.5 for
+ * the wall flux and the surface pressure, shear stress and heat flux;
+ * Section 4.1 for the coefficients).  out [n_wall][6], wall faces in
+ * increasing (caller's) face index as in ugks_wall_flux:
+ *   p_w = F_m . n, sigma_w = |F_m - p_w n|, q_w = energy flux,
+ *   Cp = p_w / d, Ct = sigma_w / d, Ch = q_w / (d u_inf),
+ * with F the wall flux per unit area and time of ugks_wall_flux, n the
+ * face normal (out of the gas) and d = rho_inf u_inf^2 / 2.  All computed on
+ * the device.  rho_inf and u_inf must be positive and finite (UGKS_ERR_ARG);
+ * same state conditions as ugks_wall_flux (UGKS_ERR_STATE). */
+int ugks_surface(ugks_t *h, double rho_inf, double u_inf, double *out);
+
+/* The library stores the velocity set of Section 2.3 in its own order (by
+ * direction, so that the lanes of a wavefront agree on upwind sides).  perm_out [n_vel] receives,
  * for each stored position, the caller's velocity index.  ugks_get_f and
  * ugks_set_f use the caller's order. */
 int ugks_velocity_order(const ugks_t *h, int *perm_out);
 
-/* The library stores cells in its own order too: along a Morton (Z-order)
+/* The library stores the cells of the mesh (Section 2.3) in its own order
+ * too: along a Morton (Z-order)
  * curve through the cell centroids, so that consecutive stored cells -- the
  * workgroups that share one XCD's L2 cache -- are mesh neighbours whatever
  * the caller's numbering.  perm_out [n_cells] receives, for each stored
@@ -266,13 +302,18 @@ int ugks_velocity_order(const ugks_t *h, int *perm_out);
  * the cell named by an error) uses the caller's numbering. */
 int ugks_cell_order(const ugks_t *h, int *perm_out);
 
-/* Device pointer of the current f (for zero-copy inspection):
+/* Device pointer of the current f, the reduced distributions of Section 2.2
+ * (for zero-copy inspection):
  * [n_cells][n_comp][n_vel] in the storage precision, the library's cell
  * order (ugks_cell_order) and velocity order (ugks_velocity_order); valid
  * until the next ugks_step or ugks_destroy. */
 const void *ugks_device_f(const ugks_t *h);
 
+/* Free the handle and all its device memory (ownership as stated at the top
+ * of this file); NULL is ignored. */
 void ugks_destroy(ugks_t *h);
+/* Text of the last failure on h (NULL: of the last failed ugks_create or
+ * ugks_batch_create of the calling thread); valid until the next call on h. */
 const char *ugks_last_error(const ugks_t *h);
 
 #ifdef __cplusplus

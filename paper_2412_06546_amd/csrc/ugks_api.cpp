@@ -35,7 +35,7 @@ struct ugks {
     double *rho_w = nullptr;       // in-place mode: wall densities
     int n_wallf = 0;
     int *wallf = nullptr;
-    double *wallF = nullptr;
+    double *wallF = nullptr, *surf = nullptr;
     int stepped = 0;
     double dt = 0.0;
     long nstep = 0;
@@ -441,7 +441,7 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
                       : nbytes<CellGeo<3>>(nc) + nbytes<FaceGeo<3>>(nf) + nbytes<FaceEq<3>>(nf);
     b += nbytes<double>(D * nv) + nbytes<double>(nv) + nbytes<double>((size_t)std::max(1, nbc) * NW);
     b += nbytes<double>(nc * NW) + nbytes<double>(nc * D) + nbytes<double>(nc * NW * D) + nbytes<double>(nc * NW);
-    b += nbytes<double>(nc) + nbytes<double>(NW) + nbytes<int>(2);
+    b += nbytes<double>(nc) + nbytes<double>(NW * (1 + (size_t)residual_groups((int)nc))) + nbytes<int>(2);
     if (ntab) b += nbytes<double>(ntab) + nbytes<int>(nv);
     if (mem_mode == UGKS_MEM_IN_PLACE) {
         const int ch = chunk_of(chunk, (int)nv);
@@ -451,7 +451,7 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
     } else {
         b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
     }
-    b += nbytes<int>(nwallf) + nbytes<double>(nwallf * NW);
+    b += nbytes<int>(nwallf) + nbytes<double>(nwallf * NW) + nbytes<double>(nwallf * 6);
     return b;
 }
 
@@ -497,7 +497,7 @@ void release(ugks_t *h)
     if (h->h_res) (void)hipHostFree(h->h_res);
     if (h->done_ev) (void)hipEventDestroy(h->done_ev);
     void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
-                    h->cell_dt, h->res, h->err, h->u1d, h->kidx, h->wallf, h->wallF, h->ring, h->mom_part, h->rho_w};
+                    h->cell_dt, h->res, h->err, h->u1d, h->kidx, h->wallf, h->wallF, h->surf, h->ring, h->mom_part, h->rho_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -590,7 +590,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         h->gW = dev_alloc<double>(h, nc * (D + 2) * D);
         h->dW2 = dev_alloc<double>(h, nc * (D + 2));
         h->cell_dt = dev_alloc<double>(h, nc);
-        h->res = dev_alloc<double>(h, D + 2);
+        h->res = dev_alloc<double>(h, (D + 2) * (1 + (size_t)residual_groups((int)nc)));
         h->err = dev_alloc<int>(h, 2);
         {
             std::vector<std::pair<int, int>> wf;  // (caller's face, stored face)
@@ -602,6 +602,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             h->n_wallf = (int)list.size();
             h->wallf = dev_alloc<int>(h, list.size());
             h->wallF = dev_alloc<double>(h, list.size() * (D + 2));
+            h->surf = dev_alloc<double>(h, list.size() * 6);
             if (!list.empty()) upload(h->wallf, list.data(), sizeof(int) * list.size(), h->stream);
         }
         if (h->tensor) {
@@ -1032,6 +1033,32 @@ extern "C" int ugks_wall_flux(ugks_t *h, double *out)
             hip_check(launch_wall_flux(h->P, h->f[1 - h->cur], h->wallf, h->n_wallf, h->wallF, h->stream), "wall flux launch");
             hip_check(hipMemcpyAsync(out, h->wallF, sizeof(double) * h->n_wallf * (h->dim + 2), hipMemcpyDeviceToHost,
                                      h->stream), "copy wall flux");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        }
+    } catch (const Fail &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, Fail{UGKS_ERR_ALLOC, std::string("host: ") + e.what()});
+    }
+    return UGKS_OK;
+}
+
+extern "C" int ugks_surface(ugks_t *h, double rho_inf, double u_inf, double *out)
+{
+    if (!h || !out) return UGKS_ERR_ARG;
+    if (!(rho_inf > 0.0) || !(u_inf > 0.0) || !std::isfinite(rho_inf) || !std::isfinite(u_inf))
+        return fail(h, Fail{UGKS_ERR_ARG, "rho_inf and u_inf must be positive and finite"});
+    if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
+    if (!h->stepped) return fail(h, Fail{UGKS_ERR_STATE, "no step since creation or ugks_set_f"});
+    if (h->mem_mode == UGKS_MEM_IN_PLACE)
+        return fail(h, Fail{UGKS_ERR_STATE, "an in-place handle keeps no copy of the f that started the step"});
+    try {
+        if (h->n_wallf) {
+            hip_check(launch_wall_flux(h->P, h->f[1 - h->cur], h->wallf, h->n_wallf, h->wallF, h->stream), "wall flux launch");
+            hip_check(launch_surface(h->P, h->wallf, h->wallF, h->n_wallf, rho_inf, u_inf, h->surf, h->stream),
+                      "surface launch");
+            hip_check(hipMemcpyAsync(out, h->surf, sizeof(double) * h->n_wallf * 6, hipMemcpyDeviceToHost, h->stream),
+                      "copy surface quantities");
             hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         }
     } catch (const Fail &e) {

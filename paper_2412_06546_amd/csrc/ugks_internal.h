@@ -126,8 +126,15 @@ hipError_t launch_sweep(const Params &p, const void *f_in, void *f_out, hipStrea
 // the in-place step's sweep: wall densities (if walls), one kernel per
 // velocity chunk, the final kernel; f is read and updated in place
 hipError_t launch_sweep_inplace(const Params &p, void *f, bool walls, hipStream_t s);
+// L2 norm over cells of the last change of W: out[0..D+2) receives it and
+// out[D+2 ..) holds residual_groups(nc) * (D+2) partial sums
+constexpr int kResidualGroups = 256;
+int residual_groups(int nc);
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s);
 // macroscopic flux [n][dim+2] through the wall faces faces[0..n) in the step that started from f
 hipError_t launch_wall_flux(const Params &p, const void *f, const int *faces, int n, double *out, hipStream_t s);
+// surface quantities [n][6] (p_w, sigma_w, q_w, Cp, Ct, Ch) from the wall flux [n][dim+2]
+hipError_t launch_surface(const Params &p, const int *faces, const double *flux, int n, double rho_inf, double u_inf,
+                          double *out, hipStream_t s);
 
 }  // namespace ugx

@@ -1489,10 +1489,43 @@ __device__ __forceinline__ void residual(const Params p, double *out)
         for (int m = 0; m < NW; ++m) out[m] = sqrt(s[m]);
 }
 
+// One case: workgroup g sums the squared changes of a contiguous range of
+// cells into part[g] (fixed order), then one workgroup sums the partial sums
+// in order and takes the square roots.  Deterministic, and spread over the
+// chip instead of one compute unit.
 template <int D>
-__global__ __launch_bounds__(256) void k_residual(Params p, double *out)
+__global__ __launch_bounds__(256) void k_residual_part(Params p, double *part, int per)
 {
-    residual<D>(p, out);
+    constexpr int NW = D + 2;
+    __shared__ double lds[4 * NW];
+    double s[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) s[m] = 0.0;
+    const int i0 = blockIdx.x * per, i1 = min(p.nc, i0 + per);
+    for (int i = i0 + threadIdx.x; i < i1; i += 256)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) s[m] += p.dW2[(size_t)i * NW + m];
+    block_reduce<256>(s, lds, OpAdd{});
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) part[(size_t)blockIdx.x * NW + m] = s[m];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_residual_final(const double *__restrict__ part, int ng, double *out)
+{
+    constexpr int NW = D + 2;
+    __shared__ double lds[4 * NW];
+    double s[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) s[m] = 0.0;
+    for (int g = threadIdx.x; g < ng; g += 256)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) s[m] += part[(size_t)g * NW + m];
+    block_reduce<256>(s, lds, OpAdd{});
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) out[m] = sqrt(s[m]);
 }
 
 // ------------------------------------------------------------------------
@@ -1704,6 +1737,52 @@ hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s
                          : (p.fstore ? sweep_d<3, float>(p, fi, fo, s) : sweep_d<3, double>(p, fi, fo, s));
 }
 
+// Surface quantities of Section 2.5 from the wall flux of the last step (per
+// unit area and time), one thread per wall face: surface pressure
+// p_w = F_m . n (n out of the gas), shear stress sigma_w = |F_m - p_w n|,
+// heat flux q_w = the energy component, and the coefficients of
+// Section 4.1: Cp = p_w / d, Ct = sigma_w / d, Ch = q_w / (d u_inf) with
+// d = rho_inf u_inf^2 / 2.  out [n][6].
+template <int D>
+__global__ __launch_bounds__(256) void k_surface(Params p, const int *__restrict__ wall_faces,
+                                                 const double *__restrict__ flux, int n, double rho_inf, double u_inf,
+                                                 double *__restrict__ out)
+{
+    constexpr int NW = D + 2;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const FaceGeo<D> &F = static_cast<const FaceGeo<D> *>(p.fgeo)[wall_faces[t]];
+    const double *w = flux + (size_t)t * NW;
+    double pw = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) pw += w[1 + d] * F.n[d];
+    double s2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double tang = w[1 + d] - pw * F.n[d];
+        s2 += tang * tang;
+    }
+    const double sig = sqrt(s2), qw = w[NW - 1];
+    const double dyn = 0.5 * rho_inf * u_inf * u_inf;
+    double *o = out + (size_t)t * 6;
+    o[0] = pw;
+    o[1] = sig;
+    o[2] = qw;
+    o[3] = pw / dyn;
+    o[4] = sig / dyn;
+    o[5] = qw / (dyn * u_inf);
+}
+
+hipError_t launch_surface(const Params &p, const int *faces, const double *flux, int n, double rho_inf, double u_inf,
+                          double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((n + 255) / 256);
+    if (p.dim == 2) hipLaunchKernelGGL(k_surface<2>, grid, dim3(256), 0, s, p, faces, flux, n, rho_inf, u_inf, out);
+    else hipLaunchKernelGGL(k_surface<3>, grid, dim3(256), 0, s, p, faces, flux, n, rho_inf, u_inf, out);
+    return hipGetLastError();
+}
+
 template <int D, typename FT>
 hipError_t wall_flux_d(const Params &p, const void *f, const int *faces, int n, double *out, hipStream_t s)
 {
@@ -1776,10 +1855,19 @@ hipError_t launch_batch_residual(const BatchItem *items, int n, int dim, hipStre
     return hipGetLastError();
 }
 
+int residual_groups(int nc) { return std::max(1, std::min(kResidualGroups, (nc + 2047) / 2048)); }
+
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s)
 {
-    if (p.dim == 2) hipLaunchKernelGGL(k_residual<2>, dim3(1), dim3(256), 0, s, p, out);
-    else hipLaunchKernelGGL(k_residual<3>, dim3(1), dim3(256), 0, s, p, out);
+    const int ng = residual_groups(p.nc), per = (p.nc + ng - 1) / ng;
+    double *part = out + (p.dim + 2);
+    if (p.dim == 2) {
+        hipLaunchKernelGGL(k_residual_part<2>, dim3(ng), dim3(256), 0, s, p, part, per);
+        hipLaunchKernelGGL(k_residual_final<2>, dim3(1), dim3(256), 0, s, part, ng, out);
+    } else {
+        hipLaunchKernelGGL(k_residual_part<3>, dim3(ng), dim3(256), 0, s, p, part, per);
+        hipLaunchKernelGGL(k_residual_final<3>, dim3(1), dim3(256), 0, s, part, ng, out);
+    }
     return hipGetLastError();
 }
 

@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     L.ugks_n_wall_faces.argtypes = [C.c_void_p]
     L.ugks_wall_flux.restype = C.c_int
     L.ugks_wall_flux.argtypes = [C.c_void_p, _dp]
+    L.ugks_surface.restype = C.c_int
+    L.ugks_surface.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp]
     L.ugks_cell_order.restype = C.c_int
     L.ugks_cell_order.argtypes = [C.c_void_p, _ip]
     L.ugks_device_f.restype = C.c_void_p
@@ -206,8 +208,6 @@ class Solver:
         _check(L, None, code)
         self._h = h
         self.ncomp = L.ugks_n_comp(h)
-        m = case["mesh"]
-        self.wall_normals = np.asarray(m["face_normal"])[np.asarray(m["face_bc"]) == UGKS_BC_WALL].copy()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -292,17 +292,13 @@ class Solver:
 
     def surface(self, rho_inf: float, u_inf: float):
         """Surface pressure, shear stress and heat flux of every wall face in
-        the last step, and the coefficients Cp, Ct, Ch (Section 4.1): the
-        first two divided by rho_inf u_inf^2 / 2, the heat flux by
-        rho_inf u_inf^3 / 2."""
-        F = self.wall_flux()
-        n = self.wall_normals
-        Fm = F[:, 1:1 + self.dim]
-        p = (Fm * n).sum(1)
-        sigma = np.linalg.norm(Fm - p[:, None] * n, axis=1)
-        qw = F[:, -1]
-        d = 0.5 * rho_inf * u_inf ** 2
-        return {"p": p, "sigma": sigma, "q": qw, "Cp": p / d, "Ct": sigma / d, "Ch": qw / (d * u_inf)}
+        the last step and the coefficients Cp, Ct, Ch (ugks_surface)."""
+        n = self._L.ugks_n_wall_faces(self._h)
+        out = np.zeros((n, 6))
+        _check(self._L, self._h, self._L.ugks_surface(self._h, float(rho_inf), float(u_inf),
+                                                      out.ctypes.data_as(_dp)))
+        return {"p": out[:, 0], "sigma": out[:, 1], "q": out[:, 2], "Cp": out[:, 3], "Ct": out[:, 4],
+                "Ch": out[:, 5]}
 
     def cell_order(self):
         """Stored cell position -> caller's cell index."""

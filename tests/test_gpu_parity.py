@@ -460,9 +460,29 @@ def test_wall_flux_matches_oracle(which):
     Fg, Fo = s.wall_flux(), o.wall_flux()
     assert Fg.shape == Fo.shape and len(Fg) > 0
     err = _wall_flux_err(Fg, Fo)
-    sf = s.surface(1.0, 1.0)
-    _say(f"    wall flux rel err {err:.2e}; max shear {sf['sigma'].max():.3e}, max |heat flux| {np.abs(sf['q']).max():.3e}")
+    rho_inf, u_inf = 1.0, 0.9129 * 5.0
+    sf = s.surface(rho_inf, u_inf)
+    # the surface quantities of Sections 2.5 and 4.1 by their definition, from
+    # the oracle's wall flux and the caller's wall normals
+    m = c["mesh"]
+    n = np.asarray(m["face_normal"])[np.asarray(m["face_bc"]) == cases.BC_WALL]
+    Fm = Fo[:, 1:-1]
+    p = (Fm * n).sum(1)
+    sig = np.linalg.norm(Fm - p[:, None] * n, axis=1)
+    qw = Fo[:, -1]
+    dyn = 0.5 * rho_inf * u_inf ** 2
+    ref = {"p": p, "sigma": sig, "q": qw, "Cp": p / dyn, "Ct": sig / dyn, "Ch": qw / (dyn * u_inf)}
+    top = max(np.abs(p).max(), 1e-300)
+    esurf = {k: np.abs(sf[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-3 * top / (1.0 if k in ("p", "sigma", "q")
+                                                                                           else dyn))
+             for k in ref}
+    _say(f"    wall flux rel err {err:.2e}; surface rel err {max(esurf.values()):.2e}; "
+         f"max shear {sf['sigma'].max():.3e}, max |heat flux| {np.abs(sf['q']).max():.3e}")
     assert err <= 1e-12
+    assert max(esurf.values()) <= 1e-12, esurf
+    with pytest.raises(ugks.UgksError) as e:
+        s.surface(-1.0, 1.0)
+    assert e.value.code == ugks.UGKS_ERR_ARG
     if which == "channel3d":
         assert sf["sigma"].max() > 1e-3
 

@@ -23,6 +23,7 @@ import pytest
 import oracle
 from oracle.brute import BruteUGKS
 from paper_2412_06546_amd import cases
+from special_cases import fallback_case
 
 
 def _l2_change(W0, W1):
@@ -65,18 +66,6 @@ def test_residual_vanishes_for_a_uniform_state():
     r = o.residual()
     assert np.all(r <= 1e-15 * math.sqrt(nc) * np.abs(W0).max(0))
     assert np.all(np.abs(r - _l2_change(W0, W1)) <= 4e-16 * math.sqrt(nc) * np.abs(W1).max(0))
-
-
-def fallback_case():
-    """A cold gas (T = 0.08) with a velocity wave of amplitude 2 on a
-    periodic triangle mesh: about a quarter of the cells fall back."""
-    mesh = cases.periodic_triangles(10, 5, 2.0, 1.0, seed=7)
-    nc = len(mesh["cell_volume"])
-    x = mesh["cell_centroid"]
-    prim0 = np.stack([np.ones(nc), 2.0 * np.sin(math.pi * x[:, 0]), np.zeros(nc), np.full(nc, 0.08)], 1)
-    vg = cases.tensor_vgrid(20, 4.0, 2)
-    gas = cases.gas_params(2 / 3, 0.81, cases.vhs_mu_ref(0.1, 0.81, 1.0), dim=2)
-    return dict(mesh=mesh, vgrid=vg, gas=gas, prim0=prim0)
 
 
 def _predicted_fallback(b):
