@@ -1,38 +1,68 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X memory-saving UGKS step.
 
-Workload: the 2D hypersonic cylinder -- 20,000 unstructured cells (200 x 95
-O-grid, outer 5 rings cut into triangles) around a unit cylinder in a
-15-radius far field, Shakhov Pr = 2/3, Ma = 5, Kn = 0.1, isothermal wall,
-60 x 60 velocity grid on [-15, 15]^2: 72 million cell-velocity updates per
-step.  A step is one full time step of the scheme (macro gradients,
-interface equilibria, fused sweep with wall, macro update, heat flux and
-both stages of the f update) on inputs resident in HBM.
+Headline workload: the X38-sized synthetic lifting body -- 1,058,685
+hexahedra and prisms around a blunt lifting body, Ma 8 at 20 degrees angle
+of attack, Kn 0.01, Shakhov Pr 0.72, isothermal wall at 5.39 T_inf,
+unstructured (octree) velocity mesh of 4,548 points, f in FP64: 4.81e9
+cell-velocity updates per step, the size of the paper's only timed workload
+(Section 4.3, Table UGKSeff) and the largest single-GPU configuration.  A
+step is one full time step of the scheme (macro gradients, interface
+equilibria, fused sweep with wall, macro update, heat flux and both stages
+of the f update) on inputs resident in HBM.
 
-Prints one JSON line: cell-velocity updates/s; the roofline of the fused
-sweep kernel (live HIP-event timing of that kernel on its stream): the
-kernel is bound by the vector ALUs, so `roofline` gives the method's
-algorithmic FP64 flop rate against the 78.6 TFLOP/s vector peak, with its
-algorithmic HBM bandwidth against 8 TB/s and the measured HBM traffic
-beside it; and the FP64 CPU oracle timed on the host on a bounded sample
-of the same workload.
+Prints one JSON line:
+  value      cell-velocity updates/s of the headline (HIP events on the
+             library's stream around the timed steps);
+  roofline   the fused sweep kernel against HBM: algorithmic bytes (f read
+             once and written once per update: 2 n_comp s bytes) over its
+             average duration (HIP events recorded by the library around
+             every sweep launch), against 8 TB/s; the measured HBM traffic
+             from the committed counter profile (when the kernel source is
+             the one profiled); the vector-ALU figure beside it (the method's
+             algorithmic FP64 flops against 78.6 TFLOP/s);
+  other_precision   the same workload with f in FP32 and BF16;
+  secondary_workloads   the 2D cylinder (20,000 cells x 3,600 velocities);
+  serving    a bounded continuous-batching leg: 16 small 2D cases run to a
+             relative residual of 1e-6, p50/p99 time-to-converged;
+  cpu_baseline   the FP64 CPU oracle on the host cores on a bounded sample of
+             the lifting body (same velocity set and cell types, fewer cells).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
-
-import numpy as np
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, vector FP64
+KERNEL_SRC = os.path.join(ROOT, "paper_2412_06546_amd", "csrc", "ugks_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILES = {"liftingbody": os.path.join(PROFILES, "k_sweep_liftingbody1m_traffic.txt"),
+                 "cylinder": os.path.join(PROFILES, "k_sweep_cylinder20k_traffic.txt")}
+
+WORKLOADS = {
+    "liftingbody": "3D X38-sized lifting body Ma 8 AoA 20 Kn 0.01 Shakhov Pr 0.72, wall 5.39 T_inf, "
+                   "unstructured (octree) velocity set",
+    "cylinder": "2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov Pr 2/3, isothermal wall",
+    "sphere": "3D sphere (tetrahedra) Ma 4 Kn 0.05 Shakhov Pr 0.72, isothermal wall",
+    "spherehex": "3D sphere (hexahedra) Ma 4 Kn 0.05 Shakhov Pr 0.72, isothermal wall",
+}
+
+
+def make_case(workload: str):
+    from paper_2412_06546_amd import cases
+    return {"cylinder": cases.case_cylinder, "sphere": cases.case_sphere,
+            "spherehex": lambda: cases.case_sphere(n=16, n_r=33, kind="hex"),
+            "liftingbody": cases.case_lifting_body}[workload]()
 
 
 def alg_flops_per_update(dim: int, nf: float) -> float:
@@ -50,8 +80,6 @@ def alg_flops_per_update(dim: int, nf: float) -> float:
     slope = nc * (nf * (1 + 2 * dim) + nf * (2 * dim + 2 + 3 + 4 + 2) + 9 + 2 * dim)
     faces = 0.5 * nf * (2 * dim + nc * 4 * dim + 2 + (50 if nc == 2 else 30) + 1 + 2 * nc)
     return slope + faces + (75 if dim == 2 else 50)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cylinder20k_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2412_06546_amd", "csrc", "ugks_kernels.hip")
 
 
 def kernel_source_hash() -> str:
@@ -59,13 +87,15 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(fstore: str):
+def measured_traffic(workload: str, fstore: str, path: str | None = None):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary of this workload, or None when there is none or the kernel
+    source changed since it was taken."""
+    path = path or TRAFFIC_FILES.get(workload)
+    if not path or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -73,6 +103,12 @@ def measured_traffic(fstore: str):
         return None
     key = f"traffic_bytes_per_launch_{fstore}"
     return float(vals[key]) if key in vals else None
+
+
+def mean_faces_per_cell(case) -> float:
+    fc = np.asarray(case["mesh"]["face_cells"])
+    nc = len(case["mesh"]["cell_volume"])
+    return float(np.bincount(np.concatenate([fc[:, 0], fc[:, 1][fc[:, 1] >= 0]]), minlength=nc).mean())
 
 
 def copy_calibration(nbytes: int, reps: int):
@@ -86,43 +122,63 @@ def copy_calibration(nbytes: int, reps: int):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(case, target_s: float, max_steps: int):
-    """The FP64 oracle as it stands, on the host cores, on the same workload;
-    set-up (time step, initial state) excluded.  Timed with all cores
-    (bounded by target_s), then one step on one core."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(target_s: float):
+    """The FP64 oracle as it stands, on the host cores.  The full lifting
+    body (38.5 GB of f, about a minute per step on 16 cores) is beyond a
+    bounded run, so the sample is a cut-down of the same workload: the same
+    4,548-point velocity set, hexahedra and prisms, wall and far field,
+    64,920 cells (16 x 16 points per cube face, 40 layers), timed over whole
+    steps on all cores up to target_s; then a smaller cut-down (8 x 8 points,
+    20 layers: 7,830 cells) for one step on one core.  Set-up (time step,
+    initial state) excluded."""
     import oracle
+    from paper_2412_06546_amd import cases
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    case = cases.case_lifting_body(n=16, n_r=40, n_prism_columns=87)
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
-    o = oracle.Oracle(case, omp_threads=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    o = oracle.Oracle(case, omp_threads=threads)
     cores = o.threads
     steps, t = 0, 0.0
-    while steps < max_steps and t < target_s:
+    while steps < 8 and t < target_s:
         t0 = time.perf_counter()
         o.step(1)
         t += time.perf_counter() - t0
         steps += 1
-    o.set_threads(1)
+    del o
+    small = cases.case_lifting_body(n=8, n_r=20, n_prism_columns=21)
+    nc1 = len(small["mesh"]["cell_volume"])
+    o1 = oracle.Oracle(small, omp_threads=1)
     t0 = time.perf_counter()
-    o.step(1)
+    o1.step(1)
     t1 = time.perf_counter() - t0
-    o.set_threads(cores)
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
-    except OSError:
-        pass
+    del o1
+    oracle.lib().orc_set_threads(cores)
     return {"value": nc * nv * steps / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
-            "single_core_value": nc * nv / t1, "host_cpu": model, "host_logical_cpus": os.cpu_count(),
-            "sample": f"{steps} full steps of the same {nc}-cell x {nv}-velocity workload on {cores} threads "
-                      f"({t:.1f} s, OpenMP over cells, gcc -O2), then 1 step on 1 thread ({t1:.1f} s)"}
+            "single_core_value": nc1 * nv / t1, "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "sample": f"{steps} full steps of a {nc}-cell cut-down of the lifting body (same 4,548-velocity set, "
+                      f"hexahedra and prisms, wall and far field) on {cores} threads ({t:.1f} s, OpenMP over "
+                      f"cells, gcc -O2); then 1 step of a {nc1}-cell cut-down on 1 thread ({t1:.1f} s)"}
 
 
 def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers", chunk: int = 0):
+    """Warm-up steps, then exactly `steps` timed steps between device
+    synchronisations; HIP events on torch's current stream (the stream the
+    library launches on) around the timed steps, and the library's own
+    events around every sweep launch."""
     import torch
     from paper_2412_06546_amd import ugks
     s = ugks.Solver(case, fstore=fstore, mem=mem, chunk=chunk)
     nc, nv, ncomp = s.nc, s.nv, s.ncomp
-    s.step(warmup)
+    if warmup:
+        s.step(warmup)
     torch.cuda.synchronize()
     s.profile(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -142,17 +198,55 @@ def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers"
     sweep_avg_s = sweep_ms / n / 1e3
     out = dict(ms_per_step=ms / steps, wall_s=wall, updates_per_s=nc * nv * steps / (ms / 1e3),
                sweep_ms_avg=sweep_ms / n, prologue_ms_avg=pro_ms / n, alg_bytes=alg_bytes,
+               bytes_per_update=ncomp * bytes_per_value * 2,
                achieved_gbs=alg_bytes / sweep_avg_s / 1e9, footprint_bytes=s.footprint_bytes,
-               finite=bool((W[:, 0] > 0).all()))
+               finite=bool(np.isfinite(W).all() and (W[:, 0] > 0).all()), nc=nc, nv=nv)
     s.close()
     return out
 
 
-def run_serving(args):
-    """Continuous batching of a Poisson stream of independent 2D cases: all-
-    triangle cylinder meshes of 2k-50k cells, 20^2-64^2 velocity grids, Ma in
-    [0.5, 6], Kn in [1e-3, 1], f in FP32 with FP64 macros, each run to a
-    residual of 1e-6 or the step cap."""
+def roofline_of(case, run, workload, fstore, mem):
+    dim = int(case["mesh"]["dim"])
+    fpu = alg_flops_per_update(dim, mean_faces_per_cell(case))
+    alg_flops = fpu * run["nc"] * run["nv"]
+    sweep_s = run["sweep_ms_avg"] / 1e3
+    tflops = alg_flops / sweep_s / 1e12
+    traffic = measured_traffic(workload, fstore) if mem == "two-buffers" else None
+    return {"bound": "hbm", "achieved": round(run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(run["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_sweep" if mem == "two-buffers" else "k_sweep_chunk (every chunk) + k_sweep_finish",
+            "kernel_ms": round(run["sweep_ms_avg"], 4),
+            "alg_bytes_per_update": run["bytes_per_update"], "alg_bytes_per_launch": run["alg_bytes"],
+            "traffic_over_algorithmic": round(traffic / run["alg_bytes"], 3) if traffic else None,
+            "alu": {"achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "alg_flops_per_update": round(fpu, 1),
+                    "alg_flops_per_launch": alg_flops}}
+
+
+def run_serving_leg(n_cases: int, max_steps: int, mode: str):
+    """The bounded serving leg: a Poisson stream of small 2D cases (2k-5k
+    triangles and quadrilaterals, 20^2-32^2 velocities, Ma 0.5-3, Kn
+    0.05-1, FP32 f with FP64 macros), each run to a residual of 1e-6 of its
+    first step's or the step cap, continuous batching under an HBM budget."""
+    from paper_2412_06546_amd import serve
+    reqs = serve.converging_stream(n_cases=n_cases, max_steps=max_steps)
+    backend = serve.GpuBackend(batched=mode == "batched")
+    srv = serve.Server(int(40e9), max_active=16, chunk=50, backend=backend)
+    res = srv.run(reqs)
+    summ = serve.Server.summary(res)
+    summ["workload"] = (f"Poisson stream (8/s) of {len(reqs)} cylinder cases, 2k-5k cells, 20^2-32^2 velocities, "
+                        f"Ma 0.5-3, Kn 0.05-1, tol 1e-6, cap {max_steps} steps, f32")
+    summ["mode"] = mode
+    summ["peak_bytes"] = srv.peak_used
+    for r in res:
+        if r.error:
+            print(f"# serving case {r.rid}: {r.error}", file=sys.stderr, flush=True)
+    return summ
+
+
+def run_serving_stream(args):
+    """--serving N: the full serving configuration (a Poisson stream of N
+    2D cylinder cases, 2k-50k triangles, 20^2-64^2 velocities)."""
     from paper_2412_06546_amd import serve
     t0 = time.perf_counter()
     reqs = serve.poisson_stream(n_cases=args.serving, rate=4.0, max_steps=args.serving_steps, fstore="f32")
@@ -164,13 +258,12 @@ def run_serving(args):
     for r in res:
         if r.error:
             print(f"# case {r.rid} ({reqs[r.rid].case['name']}): {r.error}", file=sys.stderr, flush=True)
-    line = {"metric": "serving time-to-result (p50/p99) and cell-velocity updates/s", "value": summ["p50_time_to_result_s"],
-            "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+    line = {"metric": "serving time-to-converged (p50/p99) and cell-velocity updates/s",
+            "value": summ["p50_time_to_converged_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "data": "synthetic",
             "config": {"workload": f"Poisson stream (4/s) of {len(reqs)} cylinder cases, 2k-50k triangles, "
                                    f"20^2-64^2 velocities, tol 1e-6, cap {args.serving_steps} steps, f32",
-                       "mode": args.serving_mode + (" (one batched launch per kernel per round)" if
-                                                    args.serving_mode == "batched" else " (a stream per case)"),
-                       "budget_bytes": srv.budget, "peak_bytes": srv.peak_used},
+                       "mode": args.serving_mode, "budget_bytes": srv.budget, "peak_bytes": srv.peak_used},
             "serving": summ}
     print(json.dumps(line), flush=True)
 
@@ -178,22 +271,22 @@ def run_serving(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fstore", choices=["f64", "f32", "bf16"], default="f64")
-    ap.add_argument("--workload", choices=["cylinder", "sphere", "spherehex", "liftingbody"], default="cylinder",
-                    help="cylinder: the 2D benchmark; sphere: the 3D sphere (50,688 tetrahedra x 24^3 velocities); "
-                         "spherehex: the same shell as 50,688 hexahedra; "
-                         "liftingbody: the X38-sized case (1,058,685 cells x 4,548 velocities, no CPU baseline)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="liftingbody")
     ap.add_argument("--mem", choices=["two-buffers", "in-place"], default="two-buffers",
                     help="f in two buffers (f^n, f^{n+1}) or one buffer updated in place by velocity chunks")
-    ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = the library default, 512)")
+    ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-secondary", action="store_true", help="skip the other f storage precision")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other precisions and workloads")
+    ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving-leg-cases", type=int, default=16)
+    ap.add_argument("--serving-leg-steps", type=int, default=20000)
     ap.add_argument("--serving", type=int, default=0, metavar="N",
-                    help="instead: serve a Poisson stream (4/s) of N cylinder cases and report p50/p99")
-    ap.add_argument("--serving-steps", type=int, default=400, help="step cap per served case")
+                    help="instead: serve a Poisson stream (4/s) of N cylinder cases (2k-50k cells) and report p50/p99")
+    ap.add_argument("--serving-steps", type=int, default=400, help="step cap per served case (--serving)")
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--serving-mode", choices=["batched", "streams"], default="batched")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -212,44 +305,15 @@ def main():
         copy_calibration(args.copy_calibration, 5)
         return
     if args.serving:
-        run_serving(args)
+        run_serving_stream(args)
         return
 
-    from paper_2412_06546_amd import cases
-    case = {"cylinder": cases.case_cylinder, "sphere": cases.case_sphere,
-            "spherehex": lambda: cases.case_sphere(n=16, n_r=33, kind="hex"),
-            "liftingbody": cases.case_lifting_body}[args.workload]()
+    case = make_case(args.workload)
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
     main_run = run_gpu(case, args.fstore, args.steps, args.warmup, args.mem, args.chunk)
-    print(f"# gpu {args.fstore}: {main_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    other = []
-    if not args.no_secondary:
-        for fs2 in [x for x in ("f64", "f32", "bf16") if x != args.fstore]:
-            r2 = run_gpu(case, fs2, max(5, args.steps // 2), args.warmup, args.mem, args.chunk)
-            other.append({"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
-                          "sweep_ms": r2["sweep_ms_avg"], "achieved_gbs": r2["achieved_gbs"]})
-            print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-
-    traffic = measured_traffic(args.fstore) if args.workload == "cylinder" and args.mem == "two-buffers" else None
-    # the sweep is bound by the vector ALUs (about 73 % busy, profiles/k_sweep_cylinder20k_valu.txt), not by HBM
-    dim = int(case["mesh"]["dim"])
-    nf_avg = float(np.bincount(np.concatenate([case["mesh"]["face_cells"][:, 0],
-                                               case["mesh"]["face_cells"][:, 1][case["mesh"]["face_cells"][:, 1] >= 0]]),
-                               minlength=nc).mean())
-    fpu = alg_flops_per_update(dim, nf_avg)
-    alg_flops = fpu * nc * nv
-    tflops = alg_flops / (main_run["sweep_ms_avg"] / 1e3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
-                "traffic": traffic,
-                "kernel": "k_sweep" if args.mem == "two-buffers" else "k_sweep_chunk (every chunk) + k_sweep_finish",
-                "kernel_ms": round(main_run["sweep_ms_avg"], 4),
-                "alg_flops_per_update": round(fpu, 1), "alg_flops_per_launch": alg_flops,
-                "hbm": {"achieved": round(main_run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(main_run["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                        "alg_bytes_per_launch": main_run["alg_bytes"],
-                        "traffic_gbs": round(traffic / (main_run["sweep_ms_avg"] / 1e3) / 1e9, 1) if traffic else None}}
+    print(f"# gpu {args.fstore}: {main_run['ms_per_step']:.3f} ms/step, sweep {main_run['sweep_ms_avg']:.3f} ms",
+          file=sys.stderr, flush=True)
     line = {
         "metric": "cell-velocity updates/s",
         "value": main_run["updates_per_s"],
@@ -263,25 +327,45 @@ def main():
         "vs_baseline": None,
         "dtype": args.fstore,
         "data": "synthetic",
-        "config": {"workload": f"{case['name']}: " + {
-                       "cylinder": "2D hypersonic cylinder Ma 5 Kn 0.1 Shakhov, isothermal wall",
-                       "sphere": "3D sphere Ma 4 Kn 0.05 Shakhov, isothermal wall",
-                       "spherehex": "3D sphere (hexahedra) Ma 4 Kn 0.05 Shakhov, isothermal wall",
-                       "liftingbody": "3D X38-sized lifting body Ma 8 AoA 20 Kn 0.01 Shakhov, wall 5.39 T_inf, "
-                                      "unstructured velocity set"}[args.workload],
+        "config": {"workload": f"{case['name']}: {WORKLOADS[args.workload]}",
                    "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64", "mem": args.mem,
                    "prologue_ms": round(main_run["prologue_ms_avg"], 4),
-                   "footprint_bytes": main_run["footprint_bytes"]},
-        "roofline": roofline,
+                   "footprint_bytes": main_run["footprint_bytes"], "all_cells_physical": main_run["finite"]},
+        "roofline": roofline_of(case, main_run, args.workload, args.fstore, args.mem),
     }
     if args.mem == "in-place":
         from paper_2412_06546_amd.ugks import UGKS_DEFAULT_CHUNK
         line["config"]["chunk"] = min(args.chunk if args.chunk > 0 else UGKS_DEFAULT_CHUNK, nv)
-    if other:
+    if not args.no_secondary:
+        other = []
+        for fs2 in [x for x in ("f64", "f32", "bf16") if x != args.fstore]:
+            r2 = run_gpu(case, fs2, max(4, args.steps // 2), min(args.warmup, 2), args.mem, args.chunk)
+            other.append({"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
+                          "sweep_ms": round(r2["sweep_ms_avg"], 4), "alg_gbs": round(r2["achieved_gbs"], 1),
+                          "speedup_over_headline": round(main_run["ms_per_step"] / r2["ms_per_step"], 3)})
+            print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         line["other_precision"] = other
-    if not args.no_cpu_baseline and args.workload != "liftingbody":
+        sec = []
+        for wl in [w for w in ("liftingbody", "cylinder") if w != args.workload]:
+            c2 = make_case(wl)
+            entry = {"workload": f"{c2['name']}: {WORKLOADS[wl]}"}
+            for fs2 in ("f64", "f32"):
+                r2 = run_gpu(c2, fs2, max(20, args.steps), 3)
+                rl = roofline_of(c2, r2, wl, fs2, "two-buffers")
+                entry[fs2] = {"value": r2["updates_per_s"], "ms_per_step": round(r2["ms_per_step"], 4),
+                              "sweep_ms": rl["kernel_ms"], "hbm_frac": rl["frac"], "alu_frac": rl["alu"]["frac"],
+                              "traffic": rl["traffic"]}
+                print(f"# gpu {wl} {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+            entry["f32_speedup_over_f64"] = round(entry["f64"]["ms_per_step"] / entry["f32"]["ms_per_step"], 3)
+            sec.append(entry)
+            del c2
+        line["secondary_workloads"] = sec
+    if not args.no_serving:
+        print("# serving leg ...", file=sys.stderr, flush=True)
+        line["serving"] = run_serving_leg(args.serving_leg_cases, args.serving_leg_steps, "batched")
+    if not args.no_cpu_baseline and args.workload == "liftingbody":
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds, 5)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -58,7 +58,10 @@ class BruteUGKS:
             d = np.array([v for _, v in self.nbrs[i]]).reshape(-1, D)
             G = d.T @ d
             tol = 1e-10 * (np.trace(G) / D) ** D
-            self.lsq.append(np.linalg.inv(G) @ d.T if np.linalg.det(G) > tol else np.zeros((D, len(d))))
+            # a stencil of at most D neighbours is an interpolation, not a
+            # least-squares fit: first order there
+            ok = len(d) > D and np.linalg.det(G) > tol
+            self.lsq.append(np.linalg.inv(G) @ d.T if ok else np.zeros((D, len(d))))
         self.eps2 = (self.K * self.vol ** (1.0 / D)) ** 3
         # time step
         if g["dt_override"] > 0:

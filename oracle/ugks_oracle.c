@@ -537,7 +537,12 @@ orc_t *orc_create(const orc_input_t *in)
         if (o->fbc[f] == 3) o->wall_face[n++] = f;
     o->wallF = (double *)calloc((size_t)(o->nwall ? o->nwall : 1) * o->NW, sizeof(double));
 
-    /* least-squares normal matrices, inverted once */
+    /* least-squares normal matrices, inverted once.  A stencil with no more
+     * neighbours than dimensions (a triangle or tetrahedron with a boundary
+     * face) has no redundancy: its fit interpolates the neighbours and its
+     * extrapolation to the cell's other faces leans downwind, which makes
+     * the second-order transport unstable there; such a cell, like one with
+     * a degenerate normal matrix, keeps a zero gradient (first order). */
     o->Ginv = (double *)calloc((size_t)o->nc * D * D, sizeof(double));
     o->eps2 = (double *)calloc(o->nc, sizeof(double));
     for (int i = 0; i < o->nc; ++i) {
@@ -551,14 +556,14 @@ orc_t *orc_create(const orc_input_t *in)
         for (int a = 0; a < D; ++a) tr += G[a * D + a];
         if (D == 2) {
             det = G[0] * G[3] - G[1] * G[2];
-            if (det > 1e-10 * pow(tr / D, D)) {
+            if (o->nnb[i] > D && det > 1e-10 * pow(tr / D, D)) {
                 Gi[0] = G[3] / det; Gi[1] = -G[1] / det;
                 Gi[2] = -G[2] / det; Gi[3] = G[0] / det;
             }
         } else {
             double c00 = G[4] * G[8] - G[5] * G[7], c01 = G[5] * G[6] - G[3] * G[8], c02 = G[3] * G[7] - G[4] * G[6];
             det = G[0] * c00 + G[1] * c01 + G[2] * c02;
-            if (det > 1e-10 * pow(tr / D, D)) {
+            if (o->nnb[i] > D && det > 1e-10 * pow(tr / D, D)) {
                 Gi[0] = c00 / det;
                 Gi[1] = (G[2] * G[7] - G[1] * G[8]) / det;
                 Gi[2] = (G[1] * G[5] - G[2] * G[4]) / det;

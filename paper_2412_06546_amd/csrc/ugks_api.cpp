@@ -376,9 +376,16 @@ void build_geometry(const StoredMesh &S, std::vector<CellGeo<D>> &cg, std::vecto
             if (bj < 0) throw Fail{UGKS_ERR_ARG, "inconsistent face adjacency at " + fname(f)};
             g.back[j] = bj;
         }
+        // A stencil with no more neighbours than dimensions (a triangle or a
+        // tetrahedron with a boundary face) is an interpolation, not a
+        // least-squares fit: its extrapolation to the other faces leans
+        // downwind and the second-order transport is unstable there, so
+        // such a cell keeps a zero gradient, as a degenerate one does.
+        int n_nb = 0;
+        for (int j = 0; j < g.nf; ++j) n_nb += g.nb[j] >= 0;
         double Gi[9] = {0}, tr = 0.0, det;
         for (int a = 0; a < D; ++a) tr += G[a * D + a];
-        const double tol = 1e-10 * std::pow(tr / D, D);
+        const double tol = n_nb > D ? 1e-10 * std::pow(tr / D, D) : HUGE_VAL;
         if (D == 2) {
             det = G[0] * G[3] - G[1] * G[2];
             if (det > tol) {

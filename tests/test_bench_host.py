@@ -19,18 +19,30 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_is_reported_only_for_the_measured_kernel_source(tmp_path, monkeypatch):
+def test_traffic_is_reported_only_for_the_measured_kernel_source(tmp_path):
     f = tmp_path / "traffic.txt"
     f.write_text("# header: ignored\n"
                  f"kernel_source_sha256_16: {bench.kernel_source_hash()}\n"
                  "traffic_bytes_per_launch_f64: 12345\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.measured_traffic("f64") == 12345.0
-    assert bench.measured_traffic("f32") is None          # not measured for this storage
+    assert bench.measured_traffic("liftingbody", "f64", str(f)) == 12345.0
+    assert bench.measured_traffic("liftingbody", "f32", str(f)) is None   # not measured for this storage
     f.write_text("kernel_source_sha256_16: 0000000000000000\ntraffic_bytes_per_launch_f64: 12345\n")
-    assert bench.measured_traffic("f64") is None          # the kernel changed since
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
-    assert bench.measured_traffic("f64") is None
+    assert bench.measured_traffic("liftingbody", "f64", str(f)) is None   # the kernel changed since
+    assert bench.measured_traffic("liftingbody", "f64", str(tmp_path / "missing.txt")) is None
+    assert bench.measured_traffic("sphere", "f64") is None                # no profile for this workload
+
+
+def test_roofline_is_priced_on_hbm_with_the_alu_figure_beside_it():
+    from paper_2412_06546_amd import cases
+    c = cases.case_periodic_wave(nx=6, ny=4, nv=4)
+    nc, nv = 20000, 3600
+    run = dict(nc=nc, nv=nv, sweep_ms_avg=3.0, achieved_gbs=nc * nv * 32 / 3e-3 / 1e9, bytes_per_update=32,
+               alg_bytes=nc * nv * 32)
+    r = bench.roofline_of(c, run, "cylinder", "f64", "in-place")
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["frac"] == pytest.approx(768.0 / 8000.0, abs=1e-4) and r["traffic"] is None
+    assert r["alu"]["unit"] == "TFLOP/s" and r["alu"]["peak"] == 78.6
+    assert r["alu"]["achieved"] == pytest.approx(r["alu"]["alg_flops_per_update"] * nc * nv / 3e-3 / 1e12, rel=1e-3)
 
 
 @pytest.mark.parametrize("dim,nf,expected", [(2, 3.9, 407.1), (3, 4.0, 267.0), (3, 6.0, 368.0)])

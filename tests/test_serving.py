@@ -91,7 +91,14 @@ def test_convergence_and_step_cap():
     assert not res[1].converged and res[1].steps == 50
     s = Server.summary(res)
     assert s["converged"] == 1 and s["capped"] == 1
-    assert s["p99_time_to_result_s"] >= s["p50_time_to_result_s"] > 0
+    # time-to-converged counts the converged case only; the capped one is apart
+    assert s["p50_time_to_converged_s"] == pytest.approx(res[0].time_to_result)
+    assert s["p99_time_to_converged_s"] == pytest.approx(res[0].time_to_result)
+    assert s["p50_time_to_result_capped_s"] == pytest.approx(res[1].time_to_result)
+    assert s["steps_to_converge_max"] == res[0].steps
+    # none converged: the percentiles are not numbers, the capped count is all
+    s2 = Server.summary([res[1]])
+    assert s2["converged"] == 0 and s2["capped"] == 1 and s2["p50_time_to_converged_s"] != s2["p50_time_to_converged_s"]
 
 
 def test_slots_limit_concurrency():
