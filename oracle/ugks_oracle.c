@@ -444,6 +444,7 @@ static void heat_flux_of(const orc_t *o, int i, const double *U, const double *f
 static void moments_from_f(orc_t *o)
 {
     int D = o->D, NW = o->NW;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < o->nc; ++i) {
         double *W = o->W + (size_t)i * NW;
         for (int m = 0; m < NW; ++m) W[m] = 0.0;
@@ -585,6 +586,7 @@ orc_t *orc_create(const orc_input_t *in)
         o->dt = in->dt_override;
     } else {
         double best = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : best)
         for (int i = 0; i < o->nc; ++i)
             for (int k = 0; k < o->nv; ++k) {
                 double out = 0.0;
@@ -605,6 +607,7 @@ orc_t *orc_create(const orc_input_t *in)
     o->f = (double *)malloc(sizeof(double) * (size_t)o->nv * o->nc * o->NC);
     o->W = (double *)calloc((size_t)o->nc * o->NW, sizeof(double));
     o->q = (double *)calloc((size_t)o->nc * D, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < o->nc; ++i) {
         double p[ORC_MAXW], zq[ORC_MAXD] = {0, 0, 0};
         for (int m = 0; m < D + 1; ++m) p[m] = in->prim0[(size_t)i * (D + 2) + m];

@@ -221,6 +221,7 @@ class Server:
         ups = sum(r.updates for r in ok)
         return {
             "cases": len(results),
+            "completed": len(ok),
             "converged": len(conv),
             "capped": len(capped),
             "rejected_or_failed": len(results) - len(ok),

@@ -530,6 +530,22 @@ def test_full_size_sphere_3d():
     assert max(e.values()) <= 1e-5
 
 
+def test_lifting_body_cut_down_100k_fp64():
+    """The lifting body at a tenth of its size: 107,118 hexahedra and prisms
+    (16 x 16 points per cube face, 66 layers, the polar columns as prisms),
+    the full 4,548-point octree velocity set, wall and far field, Ma 8 at
+    20 degrees: two steps against the oracle on every cell (W, q and f)."""
+    ugks = _gpu()
+    c = cases.case_lifting_body(n=16, n_r=66, n_prism_columns=87)
+    assert len(c["mesh"]["cell_volume"]) >= 100000 and len(c["vgrid"]["w"]) == 4548
+    _say(f"case {c['name']}: fp64, 2 steps against the oracle")
+    s, o = ugks.Solver(c), oracle.Oracle(c)
+    assert s.dt == pytest.approx(o.dt, rel=1e-15)
+    s.step(2)
+    o.step(2)
+    _compare(s, o)
+
+
 def test_full_size_lifting_body_conserves_mass():
     """The X38-sized case at its full size (1,058,685 hexahedra and prisms x
     4,548 unstructured velocities, 77 GB of f in FP64), closed: the far field
