@@ -194,6 +194,25 @@ int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int nsteps);
 const char *ugks_batch_last_error(const ugks_batch_t *b);
 void ugks_batch_destroy(ugks_batch_t *b);
 
+/* For callers that cannot allocate device or host memory at step time --
+ * code being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc: the batched step of ugks_batch_step without a batch
+ * object.  It calls no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating routine: the batch descriptors and offset tables go into a
+ * fixed device array of the library (about 17 KB per GPU, kept until the
+ * process ends), whose address is looked up once per device when the first
+ * handle is created on it.  hs[0..n) as for ugks_batch_step, all created on
+ * `stream` (a hipStream_t) with that stream's device current; at most
+ * UGKS_STATIC_BATCH_MAX cases (UGKS_ERR_ARG beyond, text from
+ * ugks_batch_last_error(NULL)).  The descriptors are copied to the device
+ * and the call waits for that copy (the host layout lives on its stack),
+ * then enqueues the steps and returns; each handle is pending as after
+ * ugks_batch_step.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (from several threads) race and must be
+ * serialised by the caller.  Results are bitwise those of ugks_batch_step. */
+#define UGKS_STATIC_BATCH_MAX 64
+int ugks_batch_step_static(ugks_t *const *hs, int n, int nsteps, void *stream);
+
 /* Device bytes ugks_create would allocate for these inputs (host-side
  * computation, no GPU needed): admission control against an HBM budget
  * (the memory of f per cell and velocity dominates, as in the accounting of

@@ -16,6 +16,8 @@
 
 using namespace ugx;
 
+static_assert(kStaticBatchMax == UGKS_STATIC_BATCH_MAX, "static batch limit of the header and the kernels");
+
 struct ugks {
     int dim = 0, nc = 0, nf = 0, nv = 0, ncomp = 0, fstore = 0, nbc = 0;
     hipStream_t stream = nullptr;
@@ -59,6 +61,9 @@ struct ugks {
 
 // text of the last failed create call, per calling thread
 static thread_local std::string g_create_error;
+// text of the last failed ugks_batch_step_static of the calling thread (a
+// fixed buffer: that entry point allocates nothing, not even on failure)
+static thread_local char g_static_batch_error[256] = "";
 
 namespace {
 
@@ -465,7 +470,10 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
 int fail(ugks_t *h, const Fail &e)
 {
     if (h) h->msg = e.msg;
-    else g_create_error = e.msg;
+    else {
+        g_create_error = e.msg;
+        g_static_batch_error[0] = 0;
+    }
     return e.code;
 }
 
@@ -688,6 +696,11 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (!(h->dt > 0.0) || h->dt >= DBL_MAX) throw Fail{UGKS_ERR_ARG, "could not form a time step"};
         P.dt = h->dt;
 
+        // pinned status copies for asynchronous and batched steps, and this
+        // device's scratch of the allocation-free batched step
+        ensure_async(h);
+        void *scr = nullptr;
+        hip_check(static_scratch(&scr), "device scratch address");
         hip_check(launch_init(P, prim_d, h->f[0], h->stream), "k_init launch");
         hip_check(launch_moments(P, h->f[0], h->stream), "k_moments launch");
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -1168,6 +1181,120 @@ extern "C" int ugks_batch_create(int max_cases, void *stream, ugks_batch_t **out
     return UGKS_OK;
 }
 
+namespace {
+// one group of a batched sweep: cases sharing the sweep's instantiation
+struct SweepGroup {
+    int first, count, grid;
+    size_t lds;
+    long key;
+    size_t off_at;  // its offset table inside off[]
+};
+constexpr int kMaxSweepGroups = 12;  // storage (3) x per-axis tables (2) x stage-1 place (2)
+
+// Checks of a batch: NULL, stream, dimension, pending steps, memory mode,
+// duplicates.  0 or an error code, with the reason in why (static text).
+int batch_check(ugks_t *const *hs, int n, hipStream_t stream, const char **why)
+{
+    const int D = hs[0] ? hs[0]->dim : 0;
+    for (int c = 0; c < n; ++c) {
+        const ugks_t *h = hs[c];
+        if (!h) return *why = "NULL handle in the batch", UGKS_ERR_ARG;
+        if (h->stream != stream) return *why = "every handle of a batch must use the batch's stream", UGKS_ERR_ARG;
+        if (h->dim != D) return *why = "cases of one batch must have the same dimension", UGKS_ERR_ARG;
+        if (h->pending) return *why = "a handle still has asynchronous steps outstanding", UGKS_ERR_STATE;
+        if (h->mem_mode == UGKS_MEM_IN_PLACE) return *why = "in-place handles cannot be batched", UGKS_ERR_ARG;
+        if (!h->h_err) return *why = "handle without its pinned status copies", UGKS_ERR_STATE;
+        for (int e = 0; e < c; ++e)
+            if (hs[e] == h) return *why = "a handle appears twice in the batch", UGKS_ERR_ARG;
+    }
+    return 0;
+}
+
+// Host layout of one batched step of hs[0..n): the descriptors items[0..n)
+// in sweep-group order, the offset tables off[0 .. 4n+3) (prologue: cell
+// gradients [n+1], face equilibria [n+1]; then one sweep table per group),
+// and the sweep groups.  order, key and lds are work arrays of n entries.
+// Nothing is allocated.
+int batch_layout(ugks_t *const *hs, int n, BatchItem *items, int *off, int *order, long *key, size_t *lds,
+                 SweepGroup *groups)
+{
+    for (int c = 0; c < n; ++c) {
+        bool s1l = false;
+        lds[c] = sweep_lds_bytes(hs[c]->P, &s1l);
+        key[c] = hs[c]->fstore * 4 + (hs[c]->P.ntab > 0 ? 2 : 0) + (s1l ? 1 : 0);
+        order[c] = c;
+    }
+    // stable insertion sort by key (a handful of cases)
+    for (int a = 1; a < n; ++a) {
+        const int v = order[a];
+        int b = a;
+        while (b > 0 && key[order[b - 1]] > key[v]) {
+            order[b] = order[b - 1];
+            --b;
+        }
+        order[b] = v;
+    }
+    std::fill(off, off + 4 * (size_t)n + 3, 0);
+    int *og = off, *of = og + (n + 1), *os = of + (n + 1);
+    for (int j = 0; j < n; ++j) {
+        const ugks_t *h = hs[order[j]];
+        items[j].p = h->P;
+        items[j].f[0] = h->f[0];
+        items[j].f[1] = h->f[1];
+        items[j].res = h->res;
+        items[j].cur = h->cur;
+        og[j + 1] = og[j] + (h->nc + 255) / 256;
+        of[j + 1] = of[j] + (h->nf + 127) / 128;
+    }
+    int ng = 0;
+    size_t at = 0;
+    for (int j = 0; j < n;) {
+        int e = j;
+        size_t mx = 0;
+        while (e < n && key[order[e]] == key[order[j]]) mx = std::max(mx, lds[order[e++]]);
+        SweepGroup &g = groups[ng++];
+        g = SweepGroup{j, e - j, 0, mx, key[order[j]], (size_t)(os - off) + at};
+        int *t = os + at;
+        t[0] = 0;
+        for (int q = 0; q < g.count; ++q) t[q + 1] = t[q] + sweep_grid(hs[order[j + q]]->nc);
+        g.grid = t[g.count];
+        at += g.count + 1;
+        j = e;
+    }
+    return ng;
+}
+
+// The launches of nsteps batched steps from descriptors already on the
+// device, then each handle's bookkeeping and its status copies.
+hipError_t batch_launch(ugks_t *const *hs, int n, int nsteps, const BatchItem *d_items, const int *d_off,
+                        const int *h_off, const SweepGroup *groups, int ng, hipStream_t s)
+{
+    const int D = hs[0]->dim;
+    hipError_t e = hipSuccess;
+    for (int st = 0; st < nsteps && e == hipSuccess; ++st) {
+        e = launch_batch_prologue(d_items, n, d_off, h_off[n], d_off + (n + 1), h_off[2 * n + 1], D, s);
+        for (int g = 0; g < ng && e == hipSuccess; ++g)
+            e = launch_batch_sweep(d_items + groups[g].first, groups[g].count, d_off + groups[g].off_at, groups[g].grid,
+                                   st, D, (int)(groups[g].key / 4), (groups[g].key & 2) != 0,
+                                   (groups[g].key & 1) != 0, groups[g].lds, s);
+    }
+    if (e == hipSuccess) e = launch_batch_residual(d_items, n, D, s);
+    for (int c = 0; c < n && e == hipSuccess; ++c) {
+        ugks_t *h = hs[c];
+        h->cur ^= (nsteps & 1);
+        h->nstep += nsteps;
+        h->stepped = 1;
+        e = hipMemcpyAsync(h->h_err, h->err, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->h_res, h->res, (h->dim + 2) * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(h->done_ev, h->stream);
+        if (e == hipSuccess) h->pending = 1;
+    }
+    return e;
+}
+
+}  // namespace
+
 extern "C" int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int nsteps)
 {
     if (!b) return UGKS_ERR_ARG;
@@ -1177,81 +1304,21 @@ extern "C" int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int ns
     };
     if (!hs || n <= 0 || n > b->max_cases) return bad(UGKS_ERR_ARG, "n must be in 1..max_cases");
     if (nsteps <= 0) return bad(UGKS_ERR_ARG, "nsteps must be positive");
-    const int D = hs[0] ? hs[0]->dim : 0;
-    for (int c = 0; c < n; ++c) {
-        const ugks_t *h = hs[c];
-        if (!h) return bad(UGKS_ERR_ARG, "NULL handle in the batch");
-        if (h->stream != b->stream) return bad(UGKS_ERR_ARG, "every handle of a batch must use the batch's stream");
-        if (h->dim != D) return bad(UGKS_ERR_ARG, "cases of one batch must have the same dimension");
-        if (h->pending) return bad(UGKS_ERR_STATE, "a handle still has asynchronous steps outstanding");
-        if (h->mem_mode == UGKS_MEM_IN_PLACE) return bad(UGKS_ERR_ARG, "in-place handles cannot be batched");
-        for (int e = 0; e < c; ++e)
-            if (hs[e] == h) return bad(UGKS_ERR_ARG, "a handle appears twice in the batch");
-    }
+    const char *why = "";
+    if (const int code = batch_check(hs, n, b->stream, &why)) return bad(code, why);
     try {
-        for (int c = 0; c < n; ++c) ensure_async(hs[c]);
-        // cases grouped by the sweep's template (storage, tables, stage-1 place)
         std::vector<int> order(n);
         std::vector<long> key(n);
         std::vector<size_t> lds(n);
-        for (int c = 0; c < n; ++c) {
-            bool s1l = false;
-            lds[c] = sweep_lds_bytes(hs[c]->P, &s1l);
-            key[c] = hs[c]->fstore * 4 + (hs[c]->P.ntab > 0 ? 2 : 0) + (s1l ? 1 : 0);
-            order[c] = c;
-        }
-        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key[a] < key[c]; });
+        SweepGroup groups[kMaxSweepGroups];
         // the staging buffers are reused: wait until the previous uploads have left them
         if (b->uploaded) hip_check(hipEventSynchronize(b->up_ev), "hipEventSynchronize");
-        BatchItem *items = b->h_items;
-        int *off = b->h_off;
-        std::fill(off, off + 4 * (size_t)n + 3, 0);
-        int *og = off, *of = og + (n + 1), *os = of + (n + 1);
-        for (int j = 0; j < n; ++j) {
-            const ugks_t *h = hs[order[j]];
-            items[j].p = h->P;
-            items[j].f[0] = h->f[0];
-            items[j].f[1] = h->f[1];
-            items[j].res = h->res;
-            items[j].cur = h->cur;
-            og[j + 1] = og[j] + (h->nc + 255) / 256;
-            of[j + 1] = of[j] + (h->nf + 127) / 128;
-        }
-        struct Group { int first, count, grid; size_t lds; long key; int *off_host; size_t off_at; };
-        std::vector<Group> groups;
-        size_t at = 0;
-        for (int j = 0; j < n;) {
-            int e = j;
-            size_t mx = 0;
-            while (e < n && key[order[e]] == key[order[j]]) mx = std::max(mx, lds[order[e++]]);
-            Group g{j, e - j, 0, mx, key[order[j]], os + at, (size_t)(os - off) + at};
-            g.off_host[0] = 0;
-            for (int q = 0; q < g.count; ++q) g.off_host[q + 1] = g.off_host[q] + sweep_grid(hs[order[j + q]]->nc);
-            g.grid = g.off_host[g.count];
-            at += g.count + 1;
-            groups.push_back(g);
-            j = e;
-        }
-        upload(b->items, items, sizeof(BatchItem) * n, b->stream);
-        upload(b->off, off, sizeof(int) * (4 * (size_t)n + 3), b->stream);
+        const int ng = batch_layout(hs, n, b->h_items, b->h_off, order.data(), key.data(), lds.data(), groups);
+        upload(b->items, b->h_items, sizeof(BatchItem) * n, b->stream);
+        upload(b->off, b->h_off, sizeof(int) * (4 * (size_t)n + 3), b->stream);
         hip_check(hipEventRecord(b->up_ev, b->stream), "hipEventRecord");
         b->uploaded = 1;
-        const int *dog = b->off, *dof = b->off + (n + 1);
-        for (int st = 0; st < nsteps; ++st) {
-            hip_check(launch_batch_prologue(b->items, n, dog, og[n], dof, of[n], D, b->stream), "batched prologue");
-            for (const Group &g : groups)
-                hip_check(launch_batch_sweep(b->items + g.first, g.count, b->off + g.off_at, g.grid, st, D,
-                                             (int)(g.key / 4), (g.key & 2) != 0, (g.key & 1) != 0, g.lds, b->stream),
-                          "batched sweep");
-        }
-        hip_check(launch_batch_residual(b->items, n, D, b->stream), "batched residual");
-        for (int c = 0; c < n; ++c) {
-            ugks_t *h = hs[c];
-            h->cur ^= (nsteps & 1);
-            h->nstep += nsteps;
-            h->stepped = 1;
-            finish_async(h);
-        }
+        hip_check(batch_launch(hs, n, nsteps, b->items, b->off, b->h_off, groups, ng, b->stream), "batched step");
     } catch (const Fail &e) {
         return bad(e.code, e.msg);
     } catch (const std::exception &e) {
@@ -1260,7 +1327,45 @@ extern "C" int ugks_batch_step(ugks_batch_t *b, ugks_t *const *hs, int n, int ns
     return UGKS_OK;
 }
 
-extern "C" const char *ugks_batch_last_error(const ugks_batch_t *b) { return b ? b->msg.c_str() : g_create_error.c_str(); }
+extern "C" int ugks_batch_step_static(ugks_t *const *hs, int n, int nsteps, void *stream)
+{
+    auto bad = [](int code, const char *m) {
+        std::snprintf(g_static_batch_error, sizeof(g_static_batch_error), "%s", m);
+        return code;
+    };
+    if (!hs || n <= 0) return bad(UGKS_ERR_ARG, "hs must hold at least one handle");
+    if (n > UGKS_STATIC_BATCH_MAX) return bad(UGKS_ERR_ARG, "at most UGKS_STATIC_BATCH_MAX (64) cases per call");
+    if (nsteps <= 0) return bad(UGKS_ERR_ARG, "nsteps must be positive");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const char *why = "";
+    if (const int code = batch_check(hs, n, s, &why)) return bad(code, why);
+    void *base = nullptr;
+    if (static_scratch(&base) != hipSuccess) return bad(UGKS_ERR_HIP, "device scratch address lookup failed");
+    BatchItem *d_items = static_cast<BatchItem *>(base);
+    int *d_off = reinterpret_cast<int *>(static_cast<unsigned char *>(base) + kStaticItemsBytes);
+    // host layout on the stack: nothing is allocated
+    BatchItem items[UGKS_STATIC_BATCH_MAX];
+    int off[4 * UGKS_STATIC_BATCH_MAX + 3];
+    int order[UGKS_STATIC_BATCH_MAX];
+    long key[UGKS_STATIC_BATCH_MAX];
+    size_t lds[UGKS_STATIC_BATCH_MAX];
+    SweepGroup groups[kMaxSweepGroups];
+    const int ng = batch_layout(hs, n, items, off, order, key, lds, groups);
+    // the layout leaves the stack before returning: copy it and wait for the copy
+    hipError_t e = hipMemcpyAsync(d_items, items, sizeof(BatchItem) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_off, off, sizeof(int) * (4 * (size_t)n + 3), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = batch_launch(hs, n, nsteps, d_items, d_off, off, groups, ng, s);
+    if (e != hipSuccess) return bad(UGKS_ERR_HIP, hipGetErrorString(e));
+    g_static_batch_error[0] = 0;
+    return UGKS_OK;
+}
+
+extern "C" const char *ugks_batch_last_error(const ugks_batch_t *b)
+{
+    if (b) return b->msg.c_str();
+    return g_static_batch_error[0] ? g_static_batch_error : g_create_error.c_str();
+}
 
 extern "C" void ugks_batch_destroy(ugks_batch_t *b)
 {

@@ -105,6 +105,15 @@ struct BatchItem {
     int cur;
 };
 
+// Allocation-free batched step: its descriptors (at most kStaticBatchMax
+// cases) live in a fixed device array of kStaticScratchBytes, items first,
+// then the offset tables (4 n + 3 ints).  static_scratch() gives the current
+// device's copy of it (its address is looked up once per device).
+constexpr int kStaticBatchMax = 64;
+constexpr size_t kStaticItemsBytes = ((sizeof(BatchItem) * kStaticBatchMax + 255) / 256) * 256;
+constexpr size_t kStaticScratchBytes = kStaticItemsBytes + sizeof(int) * (4 * kStaticBatchMax + 3);
+hipError_t static_scratch(void **out);
+
 // Dynamic LDS of the sweep for one case, and whether its stage-1 values
 // stay in LDS (s1l).
 size_t sweep_lds_bytes(const Params &p, bool *s1l);

@@ -24,6 +24,7 @@
 #include "ugks_internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 #include <cfloat>
 #include <cmath>
@@ -1856,6 +1857,39 @@ hipError_t launch_batch_residual(const BatchItem *items, int n, int dim, hipStre
 }
 
 int residual_groups(int nc) { return std::max(1, std::min(kResidualGroups, (nc + 2047) / 2048)); }
+
+// ------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free batched step: the batch
+// descriptors and offset tables.  Each GPU holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address: the device address is looked up once per device, with that
+// device current, and only that address is ever handed to copies or kernels.
+// ------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_residual(const Params &p, double *out, hipStream_t s)
 {

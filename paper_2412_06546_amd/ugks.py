@@ -22,6 +22,7 @@ _FSTORE = {"f64": UGKS_F64, "f32": UGKS_F32, "bf16": UGKS_BF16}
 UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE = 0, 1
 _MEM = {"two-buffers": UGKS_MEM_TWO_BUFFERS, "in-place": UGKS_MEM_IN_PLACE}
 UGKS_DEFAULT_CHUNK = 512
+UGKS_STATIC_BATCH_MAX = 64
 _ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
              -5: "UGKS_ERR_STATE"}
 
@@ -127,6 +128,8 @@ def load_library(path: str = LIB_PATH):
     L.ugks_batch_step.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int]
     L.ugks_batch_last_error.restype = C.c_char_p
     L.ugks_batch_last_error.argtypes = [C.c_void_p]
+    L.ugks_batch_step_static.restype = C.c_int
+    L.ugks_batch_step_static.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p]
     L.ugks_batch_destroy.restype = None
     L.ugks_batch_destroy.argtypes = [C.c_void_p]
     L.ugks_destroy.restype = None
@@ -352,3 +355,15 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def batch_step_static(solvers, nsteps: int, stream=None):
+    """ugks_batch_step_static: the batched step without a batch object (no
+    allocation); every solver must have been created on `stream`."""
+    L = load_library()
+    if stream is None:
+        stream = current_stream_handle()
+    arr = (C.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
+    code = L.ugks_batch_step_static(arr, len(solvers), int(nsteps), stream)
+    if code != UGKS_OK:
+        raise UgksError(code, L.ugks_batch_last_error(None).decode())
