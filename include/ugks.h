@@ -109,7 +109,26 @@ typedef struct {
     const double *bc_prim; /* [n_bc][dim+2]: (rho, U, T); walls use (U_w, T_w) */
     int mem_mode;       /* UGKS_MEM_TWO_BUFFERS or UGKS_MEM_IN_PLACE (below) */
     int chunk;          /* in-place mode: velocities per chunk, 0 = UGKS_DEFAULT_CHUNK */
+    int sweep;          /* UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER or UGKS_SWEEP_PUSH (below) */
 } ugks_gas_t;
+
+/* How the per-velocity sweep (Alg. 1 lines 4-8) evaluates the face fluxes.
+ * UGKS_SWEEP_PUSH: every face flux once per velocity, by the face's upwind
+ * cell with its own limited slope; the cells are coloured so that no two
+ * cells of a colour are neighbours or share one, one launch per colour adds
+ * each flux to the stage-1 values of both of its cells (the second f buffer
+ * holds them), and a final kernel forms W^{n+1}, q^{n+1} and stage 2.
+ * Needs two buffers and FP64 or FP32 f.
+ * UGKS_SWEEP_GATHER: one workgroup per cell evaluates every face of its cell,
+ * rebuilding the upwind neighbour's limited slope where needed (each
+ * interior face twice); the in-place mode, BF16 f and batched steps use it.
+ * UGKS_SWEEP_AUTO (0): push where it applies, except 2D with FP64 f (there
+ * gathering measured faster on MI355X); else gather.  Both give the same
+ * results up to the order of sums; ugks_sweep_kind tells which a handle
+ * uses. */
+#define UGKS_SWEEP_AUTO 0
+#define UGKS_SWEEP_GATHER 1
+#define UGKS_SWEEP_PUSH 2
 
 /* Storage of f.  UGKS_MEM_TWO_BUFFERS: f^n is read from one buffer and
  * f^{n+1} written to the other (2 f of memory; the fastest form).
@@ -266,6 +285,10 @@ size_t ugks_footprint_bytes(const ugks_t *h);
 /* 1 if the Gaussians over the velocity set of Section 2.3 are tabulated per
  * axis (few distinct coordinate values per axis), 0 if evaluated directly. */
 int ugks_is_tensor_grid(const ugks_t *h);
+/* UGKS_SWEEP_PUSH or UGKS_SWEEP_GATHER: how the handle's steps evaluate the
+ * face fluxes of Alg. 1 lines 4-8 (batched steps always gather); -1 for a
+ * NULL handle. */
+int ugks_sweep_kind(const ugks_t *h);
 
 /* Timing of the step's kernels with HIP events on the handle's stream (the
  * per-step wall time the paper reports in Table UGKSeff).

@@ -35,6 +35,7 @@ template <int D> struct alignas(16) CellGeo {
     double eps2;     // Venkatakrishnan epsilon^2
     double dvec[MF][D];  // centroid -> face centroid, in this cell's frame
     double lsq[MF][D];   // least-squares weights: grad = sum_j lsq_j (f_j - f_i)
+    double nb_inv_vol[MF];  // 1 / |Omega_n| of the neighbour across each slot (0 on a boundary)
 };
 
 template <int D> struct alignas(16) FaceGeo {
@@ -93,6 +94,11 @@ struct Params {
     void *ring;
     int chunk, nchunk;
     double *mom_part, *rho_w;
+    // push sweep: mom_part holds the moments of the stage-1 base [cell][dim+2];
+    // wall ordinal of every face (-1 if not a wall) and the wall flux of the
+    // last step per wall face [n_wall][dim+2] (per unit area and time)
+    const int *wall_index;
+    double *wflux;
 };
 
 // One case of a batched launch (several cases advanced by the same kernels):
@@ -132,6 +138,13 @@ hipError_t launch_init(const Params &p, const double *prim0, void *f, hipStream_
 hipError_t launch_moments(const Params &p, const void *f, hipStream_t s);
 hipError_t launch_prologue(const Params &p, hipStream_t s);  // k_cell_grad + k_face_eq
 hipError_t launch_sweep(const Params &p, const void *f_in, void *f_out, hipStream_t s);
+// the push sweep of one step (FP64 or FP32 f): the stage-1 base of f into acc
+// first when need_base, then the wall cells (wall densities into rho_w and
+// the step's wall flux), then one launch per colour over cells[coff[c] ..
+// coff[c+1]) (coff: host array of ncol + 1 offsets into the device list
+// cells), then stage 2 into f and the next base into acc
+hipError_t launch_push_step(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff,
+                            int ncol, const int *wall_cells, int n_wall_cells, hipStream_t s);
 // the in-place step's sweep: wall densities (if walls), one kernel per
 // velocity chunk, the final kernel; f is read and updated in place
 hipError_t launch_sweep_inplace(const Params &p, void *f, bool walls, hipStream_t s);

@@ -95,6 +95,33 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double *lds, Op op)
     __syncthreads();
 }
 
+// The same reduction for wide workgroups (many wavefronts): one thread per
+// value sums the wavefronts' results, in the same fixed order, and the
+// totals are broadcast through LDS; lds holds (BS / 64 + 1) * N doubles.
+template <int BS, int N, typename Op>
+__device__ __forceinline__ void block_reduce_wide(double (&v)[N], double *lds, Op op)
+{
+    constexpr int NWAVE = BS / 64;
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[n] = op(v[n], __shfl_xor(v[n], off, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int n = 0; n < N; ++n) lds[wid * N + n] = v[n];
+    __syncthreads();
+    if ((int)threadIdx.x < N) {
+        double s = lds[threadIdx.x];
+        for (int w = 1; w < NWAVE; ++w) s = op(s, lds[w * N + threadIdx.x]);
+        lds[NWAVE * N + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = lds[NWAVE * N + n];
+    __syncthreads();
+}
+
 struct OpAdd {
     __device__ double operator()(double a, double b) const { return a + b; }
 };
@@ -1391,6 +1418,488 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 }
 
 // ------------------------------------------------------------------------
+// Push sweep (two f buffers, FP64 or FP32 f): each face flux once.
+//
+// Per velocity, the flux through an interior face needs the limited slope
+// of the upwind cell only (Eq. fullSolution).  The cells are split into
+// colours such that no two cells of a colour are neighbours or share a
+// neighbour (distance-2 colouring), and one launch per colour advances its
+// cells: a workgroup owns one cell's velocity slab, rebuilds that cell's
+// own limited slope, and for every face through which the cell is upwind
+// at a velocity it evaluates the time-integrated flux once and adds it to
+// the stage-1 accumulator of both cells (- F / |Omega_i| here, + F /
+// |Omega_n| there).  Faces through which the cell is downwind are added by
+// the neighbour in its own colour's launch.  No two workgroups of a launch
+// touch the same accumulator, and the colours run in a fixed order, so the
+// sums are deterministic; the accumulator holds, before the first colour,
+// the stage-1 base f^n + (dt / 2 tau^n)(f+^n - f^n) of Eq. microS1 and,
+// after the last, the stage-1 value itself.  A final kernel per cell then
+// forms W^{n+1} = W^n + M(f~) - M(base) (M the moments (1, u, (|u|^2 h + b)
+// / 2) summed over velocities: their difference is the sum over faces of
+// the moments of the micro flux, Eqs. macroscopicFlux and
+// macroscopicUpdata), tau^{n+1}, q^{n+1}, stage 2 (Eq. microS2) into the f
+// buffer, and the next step's base (with its moments) into the
+// accumulator.  Wall cells reduce the wall density over their velocities
+// first (Eq. maxWalldes) and record the step's wall flux.
+// ------------------------------------------------------------------------
+
+// The value itself, opaque to the compiler: a multiply that produced it can
+// no longer be fused into a later add or subtract, so arithmetic on it sees
+// the rounded value -- as it does when the value is read back from memory.
+__device__ __forceinline__ double opaque(double x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// moments (1, u, (|u|^2 h + b) / 2) of one velocity's values, weighted
+template <int D>
+__device__ __forceinline__ void add_moments(double (&m)[D + 2], double w, const double (&u)[D], double u2, double h,
+                                            double b)
+{
+    m[0] = fma(w, h, m[0]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[1 + d] = fma(w * u[d], h, m[1 + d]);
+    m[D + 1] = fma(0.5 * w, fma(u2, h, b), m[D + 1]);
+}
+
+// the cell's own Gaussian table (slot MF) for (U, lam); no barrier inside
+template <int D, int BS>
+__device__ __forceinline__ void fill_cell_table(const Params &p, const double (&U)[D], double lam, double *tab)
+{
+    const int ntab = p.ntab;
+    for (int idx = threadIdx.x; idx < ntab; idx += BS) {
+        const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+        double Ud = U[0];
+        if (ax == 1) Ud = U[1];
+        if (D == 3 && ax == 2) Ud = U[D - 1];
+        const double c = p.u1d[idx] - Ud;
+        tab[Dim<D>::MF * ntab + idx] = exp(-lam * c * c);
+    }
+}
+
+// Stage-1 base of cell i and its moments: acc = f + (dt / 2 tau)(f+ - f)
+// from f^n, W^n, q^n (after a start, a restart or a step of another kind).
+template <int D, typename FT, int BS, bool TENSOR>
+__global__ __launch_bounds__(BS) void k_push_base(Params p, const FT *__restrict__ fin, FT *__restrict__ acc)
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int nv = p.nv, ntab = TENSOR ? p.ntab : 0;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if constexpr (TENSOR) fill_cell_table<D, BS>(p, cs.pn.U, cs.pn.lam, smem);
+    __syncthreads();
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    double *red = smem + (MF + 1) * ntab;
+    const size_t base = (size_t)i * NC * nv;
+    double mom[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+#pragma unroll 4
+    for (int k = threadIdx.x; k < nv; k += BS) {
+        double u[D], u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 = fma(u[d], u[d], u2);
+        }
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fp[2];
+        const double H = cs.pref_n * gauss(MF, kx, u, cs.pn.lam, cs.pn.U);
+        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
+        double bv[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double f = to_f64(fin[base + (size_t)c * nv + k]);
+            const FT s = from_f64<FT>(fma(cs.hdt_tau, fp[c] - f, f));
+            acc[base + (size_t)c * nv + k] = s;
+            bv[c] = to_f64(s);
+        }
+        add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+    }
+    block_reduce_wide<BS>(mom, red, OpAdd{});
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) p.mom_part[(size_t)i * NW + m] = mom[m];
+}
+
+// Wall faces of cell i (Section 2.5): per wall face, the incident particles'
+// mass flux (free transport of the interior reconstruction) and the
+// unit-density reflected one, summed over velocities, give rho_w
+// (Eq. maxWalldes); the face's macroscopic flux over the step (incident +
+// rho_w reflected) per unit area and time is recorded.  Workgroup-wide.
+template <int D, typename FT, int BS, bool TENSOR>
+__device__ __forceinline__ void push_wall(const Params &p, const CellGeo<D> &gi, int i, const FT *__restrict__ fin,
+                                          const Gauss<D, TENSOR> &gauss, double *red, double (&rho_w)[Dim<D>::MF])
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2;
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
+    const int nv = p.nv, nf = gi.nf;
+    const double dt = p.dt;
+#pragma unroll
+    for (int j = 0; j < MF; ++j) rho_w[j] = 0.0;
+    for (int j = 0; j < nf; ++j) {
+        const int f = gi.face[j];
+        const FaceGeo<D> &F = fg[f];
+        if (F.bc != 3) continue;  // uniform
+        const FaceEq<D> &e = fe[f];
+        double s[2 * NW + 2];
+#pragma unroll
+        for (int m = 0; m < 2 * NW + 2; ++m) s[m] = 0.0;
+        for (int k = threadIdx.x; k < nv; k += BS) {
+            double u[D], u2 = 0.0, un = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                u[d] = p.u[d * nv + k];
+                u2 = fma(u[d], u[d], u2);
+                un = fma(u[d], F.n[d], un);
+            }
+            const double wk = p.w[k];
+            double I[2] = {0.0, 0.0};
+            if (un > 0.0) {
+                double fi[NC], gri[NC][D];
+                limited_slope<D, FT>(gi, i, fin, nv, k, p.limiter, fi, gri);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double v = fi[c], ug = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        v = fma(gri[c][d], gi.dvec[j][d], v);
+                        ug = fma(u[d], gri[c][d], ug);
+                    }
+                    I[c] = dt * v - 0.5 * dt * dt * ug;
+                }
+                s[2 * NW] = fma(wk * un, I[0], s[2 * NW]);
+                double mm[NW];
+#pragma unroll
+                for (int m = 0; m < NW; ++m) mm[m] = 0.0;
+                add_moments<D>(mm, wk * un, u, u2, I[0], NC > 1 ? I[NC - 1] : 0.0);
+#pragma unroll
+                for (int m = 0; m < NW; ++m) s[m] += mm[m];
+            } else {
+                const double H = dt * e.pref * gauss(j, (TENSOR ? (unsigned)p.kidx[k] : 0u), u, e.lam, e.U);
+                I[0] = H;
+                if constexpr (NC > 1) I[1] = e.bh * H;
+                s[2 * NW + 1] = fma(wk * un, I[0], s[2 * NW + 1]);
+                double mm[NW];
+#pragma unroll
+                for (int m = 0; m < NW; ++m) mm[m] = 0.0;
+                add_moments<D>(mm, wk * un, u, u2, I[0], NC > 1 ? I[NC - 1] : 0.0);
+#pragma unroll
+                for (int m = 0; m < NW; ++m) s[NW + m] += mm[m];
+            }
+        }
+        block_reduce<BS>(s, red, OpAdd{});
+        const double rw = s[2 * NW + 1] != 0.0 ? -s[2 * NW] / s[2 * NW + 1] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < MF; ++jj)
+            if (jj == j) rho_w[jj] = rw;
+        if (threadIdx.x == 0 && p.wall_index) {
+            const int widx = p.wall_index[f];
+            if (widx >= 0)
+#pragma unroll
+                for (int m = 0; m < NW; ++m) p.wflux[(size_t)widx * NW + m] = (s[m] + rw * s[NW + m]) / dt;
+        }
+    }
+}
+
+// One colour's cells: cells[0..ncell) (stored indices), workgroups dealt to
+// the XCDs in runs as for the gather sweep.  PF: the own stencil of the
+// next velocity is loaded one iteration ahead.
+template <int D, typename FT, int BS, bool TENSOR, bool PF>
+__device__ __forceinline__ void push_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ acc)
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NT = MF + 1;
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
+    const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
+    const int nv = p.nv, nf = gi.nf, ntab = TENSOR ? p.ntab : 0;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
+    __syncthreads();
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    // wall densities of this cell's wall faces, from the step's wall kernel
+    const double *rho_w = p.rho_w + (size_t)i * MF;
+
+    const size_t base = (size_t)i * NC * nv;
+    double pv0[NC], pvn[MF][NC];
+    if (PF && tid < nv) load_stencil<D, FT>(gi, i, fin, nv, tid, pv0, pvn);
+    for (int k = tid; k < nv; k += BS) {
+        double v0[NC], vn[MF][NC];
+        if constexpr (PF) {
+#pragma unroll
+            for (int m = 0; m < NC; ++m) {
+                v0[m] = pv0[m];
+#pragma unroll
+                for (int j = 0; j < MF; ++j) vn[j][m] = pvn[j][m];
+            }
+            if (k + BS < nv) load_stencil<D, FT>(gi, i, fin, nv, k + BS, pv0, pvn);
+        } else {
+            load_stencil<D, FT>(gi, i, fin, nv, k, v0, vn);
+        }
+        double u[D], u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 = fma(u[d], u[d], u2);
+        }
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fi[NC], gri[NC][D];
+        slope_from<D>(gi, p.limiter, v0, vn, fi, gri);
+        double out[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c] = 0.0;
+        // faces one at a time (not unrolled: their records are read with
+        // scalar loads per face, which keeps the vector registers for the
+        // velocities' values)
+#pragma unroll 1
+        for (int j = 0; j < nf; ++j) {
+            const int f = gi.face[j];
+            const FaceGeo<D> &F = fg[f];
+            const FaceEq<D> &e = fe[f];
+            double un = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) un = fma(u[d], F.n[d], un);
+            const double uo = gi.side[j] ? -un : un;  // along this cell's outward normal
+            if (F.bc == 0) {
+                if (!(uo > 0.0)) continue;  // the neighbour is upwind: it adds this flux
+                // the neighbour's accumulator first, so its load overlaps the arithmetic
+                FT *an = acc + (size_t)gi.nb[j] * NC * nv;
+                double av[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) av[c] = to_f64(an[(size_t)c * nv + k]);
+                double val[NC], ug[NC], I[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    val[c] = fi[c];
+                    ug[c] = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        val[c] = fma(gri[c][d], gi.dvec[j][d], val[c]);
+                        ug[c] = fma(u[d], gri[c][d], ug[c]);
+                    }
+                }
+                const double H0 = e.pref * gauss(j, kx, u, e.lam, e.U);
+                interface_integral<D>(e, u, u2, H0, val, ug, I);
+                const double sa = F.area * uo;
+                const double vn_inv = gi.nb_inv_vol[j];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const double fl = sa * I[c];
+                    out[c] += fl;
+                    an[(size_t)c * nv + k] = from_f64<FT>(fma(fl, vn_inv, av[c]));
+                }
+            } else {
+                double I[NC];
+                if (un > 0.0) {
+                    // outgoing through a wall or far-field face: free transport
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        double v = fi[c], ug = 0.0;
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            v = fma(gri[c][d], gi.dvec[j][d], v);
+                            ug = fma(u[d], gri[c][d], ug);
+                        }
+                        I[c] = e.dt * v - e.hdt2 * ug;
+                    }
+                } else {
+                    // incoming from the wall (density rho_w) or the ghost Maxwellian
+                    const double H = (F.bc == 3 ? rho_w[j] : 1.0) * e.pref * gauss(j, kx, u, e.lam, e.U);
+                    I[0] = e.dt * H;
+                    if constexpr (NC > 1) I[1] = e.dt * e.bh * H;
+                }
+                const double sa = F.area * un;  // a boundary cell is the face's left cell
+#pragma unroll
+                for (int c = 0; c < NC; ++c) out[c] += sa * I[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            FT *a = acc + base + (size_t)c * nv + k;
+            *a = from_f64<FT>(fma(-out[c], gi.inv_vol, to_f64(*a)));
+        }
+    }
+}
+
+// The wall cells of a step (before the colours): wall densities per face slot
+// into rho_w [cell][MF] and the wall flux of the step per wall face.
+template <int D, typename FT, int BS, bool TENSOR>
+__global__ __launch_bounds__(BS) void k_push_wall(Params p, const FT *__restrict__ fin, const int *__restrict__ cells,
+                                                  int ncell)
+{
+    constexpr int MF = Dim<D>::MF, NT = MF + 1;
+    extern __shared__ double smem[];
+    if ((int)blockIdx.x >= ncell) return;
+    const int i = cells[blockIdx.x];
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const int ntab = TENSOR ? p.ntab : 0;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
+    __syncthreads();
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+    double rho_w[MF];
+    push_wall<D, FT, BS, TENSOR>(p, gi, i, fin, gauss, smem + NT * ntab, rho_w);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < MF; ++j) p.rho_w[(size_t)i * MF + j] = rho_w[j];
+}
+
+template <int D, typename FT, int BS, bool TENSOR>
+__global__ __launch_bounds__(BS) void k_push(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
+                                             const int *__restrict__ cells, int ncell)
+{
+    const int b = xcd_cell(blockIdx.x);
+    if (b >= ncell) return;
+    push_cell<D, FT, BS, TENSOR, false>(p, cells[b], fin, acc);
+}
+
+template <int D, typename FT, int BS>
+__global__ __launch_bounds__(BS) void k_push_pf(
+    Params p, const FT *__restrict__ fin, FT *__restrict__ acc, const int *__restrict__ cells, int ncell)
+{
+    const int b = xcd_cell(blockIdx.x);
+    if (b >= ncell) return;
+    push_cell<D, FT, BS, true, true>(p, cells[b], fin, acc);
+}
+
+// After the last colour: W^{n+1}, tau^{n+1}, q^{n+1}, stage 2 into f and the
+// next step's base into the accumulator.  S1L: the stage-1 slab is kept in
+// LDS between the passes (else re-read from the accumulator).
+template <int D, typename FT, int BS, bool TENSOR, bool S1L>
+__global__ __launch_bounds__(BS) void k_push_final(Params p, FT *__restrict__ fout, FT *__restrict__ acc)
+{
+    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2, NT = MF + 1;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int tid = threadIdx.x, nv = p.nv, ntab = TENSOR ? p.ntab : 0;
+    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const double dt = p.dt, Pr = p.Pr;
+    const size_t base = (size_t)i * NC * nv;
+    double *red = smem + NT * ntab;
+    FT *s1 = S1L ? reinterpret_cast<FT *>(red + (BS / 64) * (2 * NW)) : acc + base;
+    double Wn[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
+
+    // pass 1: moments of the stage-1 values (unrolled: several loads of the
+    // slab in flight per wavefront)
+    double mom[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+#pragma unroll 4
+    for (int k = tid; k < nv; k += BS) {
+        double u[D], u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 = fma(u[d], u[d], u2);
+        }
+        double v[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const FT x = acc[base + (size_t)c * nv + k];
+            if constexpr (S1L) s1[(size_t)c * nv + k] = x;
+            v[c] = to_f64(x);
+        }
+        add_moments<D>(mom, p.w[k], u, u2, v[0], NC > 1 ? v[NC - 1] : 0.0);
+    }
+    block_reduce_wide<BS>(mom, red, OpAdd{});
+    double W1[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) W1[m] = Wn[m] + (mom[m] - p.mom_part[(size_t)i * NW + m]);
+    const Prim<D> p1 = to_prim<D>(W1);
+    const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
+
+    // pass 2: heat flux of the stage-1 distribution about U^{n+1}
+    double qt[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qt[d] = 0.0;
+    for (int k = tid; k < nv; k += BS) {
+        double c[D], c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            c[d] = p.u[d * nv + k] - p1.U[d];
+            c2 += c[d] * c[d];
+        }
+        const double h = to_f64(s1[k]);
+        const double b = NC > 1 ? to_f64(s1[(size_t)(NC - 1) * nv + k]) : 0.0;
+        const double wt = 0.5 * p.w[k] * (c2 * h + b);
+#pragma unroll
+        for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
+    }
+    block_reduce_wide<BS>(qt, red, OpAdd{});
+    double q1[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q1[d] = qt[d] / (1.0 + Pr * dt / (2.0 * tau1));
+
+    if constexpr (TENSOR) {
+        fill_cell_table<D, BS>(p, p1.U, p1.lam, smem);
+        __syncthreads();
+    }
+    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
+
+    // pass 3: stage 2 (Eq. microS2) into f, the next step's base into acc
+    const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
+    const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
+    const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
+    const double bh_1 = Dim<D>::M / (2.0 * p1.lam);
+    double mb[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mb[m] = 0.0;
+    for (int k = tid; k < nv; k += BS) {
+        double u[D], u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u[d] = p.u[d * nv + k];
+            u2 = fma(u[d], u[d], u2);
+        }
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fp[2];
+        const double H = pref_1 * gauss(MF, kx, u, p1.lam, p1.U);
+        shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
+        double bv[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const FT fn = from_f64<FT>((to_f64(s1[(size_t)c * nv + k]) + a1 * fp[c]) * inv1);
+            fout[base + (size_t)c * nv + k] = fn;
+            // the base from f^{n+1} as stored (bitwise what the base kernel
+            // computes from it after a restart)
+            const double fd = opaque(to_f64(fn));
+            const FT bs = from_f64<FT>(fma(a1, fp[c] - fd, fd));
+            acc[base + (size_t)c * nv + k] = bs;
+            bv[c] = to_f64(bs);
+        }
+        add_moments<D>(mb, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+    }
+    block_reduce_wide<BS>(mb, red, OpAdd{});
+    if (tid == 0) {
+        bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            ok = ok && isfinite(W1[m]);
+            p.W[(size_t)i * NW + m] = W1[m];
+            const double dw = W1[m] - Wn[m];
+            p.dW2[(size_t)i * NW + m] = dw * dw;
+            p.mom_part[(size_t)i * NW + m] = mb[m];
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.q[(size_t)i * D + d] = q1[d];
+        if (!ok) {
+            atomicOr(p.err, 1);
+            atomicMin(p.err + 1, i);
+        }
+    }
+    (void)gi;
+}
+
+// ------------------------------------------------------------------------
 // Surface quantities (Section 2.5): the macroscopic flux through each wall
 // face in a step, from the f that started the step.  One workgroup per wall
 // face: particles leaving the gas carry the limited reconstruction of f
@@ -1736,6 +2245,67 @@ hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s
                              : (p.fstore ? sweep_d<2, float>(p, fi, fo, s) : sweep_d<2, double>(p, fi, fo, s));
     return p.fstore == 2 ? sweep_d<3, bf16s>(p, fi, fo, s)
                          : (p.fstore ? sweep_d<3, float>(p, fi, fo, s) : sweep_d<3, double>(p, fi, fo, s));
+}
+
+// ------------------------------------------------------------------------
+// push sweep launches: the stage-1 base (when stale), one launch per colour,
+// the final kernel
+// ------------------------------------------------------------------------
+constexpr size_t kLdsPushFinal = 64 * 1024;
+
+template <int D, typename FT, bool TENSOR>
+hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int *cells, const int *coff, int ncol,
+                  const int *wall_cells, int n_wall_cells, hipStream_t s)
+{
+    constexpr int MF = Dim<D>::MF, NW = D + 2, NC = Dim<D>::NC, BS = 256;
+    const FT *fin = static_cast<const FT *>(fv);
+    FT *f = static_cast<FT *>(fv), *acc = static_cast<FT *>(av);
+    const size_t tab = sizeof(double) * (size_t)(MF + 1) * (TENSOR ? p.ntab : 0);
+    const size_t red = sizeof(double) * ((BS / 64) * (2 * NW + 2) + MF);
+    const unsigned gc = (unsigned)sweep_grid(p.nc);
+    constexpr int BSF = 256;  // the per-cell streaming kernels (base, final)
+    const size_t redf = sizeof(double) * (BSF / 64) * (2 * NW + 2);
+    if (need_base)
+        hipLaunchKernelGGL((k_push_base<D, FT, BSF, TENSOR>), dim3(gc), dim3(BSF), tab + redf, s, p, fin, acc);
+    if (n_wall_cells > 0)
+        hipLaunchKernelGGL((k_push_wall<D, FT, BS, TENSOR>), dim3(n_wall_cells), dim3(BS), tab + red, s, p, fin,
+                           wall_cells, n_wall_cells);
+    for (int c = 0; c < ncol; ++c) {
+        const int n = coff[c + 1] - coff[c];
+        if (n <= 0) continue;
+        const unsigned g = (unsigned)sweep_grid(n);
+        if constexpr (TENSOR)
+            hipLaunchKernelGGL((k_push_pf<D, FT, BS>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c], n);
+        else
+            hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c],
+                               n);
+    }
+    const size_t slab = sizeof(FT) * (size_t)NC * p.nv;
+    if (tab + redf + slab <= kLdsPushFinal)
+        hipLaunchKernelGGL((k_push_final<D, FT, BSF, TENSOR, true>), dim3(gc), dim3(BSF), tab + redf + slab, s, p, f,
+                           acc);
+    else
+        hipLaunchKernelGGL((k_push_final<D, FT, BSF, TENSOR, false>), dim3(gc), dim3(BSF), tab + redf, s, p, f, acc);
+    return hipGetLastError();
+}
+
+template <int D, typename FT>
+hipError_t push_d(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff, int ncol,
+                  const int *wc, int nwc, hipStream_t s)
+{
+    return p.ntab > 0 ? push_t<D, FT, true>(p, f, acc, need_base, cells, coff, ncol, wc, nwc, s)
+                      : push_t<D, FT, false>(p, f, acc, need_base, cells, coff, ncol, wc, nwc, s);
+}
+
+hipError_t launch_push_step(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff,
+                            int ncol, const int *wall_cells, int n_wall_cells, hipStream_t s)
+{
+    if (p.fstore == 2) return hipErrorInvalidValue;  // bfloat16 f takes the gather sweep
+    if (p.dim == 2)
+        return p.fstore ? push_d<2, float>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                        : push_d<2, double>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s);
+    return p.fstore ? push_d<3, float>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                    : push_d<3, double>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s);
 }
 
 // Surface quantities of Section 2.5 from the wall flux of the last step (per

@@ -23,6 +23,8 @@ UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE = 0, 1
 _MEM = {"two-buffers": UGKS_MEM_TWO_BUFFERS, "in-place": UGKS_MEM_IN_PLACE}
 UGKS_DEFAULT_CHUNK = 512
 UGKS_STATIC_BATCH_MAX = 64
+UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH = 0, 1, 2
+_SWEEP = {"auto": UGKS_SWEEP_AUTO, "gather": UGKS_SWEEP_GATHER, "push": UGKS_SWEEP_PUSH}
 _ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
              -5: "UGKS_ERR_STATE"}
 
@@ -45,7 +47,7 @@ class ugks_gas_t(C.Structure):
     _fields_ = [("Pr", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double), ("cfl", C.c_double),
                 ("dt_override", C.c_double), ("limiter_k", C.c_double), ("limiter", C.c_int),
                 ("fstore", C.c_int), ("n_bc", C.c_int), ("bc_prim", _dp), ("mem_mode", C.c_int),
-                ("chunk", C.c_int)]
+                ("chunk", C.c_int), ("sweep", C.c_int)]
 
 
 class UgksError(RuntimeError):
@@ -98,6 +100,8 @@ def load_library(path: str = LIB_PATH):
     L.ugks_step_count.argtypes = [C.c_void_p]
     L.ugks_footprint_bytes.restype = C.c_size_t
     L.ugks_footprint_bytes.argtypes = [C.c_void_p]
+    L.ugks_sweep_kind.restype = C.c_int
+    L.ugks_sweep_kind.argtypes = [C.c_void_p]
     L.ugks_is_tensor_grid.restype = C.c_int
     L.ugks_is_tensor_grid.argtypes = [C.c_void_p]
     L.ugks_profile.restype = C.c_int
@@ -156,7 +160,7 @@ def current_stream_handle():
     return None
 
 
-def _structs(case, fstore, keep, mem="two-buffers", chunk=0):
+def _structs(case, fstore, keep, mem="two-buffers", chunk=0, sweep="auto"):
     """ugks_mesh_t, ugks_vgrid_t, ugks_gas_t and prim0 for a case dict; the
     numpy buffers they point to are appended to keep."""
     m, vg, gas = case["mesh"], case["vgrid"], case["gas"]
@@ -179,30 +183,33 @@ def _structs(case, fstore, keep, mem="two-buffers", chunk=0):
     vgrid = ugks_vgrid_t(dim, len(vg["w"]), d(vg["u"]), d(vg["w"]))
     bc = np.asarray(gas["bc_prim"], dtype=np.float64)
     g = ugks_gas_t(gas["Pr"], gas["omega"], gas["mu_ref"], gas["cfl"], gas["dt_override"], gas["limiter_k"],
-                   int(gas["limiter"]), _FSTORE[fstore], bc.shape[0], d(bc), _MEM[mem], int(chunk))
+                   int(gas["limiter"]), _FSTORE[fstore], bc.shape[0], d(bc), _MEM[mem], int(chunk), _SWEEP[sweep])
     return mesh, vgrid, g, d(case["prim0"])
 
 
-def footprint_estimate(case, fstore: str = "f64", mem: str = "two-buffers", chunk: int = 0) -> int:
+def footprint_estimate(case, fstore: str = "f64", mem: str = "two-buffers", chunk: int = 0,
+                       sweep: str = "auto") -> int:
     """Device bytes ugks_create would allocate for this case (host only)."""
     L = load_library()
     keep = []
-    mesh, vgrid, g, _ = _structs(case, fstore, keep, mem, chunk)
+    mesh, vgrid, g, _ = _structs(case, fstore, keep, mem, chunk, sweep)
     return int(L.ugks_footprint_estimate(C.byref(mesh), C.byref(vgrid), C.byref(g)))
 
 
 class Solver:
     """A flow case on the GPU: ugks_create ... ugks_destroy."""
 
-    def __init__(self, case, fstore: str = "f64", stream=None, mem: str = "two-buffers", chunk: int = 0):
+    def __init__(self, case, fstore: str = "f64", stream=None, mem: str = "two-buffers", chunk: int = 0,
+                 sweep: str = "auto"):
         """mem: 'two-buffers' (f^n and f^{n+1} in separate buffers) or
-        'in-place' (one f buffer plus a ring of `chunk` velocities per cell)."""
+        'in-place' (one f buffer plus a ring of `chunk` velocities per cell);
+        sweep: 'auto', 'gather' or 'push' (UGKS_SWEEP_*)."""
         L = self._L = load_library()
         self.dim = int(case["mesh"]["dim"])
         self.nc = len(case["mesh"]["cell_volume"])
         self.nv = len(case["vgrid"]["w"])
         keep = []
-        mesh, vgrid, g, prim0 = _structs(case, fstore, keep, mem, chunk)
+        mesh, vgrid, g, prim0 = _structs(case, fstore, keep, mem, chunk, sweep)
         if stream is None:
             stream = current_stream_handle()
         self.stream = stream
@@ -235,6 +242,11 @@ class Solver:
     @property
     def footprint_bytes(self) -> int:
         return self._L.ugks_footprint_bytes(self._h)
+
+    @property
+    def sweep(self) -> str:
+        """'push' or 'gather': how this handle's steps evaluate the face fluxes."""
+        return {UGKS_SWEEP_PUSH: "push", UGKS_SWEEP_GATHER: "gather"}[self._L.ugks_sweep_kind(self._h)]
 
     @property
     def tensor_grid(self) -> bool:

@@ -530,6 +530,44 @@ def test_full_size_sphere_3d():
     assert max(e.values()) <= 1e-5
 
 
+@pytest.mark.parametrize("which", ["periodic_wave", "cylinder_small", "sphere_hex", "channel3d", "box_tet"])
+def test_push_and_gather_sweeps_both_match_oracle(which):
+    """The two ways of evaluating the face fluxes (each face once by its
+    upwind cell, coloured launches: the default; or each cell gathering all
+    its faces) against the oracle on the same case: periodic triangles,
+    the cylinder cut-down (wall, far field, triangles), a hexahedral
+    sphere shell, the 3D channel with a sliding wall, periodic tetrahedra."""
+    ugks = _gpu()
+    c = {"periodic_wave": lambda: cases.case_periodic_wave(),
+         "cylinder_small": lambda: cases.case_cylinder_small(),
+         "sphere_hex": lambda: cases.case_sphere(n=4, n_r=8, nv=12, half_width=8.0, kind="hex"),
+         "channel3d": lambda: cases.case_channel_3d(kind="hex"),
+         "box_tet": lambda: cases.case_box_wave_3d(n=4, kind="tet", nv=9)}[which]()
+    steps = 8
+    o = oracle.Oracle(c)
+    o.step(steps)
+    for sweep in ("push", "gather"):
+        _say(f"case {c['name']}: {sweep} sweep, fp64, {steps} steps")
+        s = ugks.Solver(c, sweep=sweep)
+        s.step(steps)
+        _compare(s, o)
+        s.close()
+
+
+def test_push_sweep_fp32_storage_error():
+    """FP32 f with the push sweep (the stage-1 sums accumulate in the FP32
+    second buffer): within the FP32 bound against the FP64 oracle."""
+    ugks = _gpu()
+    c = cases.case_cylinder_small()
+    _say(f"case {c['name']}: push sweep, f32, 20 steps")
+    s, o = ugks.Solver(c, fstore="f32", sweep="push"), oracle.Oracle(c)
+    s.step(20)
+    o.step(20)
+    e = prim_errors(s.macros()[0], o.macros()[0])
+    _say(f"    f32 push relative errors {e}")
+    assert max(e.values()) <= 1e-5
+
+
 def test_lifting_body_cut_down_100k_fp64():
     """The lifting body at a tenth of its size: 107,118 hexahedra and prisms
     (16 x 16 points per cube face, 66 layers, the polar columns as prisms),

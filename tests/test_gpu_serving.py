@@ -38,11 +38,21 @@ def test_footprint_estimate_matches_allocation():
     c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(c["vgrid"]["u"][keep]), w=np.ascontiguousarray(c["vgrid"]["w"][keep]))
     cs.append(c)
     for c in cs:
+        dim = c["mesh"]["dim"]
         for fs in ("f64", "f32", "bf16"):
-            est = ugks.footprint_estimate(c, fs)
-            s = ugks.Solver(c, fstore=fs)
-            assert s.footprint_bytes == est, (c.get("name"), fs)
-            s.close()
+            for sw in ("auto", "gather", "push") if fs != "bf16" else ("auto", "gather"):
+                est = ugks.footprint_estimate(c, fs, sweep=sw)
+                s = ugks.Solver(c, fstore=fs, sweep=sw)
+                assert s.footprint_bytes == est, (c.get("name"), fs, sw)
+                # the automatic choice: push, except 2D FP64 and BF16 f
+                auto = "gather" if fs == "bf16" or (dim == 2 and fs == "f64") else "push"
+                assert s.sweep == (auto if sw == "auto" else sw), (c.get("name"), fs, sw)
+                s.close()
+    # the push sweep needs two buffers and FP64 or FP32 f
+    assert ugks.footprint_estimate(cs[0], "bf16", sweep="push") == 0
+    with pytest.raises(ugks.UgksError) as e:
+        ugks.Solver(cs[0], fstore="bf16", sweep="push")
+    assert e.value.code == ugks.UGKS_ERR_ARG
 
 
 @pytest.mark.parametrize("batched", [True, False])
@@ -64,7 +74,9 @@ def test_each_result_in_the_mix_equals_the_result_alone(batched):
     assert any(r.admitted > r.arrival for r in res)      # some waited for memory
     for r, c in zip(res, cs):
         assert r.steps == steps
-        alone = ugks.Solver(c)
+        # batched rounds run the gather sweep (ugks_batch_step), a stream per
+        # case the default (push) sweep: the lone run takes the same one
+        alone = ugks.Solver(c, sweep="gather" if batched else "auto")
         alone.step(steps)
         W, q = alone.macros()
         alone.close()
@@ -123,7 +135,7 @@ def test_batched_steps_are_bitwise_those_of_each_case_alone():
             while r is None:
                 r = s.poll()
     for (c, fs), s in zip(mix, solvers):
-        alone = ugks.Solver(c, fstore=fs)
+        alone = ugks.Solver(c, fstore=fs, sweep="gather")   # the batched kernels gather
         alone.step(7)
         Wa, qa = alone.macros()
         Wb, qb = s.macros()

@@ -145,7 +145,7 @@ def test_in_place_footprint_is_one_f_plus_the_ring(dim):
     c = cases.case_periodic_wave() if dim == 2 else cases.case_channel_3d(n=3, kind="prism", nv=8)
     nc, nv = len(c["mesh"]["cell_volume"]), len(c["vgrid"]["w"])
     ncomp = 2 if dim == 2 else 1
-    two = ugks.footprint_estimate(c, "f64", "two-buffers")
+    two = ugks.footprint_estimate(c, "f64", "two-buffers", sweep="gather")
     one = {ch: ugks.footprint_estimate(c, "f64", "in-place", ch) for ch in (1, 2, nv, 10 * nv)}
     f_bytes = nc * ncomp * nv * 8
     assert one[1] < one[2] < one[nv] == one[10 * nv]
