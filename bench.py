@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, vector FP64
 KERNEL_SRC = os.path.join(ROOT, "paper_2412_06546_amd", "csrc", "ugks_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILES = {"liftingbody": os.path.join(PROFILES, "k_sweep_liftingbody1m_traffic.txt"),
+TRAFFIC_FILES = {"liftingbody": os.path.join(PROFILES, "k_push_sweep_liftingbody1m_traffic.txt"),
                  "cylinder": os.path.join(PROFILES, "k_sweep_cylinder20k_traffic.txt")}
 
 WORKLOADS = {
@@ -200,9 +200,20 @@ def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers"
                sweep_ms_avg=sweep_ms / n, prologue_ms_avg=pro_ms / n, alg_bytes=alg_bytes,
                bytes_per_update=ncomp * bytes_per_value * 2,
                achieved_gbs=alg_bytes / sweep_avg_s / 1e9, footprint_bytes=s.footprint_bytes,
-               finite=bool(np.isfinite(W).all() and (W[:, 0] > 0).all()), nc=nc, nv=nv)
+               finite=bool(np.isfinite(W).all() and (W[:, 0] > 0).all()), nc=nc, nv=nv, sweep=s.sweep,
+               n_colours=s.n_colours)
     s.close()
     return out
+
+
+def sweep_kernels(run, mem):
+    """The kernels one timed sweep launch consists of."""
+    if mem == "in-place":
+        return "k_sweep_chunk (every chunk) + k_sweep_finish"
+    if run.get("sweep") == "push":
+        return (f"push sweep: k_push_wall, {run['n_colours']} colour launches of k_push_pf (k_push), "
+                f"k_push_final, timed together")
+    return "k_sweep_pf (k_sweep)"
 
 
 def roofline_of(case, run, workload, fstore, mem):
@@ -214,7 +225,7 @@ def roofline_of(case, run, workload, fstore, mem):
     traffic = measured_traffic(workload, fstore) if mem == "two-buffers" else None
     return {"bound": "hbm", "achieved": round(run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(run["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_sweep" if mem == "two-buffers" else "k_sweep_chunk (every chunk) + k_sweep_finish",
+            "kernel": sweep_kernels(run, mem),
             "kernel_ms": round(run["sweep_ms_avg"], 4),
             "alg_bytes_per_update": run["bytes_per_update"], "alg_bytes_per_launch": run["alg_bytes"],
             "traffic_over_algorithmic": round(traffic / run["alg_bytes"], 3) if traffic else None,

@@ -289,6 +289,10 @@ int ugks_is_tensor_grid(const ugks_t *h);
  * face fluxes of Alg. 1 lines 4-8 (batched steps always gather); -1 for a
  * NULL handle. */
 int ugks_sweep_kind(const ugks_t *h);
+/* The number of colour classes (launches per step) of the push sweep: cells
+ * of one class share no neighbour and are not neighbours; 0 when the handle
+ * gathers, -1 for a NULL handle. */
+int ugks_sweep_colours(const ugks_t *h);
 
 /* Timing of the step's kernels with HIP events on the handle's stream (the
  * per-step wall time the paper reports in Table UGKSeff).

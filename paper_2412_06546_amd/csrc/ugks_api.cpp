@@ -1237,6 +1237,12 @@ extern "C" long ugks_step_count(const ugks_t *h) { return h ? h->nstep : -1; }
 extern "C" size_t ugks_footprint_bytes(const ugks_t *h) { return h ? h->bytes : 0; }
 extern "C" int ugks_sweep_kind(const ugks_t *h) { return h ? (h->push ? UGKS_SWEEP_PUSH : UGKS_SWEEP_GATHER) : -1; }
 
+extern "C" int ugks_sweep_colours(const ugks_t *h)
+{
+    if (!h) return -1;
+    return h->push ? (int)h->colour_off.size() - 1 : 0;
+}
+
 extern "C" int ugks_is_tensor_grid(const ugks_t *h) { return h ? h->tensor : 0; }
 extern "C" const void *ugks_device_f(const ugks_t *h) { return h ? h->f[h->cur] : nullptr; }
 

@@ -44,6 +44,15 @@ __device__ __forceinline__ double to_f64(double x) { return x; }
 __device__ __forceinline__ double to_f64(float x) { return (double)x; }
 __device__ __forceinline__ double to_f64(bf16s x) { return (double)__uint_as_float((unsigned)x.bits << 16); }
 
+// The value itself, opaque to the compiler: a multiply that produced it can
+// no longer be fused into a later add or subtract, so arithmetic on it sees
+// the rounded value -- as it does when the value is read back from memory.
+__device__ __forceinline__ double opaque(double x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 template <typename FT> __device__ __forceinline__ FT from_f64(double x);
 template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
 template <> __device__ __forceinline__ float from_f64<float>(double x) { return (float)x; }
@@ -810,7 +819,8 @@ template <int D> __device__ __forceinline__ CellStep<D> cell_step(const Params &
 // One-dimensional Gaussian factors of every face's Maxwellian and of f+^n
 // (tables 0..MF-1: the face slots, table MF: the cell); no barrier inside.
 template <int D, int BS>
-__device__ __forceinline__ void fill_tables(const Params &p, const CellGeo<D> &gi, const Prim<D> &pn, double *tab)
+__device__ __forceinline__ void fill_tables(const Params &p, const CellGeo<D> &gi, double lam_c, double U0, double U1,
+                                            double U2, double *tab)
 {
     constexpr int NT = Dim<D>::MF + 1;
     const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
@@ -826,14 +836,21 @@ __device__ __forceinline__ void fill_tables(const Params &p, const CellGeo<D> &g
             if (ax == 1) Ud = e.U[1];
             if (D == 3 && ax == 2) Ud = e.U[D - 1];
         } else {
-            lam = pn.lam;
-            Ud = pn.U[0];
-            if (ax == 1) Ud = pn.U[1];
-            if (D == 3 && ax == 2) Ud = pn.U[D - 1];
+            lam = lam_c;
+            Ud = ax == 0 ? U0 : (ax == 1 ? U1 : U2);
         }
         const double c = p.u1d[idx] - Ud;
         tab[t] = exp(-lam * c * c);
     }
+}
+
+// (the cell's state passed as scalars: a choice between fields of a
+// structure would become a load at a chosen address, which keeps the
+// structure in scratch memory)
+template <int D, int BS>
+__device__ __forceinline__ void fill_tables(const Params &p, const CellGeo<D> &gi, const Prim<D> &pn, double *tab)
+{
+    fill_tables<D, BS>(p, gi, pn.lam, pn.U[0], pn.U[1], pn.U[D - 1], tab);
 }
 
 template <int D> __device__ __forceinline__ int has_wall_face(const Params &p, const CellGeo<D> &gi)
@@ -1443,15 +1460,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 // first (Eq. maxWalldes) and record the step's wall flux.
 // ------------------------------------------------------------------------
 
-// The value itself, opaque to the compiler: a multiply that produced it can
-// no longer be fused into a later add or subtract, so arithmetic on it sees
-// the rounded value -- as it does when the value is read back from memory.
-__device__ __forceinline__ double opaque(double x)
-{
-    asm volatile("" : "+v"(x));
-    return x;
-}
-
 // moments (1, u, (|u|^2 h + b) / 2) of one velocity's values, weighted
 template <int D>
 __device__ __forceinline__ void add_moments(double (&m)[D + 2], double w, const double (&u)[D], double u2, double h,
@@ -1463,64 +1471,154 @@ __device__ __forceinline__ void add_moments(double (&m)[D + 2], double w, const 
     m[D + 1] = fma(0.5 * w, fma(u2, h, b), m[D + 1]);
 }
 
-// the cell's own Gaussian table (slot MF) for (U, lam); no barrier inside
-template <int D, int BS>
-__device__ __forceinline__ void fill_cell_table(const Params &p, const double (&U)[D], double lam, double *tab)
+// Two consecutive values of an f slab in one 2-wide access (the element
+// offset even, so the access is aligned): the per-cell streaming kernels
+// take velocities in pairs when the velocity count is even, which doubles
+// the bytes each load keeps in flight.
+template <typename FT> struct Vec2;
+template <> struct Vec2<double> { using T = double2; };
+template <> struct Vec2<float> { using T = float2; };
+template <typename FT> __device__ __forceinline__ void load2(const FT *__restrict__ q, double &a, double &b)
 {
-    const int ntab = p.ntab;
-    for (int idx = threadIdx.x; idx < ntab; idx += BS) {
-        const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
-        double Ud = U[0];
-        if (ax == 1) Ud = U[1];
-        if (D == 3 && ax == 2) Ud = U[D - 1];
-        const double c = p.u1d[idx] - Ud;
-        tab[Dim<D>::MF * ntab + idx] = exp(-lam * c * c);
+    const typename Vec2<FT>::T v = *reinterpret_cast<const typename Vec2<FT>::T *>(q);
+    a = to_f64(v.x);
+    b = to_f64(v.y);
+}
+template <typename FT> __device__ __forceinline__ void store2(FT *__restrict__ q, FT a, FT b)
+{
+    typename Vec2<FT>::T v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<typename Vec2<FT>::T *>(q) = v;
+}
+
+// velocity k's components of the velocity set
+template <int D>
+__device__ __forceinline__ void velocity(const Params &p, int k, double (&u)[D], double &u2)
+{
+    u2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        u[d] = p.u[d * p.nv + k];
+        u2 = fma(u[d], u[d], u2);
     }
 }
 
+// Sum over the 64 lanes of a wavefront.  Every lane ends with the same
+// bits: each butterfly step adds the same two values in both partner lanes.
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// The cell's own Gaussian factor table for (U, lam), filled by one
+// wavefront into its own LDS region (ntab doubles), and a lookup in it.
+template <int D>
+__device__ __forceinline__ void fill_wave_table(const Params &p, const double (&U)[D], double lam, double *tb, int lane)
+{
+    const double U0 = U[0], U1 = U[1], U2 = U[D - 1];
+    for (int idx = lane; idx < p.ntab; idx += 64) {
+        const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+        const double Ud = ax == 0 ? U0 : (ax == 1 ? U1 : U2);
+        const double c = p.u1d[idx] - Ud;
+        tb[idx] = exp(-lam * c * c);
+    }
+    // the lanes' LDS writes before any lane of the wavefront reads them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <int D>
+__device__ __forceinline__ double wave_table_gauss(const Params &p, const double *tb, unsigned kx)
+{
+    double g = tb[kx & 1023u] * tb[p.n1d[0] + ((kx >> 10) & 1023u)];
+    if constexpr (D == 3) g *= tb[p.n1d[0] + p.n1d[1] + (kx >> 20)];
+    return g;
+}
+template <int D, bool TENSOR>
+__device__ __forceinline__ double own_gauss(const Params &p, const double *tb, unsigned kx, const double (&u)[D],
+                                            double lam, const double (&U)[D])
+{
+    if constexpr (TENSOR) {
+        return wave_table_gauss<D>(p, tb, kx);
+    } else {
+        double c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double c = u[d] - U[d];
+            c2 += c * c;
+        }
+        return exp(-lam * c2);
+    }
+}
+
+// The per-cell streaming kernels of the push sweep run one wavefront per
+// cell (four cells per workgroup, consecutive): the reductions over a
+// cell's velocities are lane butterflies, with no workgroup barrier, so
+// that each wavefront streams its slab without waiting for others.
+constexpr int kPushCellsPerGroup = 4;
+
 // Stage-1 base of cell i and its moments: acc = f + (dt / 2 tau)(f+ - f)
 // from f^n, W^n, q^n (after a start, a restart or a step of another kind).
-template <int D, typename FT, int BS, bool TENSOR>
-__global__ __launch_bounds__(BS) void k_push_base(Params p, const FT *__restrict__ fin, FT *__restrict__ acc)
+// V2: velocities in pairs (even velocity count).  Same lane order and
+// arithmetic as the final kernel's pass 3, so both give the same bits.
+template <int D, typename FT, bool TENSOR, bool V2>
+__global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restrict__ fin, FT *__restrict__ acc)
 {
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2;
+    constexpr int NC = Dim<D>::NC, NW = D + 2, VW = V2 ? 2 : 1;
     extern __shared__ double smem[];
-    const int i = xcd_cell(blockIdx.x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = kPushCellsPerGroup * xcd_cell(blockIdx.x) + wv;
     if (i >= p.nc) return;
-    const int nv = p.nv, ntab = TENSOR ? p.ntab : 0;
+    const int nv = p.nv;
     const CellStep<D> cs = cell_step<D>(p, i);
-    if constexpr (TENSOR) fill_cell_table<D, BS>(p, cs.pn.U, cs.pn.lam, smem);
-    __syncthreads();
-    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
-    double *red = smem + (MF + 1) * ntab;
+    double *tb = smem + (size_t)wv * (TENSOR ? p.ntab : 0);
+    if constexpr (TENSOR) fill_wave_table<D>(p, cs.pn.U, cs.pn.lam, tb, lane);
     const size_t base = (size_t)i * NC * nv;
     double mom[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) mom[m] = 0.0;
 #pragma unroll 4
-    for (int k = threadIdx.x; k < nv; k += BS) {
-        double u[D], u2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            u[d] = p.u[d * nv + k];
-            u2 = fma(u[d], u[d], u2);
-        }
-        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-        double fp[2];
-        const double H = cs.pref_n * gauss(MF, kx, u, cs.pn.lam, cs.pn.U);
-        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
-        double bv[2] = {0.0, 0.0};
+    for (int k0 = VW * lane; k0 < nv; k0 += VW * 64) {
+        double f[VW][2];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double f = to_f64(fin[base + (size_t)c * nv + k]);
-            const FT s = from_f64<FT>(fma(cs.hdt_tau, fp[c] - f, f));
-            acc[base + (size_t)c * nv + k] = s;
-            bv[c] = to_f64(s);
+            if constexpr (V2)
+                load2<FT>(fin + base + (size_t)c * nv + k0, f[0][c], f[1][c]);
+            else
+                f[0][c] = to_f64(fin[base + (size_t)c * nv + k0]);
         }
-        add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+        FT sv[VW][2];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int k = k0 + e;
+            double u[D], u2;
+            velocity<D>(p, k, u, u2);
+            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+            double fp[2];
+            const double H = cs.pref_n * own_gauss<D, TENSOR>(p, tb, kx, u, cs.pn.lam, cs.pn.U);
+            shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
+            double bv[2] = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                sv[e][c] = from_f64<FT>(fma(cs.hdt_tau, fp[c] - f[e][c], f[e][c]));
+                bv[c] = to_f64(sv[e][c]);
+            }
+            add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if constexpr (V2)
+                store2<FT>(acc + base + (size_t)c * nv + k0, sv[0][c], sv[1][c]);
+            else
+                acc[base + (size_t)c * nv + k0] = sv[0][c];
+        }
     }
-    block_reduce_wide<BS>(mom, red, OpAdd{});
-    if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = wave_sum(mom[m]);
+    if (lane == 0)
 #pragma unroll
         for (int m = 0; m < NW; ++m) p.mom_part[(size_t)i * NW + m] = mom[m];
 }
@@ -1619,8 +1717,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
     const FaceGeo<D> *fg = static_cast<const FaceGeo<D> *>(p.fgeo);
     const FaceEq<D> *fe = static_cast<const FaceEq<D> *>(p.feq);
     const int nv = p.nv, nf = gi.nf, ntab = TENSOR ? p.ntab : 0;
-    const CellStep<D> cs = cell_step<D>(p, i);
-    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, cs.pn, smem);
+    if constexpr (TENSOR) fill_tables<D, BS>(p, gi, to_prim<D>(p.W + (size_t)i * (D + 2)), smem);
     __syncthreads();
     const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
     // wall densities of this cell's wall faces, from the step's wall kernel
@@ -1769,83 +1866,132 @@ __global__ __launch_bounds__(BS) void k_push_pf(
 }
 
 // After the last colour: W^{n+1}, tau^{n+1}, q^{n+1}, stage 2 into f and the
-// next step's base into the accumulator.  S1L: the stage-1 slab is kept in
-// LDS between the passes (else re-read from the accumulator).
-template <int D, typename FT, int BS, bool TENSOR, bool S1L>
-__global__ __launch_bounds__(BS) void k_push_final(Params p, FT *__restrict__ fout, FT *__restrict__ acc)
+// next step's base into the accumulator; one wavefront per cell.
+//   pass 1: moments of the stage-1 values h (and b) about U^n -- orders 0 to
+//           3 of h, 0 and 1 of b -- in one sweep of the slab;
+//   macro:  mass, momentum and energy from them -> W^{n+1}, tau^{n+1}; the
+//           heat flux about U^{n+1} from the same moments, re-centred by
+//           delta = U^{n+1} - U^n (exact algebra: the third-order moment of
+//           (c - delta) expanded in delta), so no second pass is needed;
+//   pass 2: stage 2 (Eq. microS2) into f, the base into acc (re-reading the
+//           slab, which the cell's wavefront has just streamed through L2).
+// V2: velocities in pairs, in the order of the base kernel.
+template <int D> constexpr int sym_index(int a, int b)
 {
-    constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NW = D + 2, NT = MF + 1;
+    return a <= b ? a * D - a * (a - 1) / 2 + (b - a) : b * D - b * (b - 1) / 2 + (a - b);
+}
+
+template <int D, typename FT, bool TENSOR, bool V2>
+__global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ fout, FT *__restrict__ acc)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2, VW = V2 ? 2 : 1, NM = D * (D + 1) / 2;
     extern __shared__ double smem[];
-    const int i = xcd_cell(blockIdx.x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = kPushCellsPerGroup * xcd_cell(blockIdx.x) + wv;
     if (i >= p.nc) return;
-    const int tid = threadIdx.x, nv = p.nv, ntab = TENSOR ? p.ntab : 0;
-    const CellGeo<D> &gi = static_cast<const CellGeo<D> *>(p.cgeo)[i];
+    const int nv = p.nv;
     const double dt = p.dt, Pr = p.Pr;
     const size_t base = (size_t)i * NC * nv;
-    double *red = smem + NT * ntab;
-    FT *s1 = S1L ? reinterpret_cast<FT *>(red + (BS / 64) * (2 * NW)) : acc + base;
     double Wn[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
+    const Prim<D> pn = to_prim<D>(Wn);
 
-    // pass 1: moments of the stage-1 values (unrolled: several loads of the
-    // slab in flight per wavefront)
-    double mom[NW];
+    // pass 1
+    double m0 = 0.0, m1[D], m2[NM], m3[D], b0 = 0.0, b1[D];
 #pragma unroll
-    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+    for (int d = 0; d < D; ++d) m1[d] = m3[d] = b1[d] = 0.0;
+#pragma unroll
+    for (int t = 0; t < NM; ++t) m2[t] = 0.0;
 #pragma unroll 4
-    for (int k = tid; k < nv; k += BS) {
-        double u[D], u2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            u[d] = p.u[d * nv + k];
-            u2 = fma(u[d], u[d], u2);
-        }
-        double v[2] = {0.0, 0.0};
+    for (int k0 = VW * lane; k0 < nv; k0 += VW * 64) {
+        double v[VW][2];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const FT x = acc[base + (size_t)c * nv + k];
-            if constexpr (S1L) s1[(size_t)c * nv + k] = x;
-            v[c] = to_f64(x);
+            if constexpr (V2)
+                load2<FT>(acc + base + (size_t)c * nv + k0, v[0][c], v[1][c]);
+            else
+                v[0][c] = to_f64(acc[base + (size_t)c * nv + k0]);
         }
-        add_moments<D>(mom, p.w[k], u, u2, v[0], NC > 1 ? v[NC - 1] : 0.0);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int k = k0 + e;
+            const double w = p.w[k];
+            double c[D], c2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                c[d] = p.u[d * nv + k] - pn.U[d];
+                c2 = fma(c[d], c[d], c2);
+            }
+            const double wh = w * v[e][0];
+            m0 += wh;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double whc = wh * c[a];
+                m1[a] += whc;
+                m3[a] = fma(whc, c2, m3[a]);
+#pragma unroll
+                for (int bb = a; bb < D; ++bb) m2[sym_index<D>(a, bb)] = fma(whc, c[bb], m2[sym_index<D>(a, bb)]);
+            }
+            if constexpr (NC > 1) {
+                const double wb = w * v[e][NC - 1];
+                b0 += wb;
+#pragma unroll
+                for (int a = 0; a < D; ++a) b1[a] = fma(wb, c[a], b1[a]);
+            }
+        }
     }
-    block_reduce_wide<BS>(mom, red, OpAdd{});
+    m0 = wave_sum(m0);
+    b0 = wave_sum(b0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        m1[d] = wave_sum(m1[d]);
+        m3[d] = wave_sum(m3[d]);
+        b1[d] = wave_sum(b1[d]);
+    }
+#pragma unroll
+    for (int t = 0; t < NM; ++t) m2[t] = wave_sum(m2[t]);
+
+    // macro: mass, momentum, energy of the stage-1 values
+    double mom[NW], trm2 = 0.0, um1 = 0.0, uu = 0.0;
+    mom[0] = m0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        mom[1 + a] = fma(pn.U[a], m0, m1[a]);
+        trm2 += m2[sym_index<D>(a, a)];
+        um1 = fma(pn.U[a], m1[a], um1);
+        uu = fma(pn.U[a], pn.U[a], uu);
+    }
+    mom[D + 1] = 0.5 * (trm2 + 2.0 * um1 + uu * m0 + b0);
     double W1[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) W1[m] = Wn[m] + (mom[m] - p.mom_part[(size_t)i * NW + m]);
     const Prim<D> p1 = to_prim<D>(W1);
     const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
-
-    // pass 2: heat flux of the stage-1 distribution about U^{n+1}
-    double qt[D];
+    // heat flux about U^{n+1}: sum w (c' |c'|^2 h + c' b) / 2 with c' = c - delta
+    double dl[D], d2 = 0.0, m1d = 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) qt[d] = 0.0;
-    for (int k = tid; k < nv; k += BS) {
-        double c[D], c2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            c[d] = p.u[d * nv + k] - p1.U[d];
-            c2 += c[d] * c[d];
-        }
-        const double h = to_f64(s1[k]);
-        const double b = NC > 1 ? to_f64(s1[(size_t)(NC - 1) * nv + k]) : 0.0;
-        const double wt = 0.5 * p.w[k] * (c2 * h + b);
-#pragma unroll
-        for (int d = 0; d < D; ++d) qt[d] += wt * c[d];
+    for (int a = 0; a < D; ++a) {
+        dl[a] = p1.U[a] - pn.U[a];
+        d2 = fma(dl[a], dl[a], d2);
+        m1d = fma(m1[a], dl[a], m1d);
     }
-    block_reduce_wide<BS>(qt, red, OpAdd{});
     double q1[D];
+    const double qden = 1.0 + Pr * dt / (2.0 * tau1);
 #pragma unroll
-    for (int d = 0; d < D; ++d) q1[d] = qt[d] / (1.0 + Pr * dt / (2.0 * tau1));
-
-    if constexpr (TENSOR) {
-        fill_cell_table<D, BS>(p, p1.U, p1.lam, smem);
-        __syncthreads();
+    for (int a = 0; a < D; ++a) {
+        double m2d = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) m2d = fma(m2[sym_index<D>(a, bb)], dl[bb], m2d);
+        const double qa = m3[a] - 2.0 * m2d + d2 * m1[a] - dl[a] * trm2 + 2.0 * dl[a] * m1d - dl[a] * d2 * m0 + b1[a] -
+                          dl[a] * b0;
+        q1[a] = 0.5 * qa / qden;
     }
-    const Gauss<D, TENSOR> gauss{smem, ntab, p.n1d[0], p.n1d[0] + p.n1d[1]};
 
-    // pass 3: stage 2 (Eq. microS2) into f, the next step's base into acc
+    double *tb = smem + (size_t)wv * (TENSOR ? p.ntab : 0);
+    if constexpr (TENSOR) fill_wave_table<D>(p, p1.U, p1.lam, tb, lane);
+
+    // pass 2: stage 2 into f, the next step's base into acc
     const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
     const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
     const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
@@ -1853,33 +1999,52 @@ __global__ __launch_bounds__(BS) void k_push_final(Params p, FT *__restrict__ fo
     double mb[NW];
 #pragma unroll
     for (int m = 0; m < NW; ++m) mb[m] = 0.0;
-    for (int k = tid; k < nv; k += BS) {
-        double u[D], u2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            u[d] = p.u[d * nv + k];
-            u2 = fma(u[d], u[d], u2);
-        }
-        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-        double fp[2];
-        const double H = pref_1 * gauss(MF, kx, u, p1.lam, p1.U);
-        shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
-        double bv[2] = {0.0, 0.0};
+#pragma unroll 2
+    for (int k0 = VW * lane; k0 < nv; k0 += VW * 64) {
+        double sv[VW][2];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const FT fn = from_f64<FT>((to_f64(s1[(size_t)c * nv + k]) + a1 * fp[c]) * inv1);
-            fout[base + (size_t)c * nv + k] = fn;
-            // the base from f^{n+1} as stored (bitwise what the base kernel
-            // computes from it after a restart)
-            const double fd = opaque(to_f64(fn));
-            const FT bs = from_f64<FT>(fma(a1, fp[c] - fd, fd));
-            acc[base + (size_t)c * nv + k] = bs;
-            bv[c] = to_f64(bs);
+            if constexpr (V2)
+                load2<FT>(acc + base + (size_t)c * nv + k0, sv[0][c], sv[1][c]);
+            else
+                sv[0][c] = to_f64(acc[base + (size_t)c * nv + k0]);
         }
-        add_moments<D>(mb, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+        FT fo[VW][2], bo[VW][2];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int k = k0 + e;
+            double u[D], u2;
+            velocity<D>(p, k, u, u2);
+            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+            double fp[2];
+            const double H = pref_1 * own_gauss<D, TENSOR>(p, tb, kx, u, p1.lam, p1.U);
+            shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
+            double bv[2] = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fo[e][c] = from_f64<FT>((sv[e][c] + a1 * fp[c]) * inv1);
+                // the base from f^{n+1} as stored (bitwise what the base
+                // kernel computes from it after a restart)
+                const double fd = opaque(to_f64(fo[e][c]));
+                bo[e][c] = from_f64<FT>(fma(a1, fp[c] - fd, fd));
+                bv[c] = to_f64(bo[e][c]);
+            }
+            add_moments<D>(mb, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if constexpr (V2) {
+                store2<FT>(fout + base + (size_t)c * nv + k0, fo[0][c], fo[1][c]);
+                store2<FT>(acc + base + (size_t)c * nv + k0, bo[0][c], bo[1][c]);
+            } else {
+                fout[base + (size_t)c * nv + k0] = fo[0][c];
+                acc[base + (size_t)c * nv + k0] = bo[0][c];
+            }
+        }
     }
-    block_reduce_wide<BS>(mb, red, OpAdd{});
-    if (tid == 0) {
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mb[m] = wave_sum(mb[m]);
+    if (lane == 0) {
         bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
 #pragma unroll
         for (int m = 0; m < NW; ++m) {
@@ -1896,7 +2061,6 @@ __global__ __launch_bounds__(BS) void k_push_final(Params p, FT *__restrict__ fo
             atomicMin(p.err + 1, i);
         }
     }
-    (void)gi;
 }
 
 // ------------------------------------------------------------------------
@@ -2251,8 +2415,6 @@ hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s
 // push sweep launches: the stage-1 base (when stale), one launch per colour,
 // the final kernel
 // ------------------------------------------------------------------------
-constexpr size_t kLdsPushFinal = 64 * 1024;
-
 template <int D, typename FT, bool TENSOR>
 hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int *cells, const int *coff, int ncol,
                   const int *wall_cells, int n_wall_cells, hipStream_t s)
@@ -2262,11 +2424,18 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
     FT *f = static_cast<FT *>(fv), *acc = static_cast<FT *>(av);
     const size_t tab = sizeof(double) * (size_t)(MF + 1) * (TENSOR ? p.ntab : 0);
     const size_t red = sizeof(double) * ((BS / 64) * (2 * NW + 2) + MF);
-    const unsigned gc = (unsigned)sweep_grid(p.nc);
-    constexpr int BSF = 256;  // the per-cell streaming kernels (base, final)
-    const size_t redf = sizeof(double) * (BSF / 64) * (2 * NW + 2);
-    if (need_base)
-        hipLaunchKernelGGL((k_push_base<D, FT, BSF, TENSOR>), dim3(gc), dim3(BSF), tab + redf, s, p, fin, acc);
+    // the per-cell streaming kernels: a wavefront per cell, four per group;
+    // velocity pairs when the count is even (every slab offset is then
+    // even: aligned 2-wide accesses)
+    const unsigned gw = (unsigned)sweep_grid((p.nc + kPushCellsPerGroup - 1) / kPushCellsPerGroup);
+    const size_t ltab = sizeof(double) * (size_t)kPushCellsPerGroup * (TENSOR ? p.ntab : 0);
+    const bool v2 = p.nv % 2 == 0;
+    if (need_base) {
+        if (v2)
+            hipLaunchKernelGGL((k_push_base<D, FT, TENSOR, true>), dim3(gw), dim3(256), ltab, s, p, fin, acc);
+        else
+            hipLaunchKernelGGL((k_push_base<D, FT, TENSOR, false>), dim3(gw), dim3(256), ltab, s, p, fin, acc);
+    }
     if (n_wall_cells > 0)
         hipLaunchKernelGGL((k_push_wall<D, FT, BS, TENSOR>), dim3(n_wall_cells), dim3(BS), tab + red, s, p, fin,
                            wall_cells, n_wall_cells);
@@ -2280,12 +2449,10 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
             hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c],
                                n);
     }
-    const size_t slab = sizeof(FT) * (size_t)NC * p.nv;
-    if (tab + redf + slab <= kLdsPushFinal)
-        hipLaunchKernelGGL((k_push_final<D, FT, BSF, TENSOR, true>), dim3(gc), dim3(BSF), tab + redf + slab, s, p, f,
-                           acc);
+    if (v2)
+        hipLaunchKernelGGL((k_push_final<D, FT, TENSOR, true>), dim3(gw), dim3(256), ltab, s, p, f, acc);
     else
-        hipLaunchKernelGGL((k_push_final<D, FT, BSF, TENSOR, false>), dim3(gc), dim3(BSF), tab + redf, s, p, f, acc);
+        hipLaunchKernelGGL((k_push_final<D, FT, TENSOR, false>), dim3(gw), dim3(256), ltab, s, p, f, acc);
     return hipGetLastError();
 }
 

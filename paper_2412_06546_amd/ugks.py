@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     L.ugks_footprint_bytes.argtypes = [C.c_void_p]
     L.ugks_sweep_kind.restype = C.c_int
     L.ugks_sweep_kind.argtypes = [C.c_void_p]
+    L.ugks_sweep_colours.restype = C.c_int
+    L.ugks_sweep_colours.argtypes = [C.c_void_p]
     L.ugks_is_tensor_grid.restype = C.c_int
     L.ugks_is_tensor_grid.argtypes = [C.c_void_p]
     L.ugks_profile.restype = C.c_int
@@ -247,6 +249,11 @@ class Solver:
     def sweep(self) -> str:
         """'push' or 'gather': how this handle's steps evaluate the face fluxes."""
         return {UGKS_SWEEP_PUSH: "push", UGKS_SWEEP_GATHER: "gather"}[self._L.ugks_sweep_kind(self._h)]
+
+    @property
+    def n_colours(self) -> int:
+        """Colour classes of the push sweep (one launch each per step); 0 when gathering."""
+        return self._L.ugks_sweep_colours(self._h)
 
     @property
     def tensor_grid(self) -> bool:

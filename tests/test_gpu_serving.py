@@ -47,6 +47,7 @@ def test_footprint_estimate_matches_allocation():
                 # the automatic choice: push, except 2D FP64 and BF16 f
                 auto = "gather" if fs == "bf16" or (dim == 2 and fs == "f64") else "push"
                 assert s.sweep == (auto if sw == "auto" else sw), (c.get("name"), fs, sw)
+                assert (s.n_colours > 0) == (s.sweep == "push")
                 s.close()
     # the push sweep needs two buffers and FP64 or FP32 f
     assert ugks.footprint_estimate(cs[0], "bf16", sweep="push") == 0
