@@ -23,8 +23,10 @@ Prints one JSON line:
              algorithmic FP64 flops against 78.6 TFLOP/s);
   other_precision   the same workload with f in FP32 and BF16;
   secondary_workloads   the 2D cylinder (20,000 cells x 3,600 velocities);
-  serving    a bounded continuous-batching leg: 16 small 2D cases run to a
-             relative residual of 1e-6, p50/p99 time-to-converged;
+  serving    a bounded serving leg: a Poisson stream of 16 small 2D cases
+             (supersonic cylinders, FP64 f) each run to a relative residual
+             of 1e-6 (cap 60,000 steps): converged and capped counts, p50/p99
+             time-to-converged, updates/s;
   cpu_baseline   the FP64 CPU oracle on the host cores on a bounded sample of
              the lifting body (same velocity set and cell types, fewer cells).
 """
@@ -236,9 +238,9 @@ def roofline_of(case, run, workload, fstore, mem):
 
 def run_serving_leg(n_cases: int, max_steps: int, mode: str):
     """The bounded serving leg: a Poisson stream of small 2D cases (2k-5k
-    triangles and quadrilaterals, 20^2-32^2 velocities, Ma 0.5-3, Kn
-    0.05-1, FP32 f with FP64 macros), each run to a residual of 1e-6 of its
-    first step's or the step cap, continuous batching under an HBM budget."""
+    triangles and quadrilaterals, 20^2-32^2 velocities, Ma 1.5-3, Kn
+    0.05-1, FP64 f), each run to a residual of 1e-6 of its first step's or
+    the step cap, continuous batching under an HBM budget."""
     from paper_2412_06546_amd import serve
     reqs = serve.converging_stream(n_cases=n_cases, max_steps=max_steps)
     backend = serve.GpuBackend(batched=mode == "batched")
@@ -246,7 +248,7 @@ def run_serving_leg(n_cases: int, max_steps: int, mode: str):
     res = srv.run(reqs)
     summ = serve.Server.summary(res)
     summ["workload"] = (f"Poisson stream (8/s) of {len(reqs)} cylinder cases, 2k-5k cells, 20^2-32^2 velocities, "
-                        f"Ma 0.5-3, Kn 0.05-1, tol 1e-6, cap {max_steps} steps, f32")
+                        f"Ma 1.5-3, Kn 0.05-1, tol 1e-6, cap {max_steps} steps, f64")
     summ["mode"] = mode
     summ["peak_bytes"] = srv.peak_used
     for r in res:
@@ -294,7 +296,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-leg-cases", type=int, default=16)
-    ap.add_argument("--serving-leg-steps", type=int, default=20000)
+    ap.add_argument("--serving-leg-steps", type=int, default=60000)
+    ap.add_argument("--serving-leg-mode", choices=["batched", "streams"], default="streams",
+                    help="serving leg: batched steps on one stream, or a stream per case (measured the faster)")
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="instead: serve a Poisson stream (4/s) of N cylinder cases (2k-50k cells) and report p50/p99")
     ap.add_argument("--serving-steps", type=int, default=400, help="step cap per served case (--serving)")
@@ -373,7 +377,7 @@ def main():
         line["secondary_workloads"] = sec
     if not args.no_serving:
         print("# serving leg ...", file=sys.stderr, flush=True)
-        line["serving"] = run_serving_leg(args.serving_leg_cases, args.serving_leg_steps, "batched")
+        line["serving"] = run_serving_leg(args.serving_leg_cases, args.serving_leg_steps, args.serving_leg_mode)
     if not args.no_cpu_baseline and args.workload == "liftingbody":
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
