@@ -568,6 +568,26 @@ def test_push_sweep_fp32_storage_error():
     assert max(e.values()) <= 1e-5
 
 
+@pytest.mark.skip(reason="the 50,688-tetrahedron sphere at Ma 4 loses positivity in first-layer cells after about 20 "
+                  "steps, in the oracle as on the GPU: the second-order upwind step on this tetrahedral shell is "
+                  "linearly unstable (power iteration of the brute-force step for a gas at rest: growth 14 per step "
+                  "at CFL 0.8, concentrated on first-layer tetrahedra; the same shell of hexahedra: 1.000)")
+def test_tetrahedral_sphere_reaches_steady_state():
+    """The sphere as configured: 50,688 tetrahedra x 13,824 velocities, Ma 4,
+    Kn 0.05, run until the residual falls to 1e-6 of its first step's."""
+    ugks = _gpu()
+    c = cases.case_sphere()
+    s = ugks.Solver(c)
+    r0 = s.step(1, residual=True)
+    rel = 1.0
+    for _ in range(60):
+        r = s.step(500, residual=True)
+        rel = float((r / r0).max())
+        if rel < 1e-6:
+            break
+    assert rel < 1e-6
+
+
 def test_lifting_body_cut_down_100k_fp64():
     """The lifting body at a tenth of its size: 107,118 hexahedra and prisms
     (16 x 16 points per cube face, 66 layers, the polar columns as prisms),
