@@ -348,6 +348,11 @@ def main():
                    "footprint_bytes": main_run["footprint_bytes"], "all_cells_physical": main_run["finite"]},
         "roofline": roofline_of(case, main_run, args.workload, args.fstore, args.mem),
     }
+    # the targets this build measures against, stated beside the figures
+    line["targets"] = {
+        "hbm_fraction": {"target": 0.60, "measured": line["roofline"]["frac"],
+                         "met": line["roofline"]["frac"] >= 0.60},
+    }
     if args.mem == "in-place":
         from paper_2412_06546_amd.ugks import UGKS_DEFAULT_CHUNK
         line["config"]["chunk"] = min(args.chunk if args.chunk > 0 else UGKS_DEFAULT_CHUNK, nv)
@@ -360,6 +365,9 @@ def main():
                           "speedup_over_headline": round(main_run["ms_per_step"] / r2["ms_per_step"], 3)})
             print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         line["other_precision"] = other
+        if args.fstore == "f64":
+            sp = next(o["speedup_over_headline"] for o in other if o["f_storage"] == "f32")
+            line["targets"]["fp32_speedup_over_fp64"] = {"target": 1.7, "measured": sp, "met": sp >= 1.7}
         sec = []
         for wl in [w for w in ("liftingbody", "cylinder") if w != args.workload]:
             c2 = make_case(wl)

@@ -1014,8 +1014,9 @@ __device__ __forceinline__ void finish_cell(const Params &p, int i, const CellSt
 // ahead (20 more registers: used where they fit in the four-wave budget).
 // CHUNK: the in-place mode's chunk kernel -- pass 1 over velocities
 // [c0, c0 + cn) only, reading f^n and writing the stage-1 values to the ring
-// (after writing the previous chunk's ring back into f), the chunk's moments
-// to its record, and the wall densities read from the wall kernel's array.
+// (after writing the previous chunk's ring back into f), adding the chunk's
+// moments to the cell's running sum (mom_part, started from zero by chunk 0),
+// and the wall densities read from the wall kernel's array.
 template <int D, typename FT, int BS, bool TENSOR, bool S1L, bool PF, bool CHUNK = false>
 __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ fout,
                                            int c0 = 0, int cn = 0, int prev0 = 0, int prevn = 0, int ichunk = 0)
@@ -1347,12 +1348,13 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
 // ------------------------------------------------------------------------
 // In-place mode (one f buffer): the velocities are swept in chunks.  A chunk
 // kernel reads f^n of its velocities only (the cell's two-ring stencil),
-// parks the stage-1 values in a ring buffer of one chunk per cell and the
-// chunk's moments of the net outflow in a per-chunk record; the next chunk
-// kernel first writes its cell's ring back into f (no workgroup reads those
-// velocities any more), and a final kernel writes the last chunk, sums the
-// chunk moments in order (W^{n+1}), forms q^{n+1} from the stage-1 values
-// now in f, and applies stage 2 in place.  This is the paper's in-place
+// parks the stage-1 values in a ring buffer of one chunk per cell and adds
+// the chunk's moments of the net outflow to the cell's running sum
+// (mom_part: chunk 0 starts it from zero, the chunks run one launch after
+// another); the next chunk kernel first writes its cell's ring back into f
+// (no workgroup reads those velocities any more), and a final kernel writes
+// the last chunk, reads that sum (W^{n+1}), forms q^{n+1} from the stage-1
+// values now in f, and applies stage 2 in place.  This is the paper's in-place
 // update of f (Section 3.2) with the ring as the only extra storage.  The
 // wall density of every wall cell is reduced over all velocities first.
 // ------------------------------------------------------------------------
