@@ -2414,6 +2414,231 @@ hipError_t launch_sweep(const Params &p, const void *fi, void *fo, hipStream_t s
 }
 
 // ------------------------------------------------------------------------
+// Register-resident form of the push sweep's per-cell kernels, for slabs of
+// at most NPT velocities per thread (one 256-thread workgroup per cell;
+// thread t holds velocities t, t + 256, ...): the final kernel loads the
+// whole stage-1 slab into registers in one go -- every load of a thread in
+// flight together -- takes its moments, and applies stage 2 from the
+// registers, so the slab is read once.  The base kernel of this form takes
+// the velocities in the same order and reduces the same way.
+// ------------------------------------------------------------------------
+template <int D, int BS>
+__device__ __forceinline__ void fill_group_table(const Params &p, double lam, double U0, double U1, double U2,
+                                                 double *tb)
+{
+    for (int idx = threadIdx.x; idx < p.ntab; idx += BS) {
+        const int ax = idx < p.n1d[0] ? 0 : (idx < p.n1d[0] + p.n1d[1] ? 1 : 2);
+        const double Ud = ax == 0 ? U0 : (ax == 1 ? U1 : U2);
+        const double c = p.u1d[idx] - Ud;
+        tb[idx] = exp(-lam * c * c);
+    }
+    __syncthreads();
+}
+
+template <int D, typename FT, bool TENSOR>
+__global__ __launch_bounds__(256) void k_push_base_r(Params p, const FT *__restrict__ fin, FT *__restrict__ acc)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int nv = p.nv, tid = threadIdx.x;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    double *tb = smem;
+    double *red = smem + (TENSOR ? p.ntab : 0);
+    if constexpr (TENSOR) fill_group_table<D, BS>(p, cs.pn.lam, cs.pn.U[0], cs.pn.U[1], cs.pn.U[D - 1], tb);
+    const size_t base = (size_t)i * NC * nv;
+    double mom[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+#pragma unroll 4
+    for (int k = tid; k < nv; k += BS) {
+        double u[D], u2;
+        velocity<D>(p, k, u, u2);
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fp[2];
+        const double H = cs.pref_n * own_gauss<D, TENSOR>(p, tb, kx, u, cs.pn.lam, cs.pn.U);
+        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
+        double bv[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double f = to_f64(fin[base + (size_t)c * nv + k]);
+            const FT sv = from_f64<FT>(fma(cs.hdt_tau, fp[c] - f, f));
+            acc[base + (size_t)c * nv + k] = sv;
+            bv[c] = to_f64(sv);
+        }
+        add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+    }
+    block_reduce_wide<BS>(mom, red, OpAdd{});
+    if (tid == 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m) p.mom_part[(size_t)i * NW + m] = mom[m];
+}
+
+template <int D, typename FT, bool TENSOR, int NPT>
+__global__ __launch_bounds__(256) void k_push_final_r(Params p, FT *__restrict__ fout, FT *__restrict__ acc)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2, NM = D * (D + 1) / 2, BS = 256;
+    // moments about U^n: m0, m1[D], m2[NM], m3[D], and for b: b0, b1[D]
+    constexpr int NMOM = 1 + D + NM + D + (NC > 1 ? 1 + D : 0);
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int tid = threadIdx.x, nv = p.nv;
+    const double dt = p.dt, Pr = p.Pr;
+    const size_t base = (size_t)i * NC * nv;
+    double *tb = smem;
+    double *red = smem + (TENSOR ? p.ntab : 0);
+    double Wn[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
+    const Prim<D> pn = to_prim<D>(Wn);
+
+    // pass 1: the slab into registers, in its storage precision (all loads
+    // issued before any use)
+    FT v[NPT][NC];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int k = tid + BS * j;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[j][c] = k < nv ? acc[base + (size_t)c * nv + k] : from_f64<FT>(0.0);
+    }
+    double mm[NMOM];
+#pragma unroll
+    for (int t = 0; t < NMOM; ++t) mm[t] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int k = tid + BS * j;
+        if (k < nv) {
+            const double w = p.w[k];
+            double c[D], c2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                c[d] = p.u[d * nv + k] - pn.U[d];
+                c2 = fma(c[d], c[d], c2);
+            }
+            const double wh = w * to_f64(v[j][0]);
+            mm[0] += wh;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double whc = wh * c[a];
+                mm[1 + a] += whc;
+                mm[1 + D + NM + a] = fma(whc, c2, mm[1 + D + NM + a]);
+#pragma unroll
+                for (int bb = a; bb < D; ++bb)
+                    mm[1 + D + sym_index<D>(a, bb)] = fma(whc, c[bb], mm[1 + D + sym_index<D>(a, bb)]);
+            }
+            if constexpr (NC > 1) {
+                const double wb = w * to_f64(v[j][NC - 1]);
+                mm[1 + 2 * D + NM] += wb;
+#pragma unroll
+                for (int a = 0; a < D; ++a) mm[2 + 2 * D + NM + a] = fma(wb, c[a], mm[2 + 2 * D + NM + a]);
+            }
+        }
+    }
+    block_reduce_wide<BS>(mm, red, OpAdd{});
+    const double m0 = mm[0];
+    const double b0 = NC > 1 ? mm[1 + 2 * D + NM] : 0.0;
+    double m1[D], m3[D], b1[D], m2[NM];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        m1[a] = mm[1 + a];
+        m3[a] = mm[1 + D + NM + a];
+        b1[a] = NC > 1 ? mm[2 + 2 * D + NM + a] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NM; ++t) m2[t] = mm[1 + D + t];
+
+    // macro: as in k_push_final
+    double mom[NW], trm2 = 0.0, um1 = 0.0, uu = 0.0;
+    mom[0] = m0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        mom[1 + a] = fma(pn.U[a], m0, m1[a]);
+        trm2 += m2[sym_index<D>(a, a)];
+        um1 = fma(pn.U[a], m1[a], um1);
+        uu = fma(pn.U[a], pn.U[a], uu);
+    }
+    mom[D + 1] = 0.5 * (trm2 + 2.0 * um1 + uu * m0 + b0);
+    double W1[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) W1[m] = Wn[m] + (mom[m] - p.mom_part[(size_t)i * NW + m]);
+    const Prim<D> p1 = to_prim<D>(W1);
+    const double tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
+    double dl[D], d2 = 0.0, m1d = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dl[a] = p1.U[a] - pn.U[a];
+        d2 = fma(dl[a], dl[a], d2);
+        m1d = fma(m1[a], dl[a], m1d);
+    }
+    double q1[D];
+    const double qden = 1.0 + Pr * dt / (2.0 * tau1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double m2d = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) m2d = fma(m2[sym_index<D>(a, bb)], dl[bb], m2d);
+        const double qa = m3[a] - 2.0 * m2d + d2 * m1[a] - dl[a] * trm2 + 2.0 * dl[a] * m1d - dl[a] * d2 * m0 + b1[a] -
+                          dl[a] * b0;
+        q1[a] = 0.5 * qa / qden;
+    }
+    if constexpr (TENSOR) fill_group_table<D, BS>(p, p1.lam, p1.U[0], p1.U[1], p1.U[D - 1], tb);
+
+    // pass 2: stage 2 from the registers into f, the next base into acc
+    const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
+    const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
+    const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
+    const double bh_1 = Dim<D>::M / (2.0 * p1.lam);
+    double mb[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mb[m] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int k = tid + BS * j;
+        if (k < nv) {
+            double u[D], u2;
+            velocity<D>(p, k, u, u2);
+            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+            double fp[2];
+            const double H = pref_1 * own_gauss<D, TENSOR>(p, tb, kx, u, p1.lam, p1.U);
+            shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
+            double bv[2] = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const FT fo = from_f64<FT>((to_f64(v[j][c]) + a1 * fp[c]) * inv1);
+                fout[base + (size_t)c * nv + k] = fo;
+                // the base from f^{n+1} as stored (bitwise what the base
+                // kernel computes from it after a restart)
+                const double fd = opaque(to_f64(fo));
+                const FT bo = from_f64<FT>(fma(a1, fp[c] - fd, fd));
+                acc[base + (size_t)c * nv + k] = bo;
+                bv[c] = to_f64(bo);
+            }
+            add_moments<D>(mb, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+        }
+    }
+    block_reduce_wide<BS>(mb, red, OpAdd{});
+    if (tid == 0) {
+        bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            ok = ok && isfinite(W1[m]);
+            p.W[(size_t)i * NW + m] = W1[m];
+            const double dw = W1[m] - Wn[m];
+            p.dW2[(size_t)i * NW + m] = dw * dw;
+            p.mom_part[(size_t)i * NW + m] = mb[m];
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.q[(size_t)i * D + d] = q1[d];
+        if (!ok) {
+            atomicOr(p.err, 1);
+            atomicMin(p.err + 1, i);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // push sweep launches: the stage-1 base (when stale), one launch per colour,
 // the final kernel
 // ------------------------------------------------------------------------
@@ -2426,13 +2651,29 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
     FT *f = static_cast<FT *>(fv), *acc = static_cast<FT *>(av);
     const size_t tab = sizeof(double) * (size_t)(MF + 1) * (TENSOR ? p.ntab : 0);
     const size_t red = sizeof(double) * ((BS / 64) * (2 * NW + 2) + MF);
+    const unsigned gc = (unsigned)sweep_grid(p.nc);
     // the per-cell streaming kernels: a wavefront per cell, four per group;
     // velocity pairs when the count is even (every slab offset is then
     // even: aligned 2-wide accesses)
     const unsigned gw = (unsigned)sweep_grid((p.nc + kPushCellsPerGroup - 1) / kPushCellsPerGroup);
     const size_t ltab = sizeof(double) * (size_t)kPushCellsPerGroup * (TENSOR ? p.ntab : 0);
     const bool v2 = p.nv % 2 == 0;
-    if (need_base) {
+    // the register-resident form for FP64 f where a thread's share of the
+    // slab fits in 48 registers (n_comp x NPT values; with FP32 f it measured
+    // slower than the wavefront form)
+    const int npt = (p.nv + 255) / 256;
+    const int slab_regs = NC * 2;
+    int reg_form = 0;
+    if (sizeof(FT) == 8) {
+        if (npt <= 12 && 12 * slab_regs <= 48) reg_form = 12;
+        else if (npt <= 18 && 18 * slab_regs <= 48) reg_form = 18;
+        else if (npt <= 24 && 24 * slab_regs <= 48) reg_form = 24;
+    }
+    const size_t lreg = sizeof(double) * ((TENSOR ? (size_t)p.ntab : 0) + 5 * 16);
+    if (need_base && reg_form) {
+        if constexpr (sizeof(FT) == 8)
+            hipLaunchKernelGGL((k_push_base_r<D, FT, TENSOR>), dim3(gc), dim3(256), lreg, s, p, fin, acc);
+    } else if (need_base) {
         if (v2)
             hipLaunchKernelGGL((k_push_base<D, FT, TENSOR, true>), dim3(gw), dim3(256), ltab, s, p, fin, acc);
         else
@@ -2451,7 +2692,16 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
             hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c],
                                n);
     }
-    if (v2)
+    if (reg_form) {
+        if constexpr (sizeof(FT) == 8) {
+            if (reg_form == 12)
+                hipLaunchKernelGGL((k_push_final_r<D, FT, TENSOR, 12>), dim3(gc), dim3(256), lreg, s, p, f, acc);
+            else if (reg_form == 18)
+                hipLaunchKernelGGL((k_push_final_r<D, FT, TENSOR, 18>), dim3(gc), dim3(256), lreg, s, p, f, acc);
+            else
+                hipLaunchKernelGGL((k_push_final_r<D, FT, TENSOR, 24>), dim3(gc), dim3(256), lreg, s, p, f, acc);
+        }
+    } else if (v2)
         hipLaunchKernelGGL((k_push_final<D, FT, TENSOR, true>), dim3(gw), dim3(256), ltab, s, p, f, acc);
     else
         hipLaunchKernelGGL((k_push_final<D, FT, TENSOR, false>), dim3(gw), dim3(256), ltab, s, p, f, acc);
