@@ -117,15 +117,16 @@ typedef struct {
  * cell with its own limited slope; the cells are coloured so that no two
  * cells of a colour are neighbours or share one, one launch per colour adds
  * each flux to the stage-1 values of both of its cells (the second f buffer
- * holds them), and a final kernel forms W^{n+1}, q^{n+1} and stage 2.
- * Needs two buffers and FP64 or FP32 f.
+ * holds them; in the in-place mode a ring of one velocity chunk does, chunk
+ * after chunk), and a final kernel forms W^{n+1}, q^{n+1} and stage 2.
+ * Needs FP64 or FP32 f.
  * UGKS_SWEEP_GATHER: one workgroup per cell evaluates every face of its cell,
  * rebuilding the upwind neighbour's limited slope where needed (each
- * interior face twice); the in-place mode, BF16 f and batched steps use it.
- * UGKS_SWEEP_AUTO (0): push where it applies, except 2D with FP64 f (there
- * gathering measured faster on MI355X); else gather.  Both give the same
- * results up to the order of sums; ugks_sweep_kind tells which a handle
- * uses. */
+ * interior face twice); BF16 f and batched steps use it.
+ * UGKS_SWEEP_AUTO (0): push where it applies, except 2D with FP64 f in two
+ * buffers (there gathering measured faster on MI355X); else gather.  Both
+ * give the same results up to the order of sums; ugks_sweep_kind tells which
+ * a handle uses. */
 #define UGKS_SWEEP_AUTO 0
 #define UGKS_SWEEP_GATHER 1
 #define UGKS_SWEEP_PUSH 2
@@ -137,16 +138,17 @@ typedef struct {
  * stage-1 values of a chunk wait in a ring of n_cells x n_comp x chunk
  * values until no cell reads that chunk's f^n any more, and stage 2 is
  * applied in place; memory 1 f + the ring + a few doubles per cell (the
- * chunks' moment sum and the wall densities).  Both forms give the same
+ * chunks' moment sums and the wall densities).  Both forms give the same
  * results up to the order of the sums over velocities.  In-place handles
- * cannot be batched (ugks_batch_step) and keep no copy of the f that started
- * a step (ugks_wall_flux returns UGKS_ERR_STATE). */
+ * cannot be batched (ugks_batch_step); with the gather sweep they keep no
+ * copy of the f that started a step (ugks_wall_flux and ugks_surface return
+ * UGKS_ERR_STATE), the push sweep records the wall flux during the step. */
 #define UGKS_MEM_TWO_BUFFERS 0
 #define UGKS_MEM_IN_PLACE 1
 /* Velocities per chunk when gas.chunk is 0 (capped at n_vel).  Every chunk
  * launch repeats the per-cell set-up, so fewer, larger chunks are faster and
  * cost a larger ring (n_cells x n_comp x chunk values of f). */
-#define UGKS_DEFAULT_CHUNK 512
+#define UGKS_DEFAULT_CHUNK 1024
 
 typedef struct ugks ugks_t;
 
@@ -314,9 +316,11 @@ int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
  * of the interior f transported freely; incoming: the wall Maxwellian of
  * density rho_w).  n is the face normal (out of the gas, into the wall):
  * surface pressure p_w = F_m . n, shear stress |F_m - p_w n|, heat flux =
- * the energy component.  Recomputed from the f that started the last step
- * (kept in the second f buffer); UGKS_ERR_STATE if no step ran since
- * creation or ugks_set_f, or while asynchronous steps are outstanding. */
+ * the energy component.  The push sweep records it during the step; after a
+ * gather step it is recomputed from the f that started the step (kept in
+ * the second f buffer).  UGKS_ERR_STATE if no step ran since creation or
+ * ugks_set_f, while asynchronous steps are outstanding, or after an
+ * in-place gather step (which keeps no copy of that f). */
 int ugks_n_wall_faces(const ugks_t *h);
 int ugks_wall_flux(ugks_t *h, double *out);
 

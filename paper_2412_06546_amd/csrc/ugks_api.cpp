@@ -33,8 +33,9 @@ struct ugks {
     // since creation or set_f (f[1 - cur] then holds the f that started it)
     int mem_mode = UGKS_MEM_TWO_BUFFERS;
     void *ring = nullptr;          // in-place mode: one chunk of stage-1 values per cell
-    double *mom_part = nullptr;    // in-place mode: moments of the chunks swept so far
-    double *rho_w = nullptr;       // in-place mode: wall densities
+    double *mom_part = nullptr;    // moments of the chunks swept so far (in place) or of the stage-1 base (push)
+    double *rho_w = nullptr;       // wall densities (in place, push)
+    double *mom_s = nullptr;       // push sweep in place: stage-1 moments about U^n summed over the chunks
     // push sweep: colour lists (device cells, host offsets), wall cells,
     // face -> wall ordinal; whether the second buffer holds the stage-1 base
     // of the current f, and whether the last step was a push step (the wall
@@ -508,17 +509,19 @@ int chunk_of(int chunk, int nv) { return std::min(chunk > 0 ? chunk : UGKS_DEFAU
 int nchunk_of(int chunk, int nv) { return (nv + chunk - 1) / chunk; }
 
 // whether a handle sweeps by pushing each face flux once (else gathering).
-// Automatic choice: push, except for 2D with FP64 f, where gathering is
-// faster on MI355X (2D hypersonic cylinder, 20,000 cells x 3,600
-// velocities: 3.2 against 4.4 ms per step; FP32 f 2.8 push against 2.9
-// gather; the 3D lifting body 197 push against 295 ms gather in FP64).
-bool push_applies(const ugks_gas_t *gas) { return gas->mem_mode == UGKS_MEM_TWO_BUFFERS && gas->fstore != UGKS_BF16; }
+// Automatic choice: push, except for 2D with FP64 f in two buffers, where
+// gathering is faster on MI355X (2D hypersonic cylinder, 20,000 cells x
+// 3,600 velocities: 3.2 against 4.2 ms per step; FP32 f 2.7 push against 2.9
+// gather; the 3D lifting body 178 push against 295 ms gather in FP64).
+bool push_applies(const ugks_gas_t *gas) { return gas->fstore != UGKS_BF16; }
 bool uses_push(int dim, const ugks_gas_t *gas)
 {
     if (!push_applies(gas) || gas->sweep == UGKS_SWEEP_GATHER) return false;
-    if (gas->sweep == UGKS_SWEEP_PUSH) return true;
+    if (gas->sweep == UGKS_SWEEP_PUSH || gas->mem_mode == UGKS_MEM_IN_PLACE) return true;
     return !(dim == 2 && gas->fstore == UGKS_F64);
 }
+// the push sweep's running moment sums about U^n, per cell (in place)
+int shift_moments(int D) { return D == 2 ? 11 : 13; }
 
 size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, size_t ntab, size_t nwallf,
                   int mem_mode = UGKS_MEM_TWO_BUFFERS, int chunk = 0, bool push = false)
@@ -538,9 +541,13 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
     } else {
         b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
     }
-    if (push)  // colour lists, wall cells, face -> wall ordinal, base moments, wall densities
-        b += nbytes<int>(nc) + nbytes<int>(nwallf) + nbytes<int>(nf) + nbytes<double>(nc * NW) +
-             nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
+    if (push) {  // colour lists, wall cells, face -> wall ordinal
+        b += nbytes<int>(nc) + nbytes<int>(nwallf) + nbytes<int>(nf);
+        if (mem_mode == UGKS_MEM_IN_PLACE)  // the running moments about U^n
+            b += nbytes<double>(nc * (size_t)shift_moments(D));
+        else  // base moments, wall densities
+            b += nbytes<double>(nc * NW) + nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
+    }
     b += nbytes<int>(nwallf) + nbytes<double>(nwallf * NW) + nbytes<double>(nwallf * 6);
     return b;
 }
@@ -591,7 +598,7 @@ void release(ugks_t *h)
     if (h->done_ev) (void)hipEventDestroy(h->done_ev);
     void *ptrs[] = {h->f[0], h->f[1], h->cgeo, h->fgeo, h->feq, h->u, h->w, h->bcp, h->W, h->q, h->gW, h->dW2,
                     h->cell_dt, h->res, h->err, h->u1d, h->kidx, h->wallf, h->wallF, h->surf, h->ring, h->mom_part, h->rho_w,
-                    h->colour_cells, h->wall_cells, h->wall_index};
+                    h->mom_s, h->colour_cells, h->wall_cells, h->wall_index};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -636,7 +643,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (gas->sweep < UGKS_SWEEP_AUTO || gas->sweep > UGKS_SWEEP_PUSH)
             throw Fail{UGKS_ERR_ARG, "sweep must be UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER or UGKS_SWEEP_PUSH"};
         if (gas->sweep == UGKS_SWEEP_PUSH && !push_applies(gas))
-            throw Fail{UGKS_ERR_ARG, "the push sweep needs two f buffers and FP64 or FP32 f"};
+            throw Fail{UGKS_ERR_ARG, "the push sweep needs FP64 or FP32 f"};
         h->push = uses_push(D, gas) ? 1 : 0;
         for (int k = 0; k < vgrid->n_vel; ++k) {
             bool ok = vgrid->w[k] > 0.0 && std::isfinite(vgrid->w[k]);
@@ -708,6 +715,8 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
                 for (size_t t = 0; t < list.size(); ++t) widx[list[t]] = (int)t;
                 h->wall_index = dev_alloc<int>(h, widx.size());
                 upload(h->wall_index, widx.data(), sizeof(int) * widx.size(), h->stream);
+            }
+            if (h->push && gas->mem_mode == UGKS_MEM_TWO_BUFFERS) {
                 h->mom_part = dev_alloc<double>(h, nc * (size_t)(D + 2));
                 h->rho_w = dev_alloc<double>(h, nc * (size_t)(D == 2 ? Dim<2>::MF : Dim<3>::MF));
                 hip_check(hipMemsetAsync(h->rho_w, 0, sizeof(double) * nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF),
@@ -737,6 +746,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
             h->rho_w = dev_alloc<double>(h, nc * (size_t)(D == 2 ? Dim<2>::MF : Dim<3>::MF));
             hip_check(hipMemsetAsync(h->rho_w, 0, sizeof(double) * nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF),
                                      h->stream), "hipMemsetAsync");
+            if (h->push) h->mom_s = dev_alloc<double>(h, nc * (size_t)shift_moments(D));
         }
         upload(h->u, uT.data(), sizeof(double) * uT.size(), h->stream);
         upload(h->w, wP.data(), sizeof(double) * nv, h->stream);
@@ -780,6 +790,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         P.rho_w = h->rho_w;
         P.wall_index = h->wall_index;
         P.wflux = h->wallF;
+        P.mom_s = h->mom_s;
 
         // time step (Alg. 1 line 1), fixed for the run
         hip_check(launch_cfl(P, h->cell_dt, h->stream), "k_cfl launch");
@@ -823,7 +834,12 @@ namespace {
 // or in place
 void sweep(ugks_t *h)
 {
-    if (h->mem_mode == UGKS_MEM_IN_PLACE) {
+    if (h->mem_mode == UGKS_MEM_IN_PLACE && h->push) {
+        hip_check(launch_push_inplace(h->P, h->f[0], h->colour_cells, h->colour_off.data(),
+                                      (int)h->colour_off.size() - 1, h->wall_cells, h->n_wall_cells, h->stream),
+                  "in-place push sweep launch");
+        h->last_push = 1;
+    } else if (h->mem_mode == UGKS_MEM_IN_PLACE) {
         hip_check(launch_sweep_inplace(h->P, h->f[0], h->n_wallf > 0, h->stream), "in-place sweep launch");
     } else if (h->push) {
         hip_check(launch_push_step(h->P, h->f[h->cur], h->f[1 - h->cur], !h->base_ok, h->colour_cells,
@@ -1152,8 +1168,8 @@ extern "C" int ugks_wall_flux(ugks_t *h, double *out)
     if (!h || !out) return UGKS_ERR_ARG;
     if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
     if (!h->stepped) return fail(h, Fail{UGKS_ERR_STATE, "no step since creation or ugks_set_f"});
-    if (h->mem_mode == UGKS_MEM_IN_PLACE)
-        return fail(h, Fail{UGKS_ERR_STATE, "an in-place handle keeps no copy of the f that started the step"});
+    if (h->mem_mode == UGKS_MEM_IN_PLACE && !h->last_push)
+        return fail(h, Fail{UGKS_ERR_STATE, "an in-place gather handle keeps no copy of the f that started the step"});
     try {
         if (h->n_wallf) {
             if (!h->last_push)  // a push step recorded its wall flux; else recompute it from the f that started it
@@ -1178,8 +1194,8 @@ extern "C" int ugks_surface(ugks_t *h, double rho_inf, double u_inf, double *out
         return fail(h, Fail{UGKS_ERR_ARG, "rho_inf and u_inf must be positive and finite"});
     if (h->pending) return fail(h, Fail{UGKS_ERR_STATE, "asynchronous steps not yet polled to completion"});
     if (!h->stepped) return fail(h, Fail{UGKS_ERR_STATE, "no step since creation or ugks_set_f"});
-    if (h->mem_mode == UGKS_MEM_IN_PLACE)
-        return fail(h, Fail{UGKS_ERR_STATE, "an in-place handle keeps no copy of the f that started the step"});
+    if (h->mem_mode == UGKS_MEM_IN_PLACE && !h->last_push)
+        return fail(h, Fail{UGKS_ERR_STATE, "an in-place gather handle keeps no copy of the f that started the step"});
     try {
         if (h->n_wallf) {
             if (!h->last_push)

@@ -99,6 +99,9 @@ struct Params {
     // last step per wall face [n_wall][dim+2] (per unit area and time)
     const int *wall_index;
     double *wflux;
+    // push sweep with one f buffer: the stage-1 moments about U^n summed over
+    // the chunks so far [cell][Shift<D>::N]
+    double *mom_s;
 };
 
 // One case of a batched launch (several cases advanced by the same kernels):
@@ -145,6 +148,11 @@ hipError_t launch_sweep(const Params &p, const void *f_in, void *f_out, hipStrea
 // cells), then stage 2 into f and the next base into acc
 hipError_t launch_push_step(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff,
                             int ncol, const int *wall_cells, int n_wall_cells, hipStream_t s);
+// the push sweep with one f buffer (FP64 or FP32 f): the wall cells, then per
+// velocity chunk the base into the ring, one launch per colour, the stage-1
+// values back into f; then W^{n+1}, q^{n+1} and stage 2 in place
+hipError_t launch_push_inplace(const Params &p, void *f, const int *cells, const int *coff, int ncol,
+                               const int *wall_cells, int n_wall_cells, hipStream_t s);
 // the in-place step's sweep: wall densities (if walls), one kernel per
 // velocity chunk, the final kernel; f is read and updated in place
 hipError_t launch_sweep_inplace(const Params &p, void *f, bool walls, hipStream_t s);

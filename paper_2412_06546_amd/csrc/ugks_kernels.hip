@@ -1710,7 +1710,8 @@ __device__ __forceinline__ void push_wall(const Params &p, const CellGeo<D> &gi,
 // the XCDs in runs as for the gather sweep.  PF: the own stencil of the
 // next velocity is loaded one iteration ahead.
 template <int D, typename FT, int BS, bool TENSOR, bool PF>
-__device__ __forceinline__ void push_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ acc)
+__device__ __forceinline__ void push_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ acc,
+                                          int k0, int kn, int accv)
 {
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NT = MF + 1;
     extern __shared__ double smem[];
@@ -1725,10 +1726,13 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
     // wall densities of this cell's wall faces, from the step's wall kernel
     const double *rho_w = p.rho_w + (size_t)i * MF;
 
-    const size_t base = (size_t)i * NC * nv;
+    // velocities [k0, k0 + kn); the accumulator holds accv velocities per
+    // cell and component, starting at k0 (the whole set, or one chunk)
+    const int kend = k0 + kn;
+    const size_t base = (size_t)i * NC * accv;
     double pv0[NC], pvn[MF][NC];
-    if (PF && tid < nv) load_stencil<D, FT>(gi, i, fin, nv, tid, pv0, pvn);
-    for (int k = tid; k < nv; k += BS) {
+    if (PF && k0 + tid < kend) load_stencil<D, FT>(gi, i, fin, nv, k0 + tid, pv0, pvn);
+    for (int k = k0 + tid; k < kend; k += BS) {
         double v0[NC], vn[MF][NC];
         if constexpr (PF) {
 #pragma unroll
@@ -1737,7 +1741,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
 #pragma unroll
                 for (int j = 0; j < MF; ++j) vn[j][m] = pvn[j][m];
             }
-            if (k + BS < nv) load_stencil<D, FT>(gi, i, fin, nv, k + BS, pv0, pvn);
+            if (k + BS < kend) load_stencil<D, FT>(gi, i, fin, nv, k + BS, pv0, pvn);
         } else {
             load_stencil<D, FT>(gi, i, fin, nv, k, v0, vn);
         }
@@ -1768,10 +1772,10 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
             if (F.bc == 0) {
                 if (!(uo > 0.0)) continue;  // the neighbour is upwind: it adds this flux
                 // the neighbour's accumulator first, so its load overlaps the arithmetic
-                FT *an = acc + (size_t)gi.nb[j] * NC * nv;
+                FT *an = acc + (size_t)gi.nb[j] * NC * accv;
                 double av[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) av[c] = to_f64(an[(size_t)c * nv + k]);
+                for (int c = 0; c < NC; ++c) av[c] = to_f64(an[(size_t)c * accv + (k - k0)]);
                 double val[NC], ug[NC], I[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -1791,7 +1795,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
                 for (int c = 0; c < NC; ++c) {
                     const double fl = sa * I[c];
                     out[c] += fl;
-                    an[(size_t)c * nv + k] = from_f64<FT>(fma(fl, vn_inv, av[c]));
+                    an[(size_t)c * accv + (k - k0)] = from_f64<FT>(fma(fl, vn_inv, av[c]));
                 }
             } else {
                 double I[NC];
@@ -1820,7 +1824,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            FT *a = acc + base + (size_t)c * nv + k;
+            FT *a = acc + base + (size_t)c * accv + (k - k0);
             *a = from_f64<FT>(fma(-out[c], gi.inv_vol, to_f64(*a)));
         }
     }
@@ -1851,20 +1855,20 @@ __global__ __launch_bounds__(BS) void k_push_wall(Params p, const FT *__restrict
 
 template <int D, typename FT, int BS, bool TENSOR>
 __global__ __launch_bounds__(BS) void k_push(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
-                                             const int *__restrict__ cells, int ncell)
+                                             const int *__restrict__ cells, int ncell, int k0, int kn, int accv)
 {
     const int b = xcd_cell(blockIdx.x);
     if (b >= ncell) return;
-    push_cell<D, FT, BS, TENSOR, false>(p, cells[b], fin, acc);
+    push_cell<D, FT, BS, TENSOR, false>(p, cells[b], fin, acc, k0, kn, accv);
 }
 
 template <int D, typename FT, int BS>
-__global__ __launch_bounds__(BS) void k_push_pf(
-    Params p, const FT *__restrict__ fin, FT *__restrict__ acc, const int *__restrict__ cells, int ncell)
+__global__ __launch_bounds__(BS) void k_push_pf(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
+                                                const int *__restrict__ cells, int ncell, int k0, int kn, int accv)
 {
     const int b = xcd_cell(blockIdx.x);
     if (b >= ncell) return;
-    push_cell<D, FT, BS, true, true>(p, cells[b], fin, acc);
+    push_cell<D, FT, BS, true, true>(p, cells[b], fin, acc, k0, kn, accv);
 }
 
 // After the last colour: W^{n+1}, tau^{n+1}, q^{n+1}, stage 2 into f and the
@@ -2639,6 +2643,244 @@ __global__ __launch_bounds__(256) void k_push_final_r(Params p, FT *__restrict__
 }
 
 // ------------------------------------------------------------------------
+// Push sweep with one f buffer (the in-place mode).  The velocities are taken
+// in chunks; per chunk, the base of the chunk's velocities goes into a ring of
+// one chunk per cell (its moments added to the cell's running sum), the
+// colour launches push the chunk's face fluxes into the ring, and a chunk-end
+// kernel writes the stage-1 values back into f -- no later launch reads f^n at
+// those velocities -- adding their moments about U^n (orders 0-3 of h, 0-1 of
+// b) to a second running sum.  After the last chunk a final kernel forms
+// W^{n+1}, tau^{n+1}, q^{n+1} from the two sums and applies stage 2 in place.
+// The wall kernel runs first, while f still holds f^n at every velocity.
+// ------------------------------------------------------------------------
+template <int D> struct Shift {
+    static constexpr int NC = Dim<D>::NC, NM = D * (D + 1) / 2;
+    static constexpr int N = 1 + D + NM + D + (NC > 1 ? 1 + D : 0);
+};
+
+// one velocity's contribution to the moments about U^n (c = u - U^n)
+template <int D>
+__device__ __forceinline__ void add_shift_moments(double (&mm)[Shift<D>::N], double w, const double (&c)[D], double c2,
+                                                  double h, double b)
+{
+    constexpr int NM = Shift<D>::NM;
+    const double wh = w * h;
+    mm[0] += wh;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double whc = wh * c[a];
+        mm[1 + a] += whc;
+        mm[1 + D + NM + a] = fma(whc, c2, mm[1 + D + NM + a]);
+#pragma unroll
+        for (int bb = a; bb < D; ++bb) mm[1 + D + sym_index<D>(a, bb)] = fma(whc, c[bb], mm[1 + D + sym_index<D>(a, bb)]);
+    }
+    if constexpr (Dim<D>::NC > 1) {
+        const double wb = w * b;
+        mm[1 + 2 * D + NM] += wb;
+#pragma unroll
+        for (int a = 0; a < D; ++a) mm[2 + 2 * D + NM + a] = fma(wb, c[a], mm[2 + 2 * D + NM + a]);
+    }
+}
+
+// W^{n+1} (W^n + the stage-1 moments - the base's moments), its primitive
+// state, tau^{n+1} and q^{n+1} (the re-centred heat flux of the stage-1
+// values) from the moments about U^n
+template <int D>
+__device__ __forceinline__ void macro_from_shift(const Params &p, const double (&mm)[Shift<D>::N],
+                                                 const double (&Wn)[D + 2], const Prim<D> &pn, const double *mom_base,
+                                                 double (&W1)[D + 2], Prim<D> &p1, double &tau1, double (&q1)[D])
+{
+    constexpr int NW = D + 2, NM = Shift<D>::NM, NC = Dim<D>::NC;
+    const double m0 = mm[0];
+    const double b0 = NC > 1 ? mm[1 + 2 * D + NM] : 0.0;
+    double m1[D], m3[D], b1[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        m1[a] = mm[1 + a];
+        m3[a] = mm[1 + D + NM + a];
+        b1[a] = NC > 1 ? mm[2 + 2 * D + NM + a] : 0.0;
+    }
+    double mom[NW], trm2 = 0.0, um1 = 0.0, uu = 0.0;
+    mom[0] = m0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        mom[1 + a] = fma(pn.U[a], m0, m1[a]);
+        trm2 += mm[1 + D + sym_index<D>(a, a)];
+        um1 = fma(pn.U[a], m1[a], um1);
+        uu = fma(pn.U[a], pn.U[a], uu);
+    }
+    mom[D + 1] = 0.5 * (trm2 + 2.0 * um1 + uu * m0 + b0);
+#pragma unroll
+    for (int m = 0; m < NW; ++m) W1[m] = Wn[m] + (mom[m] - mom_base[m]);
+    p1 = to_prim<D>(W1);
+    tau1 = collision_time(p1.rho, p1.lam, p.mu_ref, p.omega);
+    double dl[D], d2 = 0.0, m1d = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dl[a] = p1.U[a] - pn.U[a];
+        d2 = fma(dl[a], dl[a], d2);
+        m1d = fma(m1[a], dl[a], m1d);
+    }
+    const double qden = 1.0 + p.Pr * p.dt / (2.0 * tau1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double m2d = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) m2d = fma(mm[1 + D + sym_index<D>(a, bb)], dl[bb], m2d);
+        const double qa = m3[a] - 2.0 * m2d + d2 * m1[a] - dl[a] * trm2 + 2.0 * dl[a] * m1d - dl[a] * d2 * m0 + b1[a] -
+                          dl[a] * b0;
+        q1[a] = 0.5 * qa / qden;
+    }
+}
+
+// base of velocities [c0, c0 + cn) into the ring; its moments added to
+// mom_part (chunk 0 starts the sum)
+template <int D, typename FT, bool TENSOR>
+__global__ __launch_bounds__(256) void k_push_base_chunk(Params p, const FT *__restrict__ f, FT *__restrict__ ring,
+                                                         int c0, int cn, int ichunk)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int nv = p.nv, ch = p.chunk, tid = threadIdx.x;
+    const CellStep<D> cs = cell_step<D>(p, i);
+    double *tb = smem;
+    double *red = smem + (TENSOR ? p.ntab : 0);
+    if constexpr (TENSOR) fill_group_table<D, BS>(p, cs.pn.lam, cs.pn.U[0], cs.pn.U[1], cs.pn.U[D - 1], tb);
+    const size_t fb = (size_t)i * NC * nv, rb = (size_t)i * NC * ch;
+    double mom[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+#pragma unroll 2
+    for (int kk = tid; kk < cn; kk += BS) {
+        const int k = c0 + kk;
+        double u[D], u2;
+        velocity<D>(p, k, u, u2);
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fp[2];
+        const double H = cs.pref_n * own_gauss<D, TENSOR>(p, tb, kx, u, cs.pn.lam, cs.pn.U);
+        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
+        double bv[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double fv = to_f64(f[fb + (size_t)c * nv + k]);
+            const FT sv = from_f64<FT>(fma(cs.hdt_tau, fp[c] - fv, fv));
+            ring[rb + (size_t)c * ch + kk] = sv;
+            bv[c] = to_f64(sv);
+        }
+        add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+    }
+    block_reduce_wide<BS>(mom, red, OpAdd{});
+    if (tid == 0)
+#pragma unroll
+        for (int m = 0; m < NW; ++m)
+            p.mom_part[(size_t)i * NW + m] = (ichunk == 0 ? 0.0 : p.mom_part[(size_t)i * NW + m]) + mom[m];
+}
+
+// the chunk's stage-1 values from the ring back into f, their moments about
+// U^n added to mom_s (chunk 0 starts the sum)
+template <int D, typename FT>
+__global__ __launch_bounds__(256) void k_push_chunk_end(Params p, FT *__restrict__ f, const FT *__restrict__ ring,
+                                                        int c0, int cn, int ichunk)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256, N = Shift<D>::N;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int nv = p.nv, ch = p.chunk, tid = threadIdx.x;
+    double Wn[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
+    const Prim<D> pn = to_prim<D>(Wn);
+    const size_t fb = (size_t)i * NC * nv, rb = (size_t)i * NC * ch;
+    double mm[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) mm[t] = 0.0;
+#pragma unroll 4
+    for (int kk = tid; kk < cn; kk += BS) {
+        const int k = c0 + kk;
+        double v[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const FT x = ring[rb + (size_t)c * ch + kk];
+            f[fb + (size_t)c * nv + k] = x;
+            v[c] = to_f64(x);
+        }
+        double c[D], c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            c[d] = p.u[d * nv + k] - pn.U[d];
+            c2 = fma(c[d], c[d], c2);
+        }
+        add_shift_moments<D>(mm, p.w[k], c, c2, v[0], NC > 1 ? v[NC - 1] : 0.0);
+    }
+    block_reduce_wide<BS>(mm, smem, OpAdd{});
+    if (tid == 0)
+#pragma unroll
+        for (int t = 0; t < N; ++t) p.mom_s[(size_t)i * N + t] = (ichunk == 0 ? 0.0 : p.mom_s[(size_t)i * N + t]) + mm[t];
+}
+
+// after the last chunk: W^{n+1}, tau^{n+1}, q^{n+1}, stage 2 in place
+template <int D, typename FT, bool TENSOR>
+__global__ __launch_bounds__(256) void k_push_final_inplace(Params p, FT *__restrict__ f)
+{
+    constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256, N = Shift<D>::N;
+    extern __shared__ double smem[];
+    const int i = xcd_cell(blockIdx.x);
+    if (i >= p.nc) return;
+    const int nv = p.nv, tid = threadIdx.x;
+    const double dt = p.dt, Pr = p.Pr;
+    double Wn[NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
+    const Prim<D> pn = to_prim<D>(Wn);
+    double mm[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) mm[t] = p.mom_s[(size_t)i * N + t];
+    double W1[NW], tau1, q1[D];
+    Prim<D> p1;
+    macro_from_shift<D>(p, mm, Wn, pn, p.mom_part + (size_t)i * NW, W1, p1, tau1, q1);
+    double *tb = smem;
+    if constexpr (TENSOR) fill_group_table<D, BS>(p, p1.lam, p1.U[0], p1.U[1], p1.U[D - 1], tb);
+    const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
+    const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
+    const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
+    const double bh_1 = Dim<D>::M / (2.0 * p1.lam);
+    const size_t fb = (size_t)i * NC * nv;
+#pragma unroll 2
+    for (int k = tid; k < nv; k += BS) {
+        double u[D], u2;
+        velocity<D>(p, k, u, u2);
+        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+        double fp[2];
+        const double H = pref_1 * own_gauss<D, TENSOR>(p, tb, kx, u, p1.lam, p1.U);
+        shakhov<D>(u, p1.U, p1.lam, shk_1, q1, bh_1, H, fp[0], fp[1]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            FT *q = f + fb + (size_t)c * nv + k;
+            *q = from_f64<FT>((to_f64(*q) + a1 * fp[c]) * inv1);
+        }
+    }
+    if (tid == 0) {
+        bool ok = p1.rho > 0.0 && p1.lam > 0.0 && isfinite(p1.rho) && isfinite(p1.lam);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            ok = ok && isfinite(W1[m]);
+            p.W[(size_t)i * NW + m] = W1[m];
+            const double dw = W1[m] - Wn[m];
+            p.dW2[(size_t)i * NW + m] = dw * dw;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.q[(size_t)i * D + d] = q1[d];
+        if (!ok) {
+            atomicOr(p.err, 1);
+            atomicMin(p.err + 1, i);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // push sweep launches: the stage-1 base (when stale), one launch per colour,
 // the final kernel
 // ------------------------------------------------------------------------
@@ -2687,10 +2929,11 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
         if (n <= 0) continue;
         const unsigned g = (unsigned)sweep_grid(n);
         if constexpr (TENSOR)
-            hipLaunchKernelGGL((k_push_pf<D, FT, BS>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c], n);
+            hipLaunchKernelGGL((k_push_pf<D, FT, BS>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c], n,
+                               0, p.nv, p.nv);
         else
             hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c],
-                               n);
+                               n, 0, p.nv, p.nv);
     }
     if (reg_form) {
         if constexpr (sizeof(FT) == 8) {
@@ -2714,6 +2957,58 @@ hipError_t push_d(const Params &p, void *f, void *acc, bool need_base, const int
 {
     return p.ntab > 0 ? push_t<D, FT, true>(p, f, acc, need_base, cells, coff, ncol, wc, nwc, s)
                       : push_t<D, FT, false>(p, f, acc, need_base, cells, coff, ncol, wc, nwc, s);
+}
+
+template <int D, typename FT, bool TENSOR>
+hipError_t push_inplace_t(const Params &p, void *fv, const int *cells, const int *coff, int ncol,
+                          const int *wall_cells, int n_wall_cells, hipStream_t s)
+{
+    constexpr int MF = Dim<D>::MF, NW = D + 2, BS = 256;
+    FT *f = static_cast<FT *>(fv), *ring = static_cast<FT *>(p.ring);
+    const size_t tab = sizeof(double) * (size_t)(MF + 1) * (TENSOR ? p.ntab : 0);
+    const size_t red = sizeof(double) * ((BS / 64) * (2 * NW + 2) + MF);
+    const unsigned gc = (unsigned)sweep_grid(p.nc);
+    const size_t lcell = sizeof(double) * ((TENSOR ? (size_t)p.ntab : 0) + 5 * 16);
+    if (n_wall_cells > 0)
+        hipLaunchKernelGGL((k_push_wall<D, FT, BS, TENSOR>), dim3(n_wall_cells), dim3(BS), tab + red, s, p, f,
+                           wall_cells, n_wall_cells);
+    for (int q = 0; q < p.nchunk; ++q) {
+        const int c0 = q * p.chunk, cn = std::min(p.chunk, p.nv - c0);
+        hipLaunchKernelGGL((k_push_base_chunk<D, FT, TENSOR>), dim3(gc), dim3(BS), lcell, s, p, f, ring, c0, cn, q);
+        for (int c = 0; c < ncol; ++c) {
+            const int n = coff[c + 1] - coff[c];
+            if (n <= 0) continue;
+            const unsigned g = (unsigned)sweep_grid(n);
+            if constexpr (TENSOR)
+                hipLaunchKernelGGL((k_push_pf<D, FT, BS>), dim3(g), dim3(BS), tab + red, s, p, f, ring, cells + coff[c],
+                                   n, c0, cn, p.chunk);
+            else
+                hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, f, ring,
+                                   cells + coff[c], n, c0, cn, p.chunk);
+        }
+        hipLaunchKernelGGL((k_push_chunk_end<D, FT>), dim3(gc), dim3(BS), lcell, s, p, f, ring, c0, cn, q);
+    }
+    hipLaunchKernelGGL((k_push_final_inplace<D, FT, TENSOR>), dim3(gc), dim3(BS), lcell, s, p, f);
+    return hipGetLastError();
+}
+
+template <int D, typename FT>
+hipError_t push_inplace_d(const Params &p, void *f, const int *cells, const int *coff, int ncol, const int *wc,
+                          int nwc, hipStream_t s)
+{
+    return p.ntab > 0 ? push_inplace_t<D, FT, true>(p, f, cells, coff, ncol, wc, nwc, s)
+                      : push_inplace_t<D, FT, false>(p, f, cells, coff, ncol, wc, nwc, s);
+}
+
+hipError_t launch_push_inplace(const Params &p, void *f, const int *cells, const int *coff, int ncol,
+                               const int *wall_cells, int n_wall_cells, hipStream_t s)
+{
+    if (p.fstore == 2) return hipErrorInvalidValue;  // bfloat16 f takes the gather sweep
+    if (p.dim == 2)
+        return p.fstore ? push_inplace_d<2, float>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                        : push_inplace_d<2, double>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s);
+    return p.fstore ? push_inplace_d<3, float>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                    : push_inplace_d<3, double>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s);
 }
 
 hipError_t launch_push_step(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff,

@@ -21,7 +21,7 @@ UGKS_BC_INTERIOR, UGKS_BC_INFLOW, UGKS_BC_OUTFLOW, UGKS_BC_WALL = 0, 1, 2, 3
 _FSTORE = {"f64": UGKS_F64, "f32": UGKS_F32, "bf16": UGKS_BF16}
 UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE = 0, 1
 _MEM = {"two-buffers": UGKS_MEM_TWO_BUFFERS, "in-place": UGKS_MEM_IN_PLACE}
-UGKS_DEFAULT_CHUNK = 512
+UGKS_DEFAULT_CHUNK = 1024
 UGKS_STATIC_BATCH_MAX = 64
 UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH = 0, 1, 2
 _SWEEP = {"auto": UGKS_SWEEP_AUTO, "gather": UGKS_SWEEP_GATHER, "push": UGKS_SWEEP_PUSH}

@@ -717,15 +717,17 @@ def test_2d_unstructured_velocity_set_fp64():
     _compare(s, o)
 
 
+@pytest.mark.parametrize("sweep", ["push", "gather"])
 @pytest.mark.parametrize("name,chunk", [("periodic wave", 0), ("periodic wave", 100), ("periodic wave", 5000),
                                         ("periodic wave", 1), ("cylinder cut-down", 0), ("cylinder cut-down", 96),
                                         ("3D channel", 64), ("3D channel", 1), ("scattered velocities", 10)])
-def test_in_place_mode_matches_the_oracle(name, chunk):
+def test_in_place_mode_matches_the_oracle(name, chunk, sweep):
     """UGKS_MEM_IN_PLACE: one f buffer updated in place, velocities swept in
     chunks (two ragged chunks, several, one, one velocity per chunk), walls
-    and far field, Cartesian and scattered velocity sets: parity with the
-    oracle, and a footprint that is the estimate's and, with a ring smaller
-    than f, below the two-buffer one."""
+    and far field, Cartesian and scattered velocity sets, by the push sweep
+    (colour launches per chunk into a ring) and by the gather sweep: parity
+    with the oracle, and a footprint that is the estimate's and, with a ring
+    smaller than f, below the two-buffer one."""
     ugks = _gpu()
     if name == "periodic wave":
         c = cases.case_periodic_wave()
@@ -738,11 +740,12 @@ def test_in_place_mode_matches_the_oracle(name, chunk):
         rng = np.random.default_rng(9)
         u, w = c["vgrid"]["u"], c["vgrid"]["w"]
         c["vgrid"] = dict(dim=2, u=np.ascontiguousarray(u + rng.uniform(-1e-3, 1e-3, u.shape)), w=w)
-    _say(f"case {c['name']}: in place, chunk {chunk}, 10 steps")
-    s = ugks.Solver(c, mem="in-place", chunk=chunk)
+    _say(f"case {c['name']}: in place, {sweep} sweep, chunk {chunk}, 10 steps")
+    s = ugks.Solver(c, mem="in-place", chunk=chunk, sweep=sweep)
+    assert s.sweep == sweep
     two = ugks.Solver(c)
-    assert s.footprint_bytes == ugks.footprint_estimate(c, mem="in-place", chunk=chunk)
-    if min(chunk or 512, s.nv) < s.nv:     # a ring smaller than f
+    assert s.footprint_bytes == ugks.footprint_estimate(c, mem="in-place", chunk=chunk, sweep=sweep)
+    if min(chunk or ugks.UGKS_DEFAULT_CHUNK, s.nv) < s.nv:     # a ring smaller than f
         assert s.footprint_bytes < two.footprint_bytes
     o = oracle.Oracle(c)
     s.step(10)
@@ -753,20 +756,34 @@ def test_in_place_mode_matches_the_oracle(name, chunk):
 
 def test_in_place_mode_storage_precision_and_restrictions():
     """In place with FP32 f agrees with the two-buffer FP32 run to FP32
-    rounding; the wall flux and batching are refused for in-place handles."""
+    rounding (push and gather); the push sweep in place records the wall
+    flux as the two-buffer push sweep does, the gather sweep in place
+    refuses it; batching is refused for in-place handles."""
     import ctypes
     import torch
     ugks = _gpu()
     c = cases.case_cylinder_small()
-    a = ugks.Solver(c, fstore="f32", mem="in-place", chunk=128)
     b = ugks.Solver(c, fstore="f32")
-    a.step(8)
     b.step(8)
-    eW, eq = macro_rel_err(*a.macros(), *b.macros())
-    assert eW < 1e-6 and eq < 1e-5, (eW, eq)
-    with pytest.raises(ugks.UgksError) as e:
-        a.wall_flux()
-    assert e.value.code == ugks.UGKS_ERR_STATE
+    for sweep in ("push", "gather"):
+        a = ugks.Solver(c, fstore="f32", mem="in-place", chunk=128, sweep=sweep)
+        a.step(8)
+        eW, eq = macro_rel_err(*a.macros(), *b.macros())
+        assert eW < 1e-6 and eq < 1e-5, (sweep, eW, eq)
+        if sweep == "push":
+            Fa, Fb = a.wall_flux(), b.wall_flux()
+            assert np.abs(Fa - Fb).max() <= 1e-5 * np.abs(Fb).max()
+        else:
+            with pytest.raises(ugks.UgksError) as e:
+                a.wall_flux()
+            assert e.value.code == ugks.UGKS_ERR_STATE
+        a.close()
+    # FP64: the push sweep's wall flux in place against the oracle's
+    a, o = ugks.Solver(c, mem="in-place", chunk=100), oracle.Oracle(c)
+    a.step(3)
+    o.step(3)
+    Fo = o.wall_flux()
+    assert np.abs(a.wall_flux() - Fo).max() <= 1e-12 * np.abs(Fo).max()
     stream = torch.cuda.Stream()
     sh = ctypes.c_void_p(stream.cuda_stream)
     batch = ugks.Batch(2, sh)
@@ -777,13 +794,15 @@ def test_in_place_mode_storage_precision_and_restrictions():
 
 
 def test_in_place_mode_async_steps_and_checkpoint():
-    """In place: asynchronous steps equal synchronous ones bit for bit; a
-    checkpoint taken after 4 steps and restored in a fresh in-place handle
-    continues exactly, and in a two-buffer handle (the state does not depend
-    on the memory mode) to the rounding of the velocity sums."""
+    """In place (push sweep): asynchronous steps equal synchronous ones bit
+    for bit; a checkpoint taken after 4 steps and restored in a fresh
+    in-place handle continues exactly, and in a two-buffer handle (the state
+    does not depend on the memory mode) to the rounding of the velocity
+    sums."""
     ugks = _gpu()
     c = cases.case_cylinder_small()
     a = ugks.Solver(c, mem="in-place", chunk=200)
+    assert a.sweep == "push"
     b = ugks.Solver(c, mem="in-place", chunk=200)
     a.step(4)
     b.step_async(4)

@@ -146,14 +146,16 @@ def test_in_place_footprint_is_one_f_plus_the_ring(dim):
     nc, nv = len(c["mesh"]["cell_volume"]), len(c["vgrid"]["w"])
     ncomp = 2 if dim == 2 else 1
     two = ugks.footprint_estimate(c, "f64", "two-buffers", sweep="gather")
-    one = {ch: ugks.footprint_estimate(c, "f64", "in-place", ch) for ch in (1, 2, nv, 10 * nv)}
     f_bytes = nc * ncomp * nv * 8
-    assert one[1] < one[2] < one[nv] == one[10 * nv]
-    assert one[1] < two
-    # beyond one f and the ring: the moment sum and the wall densities,
-    # a few doubles per cell (plus allocation rounding)
-    extra = one[1] - (two - f_bytes) - nc * ncomp * 8
-    assert 0 < extra <= nc * 16 * 8 + 4096
-    # the ring is the only part that grows with the chunk
-    ring_growth = nc * ncomp * (nv - 1) * 8
-    assert ring_growth <= one[nv] - one[1] <= ring_growth + 4096
+    # beyond one f and the ring: gather -- the moment sum and the wall
+    # densities; push -- also the colour lists, the face -> wall ordinal and
+    # the running moments about U^n: a few tens of doubles per cell at most
+    for sweep, per_cell in (("gather", 16), ("push", 28)):
+        one = {ch: ugks.footprint_estimate(c, "f64", "in-place", ch, sweep=sweep) for ch in (1, 2, nv, 10 * nv)}
+        assert one[1] < one[2] < one[nv] == one[10 * nv]
+        assert one[1] < two
+        extra = one[1] - (two - f_bytes) - nc * ncomp * 8
+        assert 0 < extra <= nc * per_cell * 8 + 4096, (sweep, extra / nc)
+        # the ring is the only part that grows with the chunk
+        ring_growth = nc * ncomp * (nv - 1) * 8
+        assert ring_growth <= one[nv] - one[1] <= ring_growth + 4096
