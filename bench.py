@@ -214,7 +214,7 @@ def sweep_kernels(run, mem):
         return "k_sweep_chunk (every chunk) + k_sweep_finish"
     if run.get("sweep") == "push":
         return (f"push sweep: k_push_wall, {run['n_colours']} colour launches of k_push_pf (k_push), "
-                f"k_push_final, timed together")
+                f"k_push_final_r (k_push_final), timed together")
     return "k_sweep_pf (k_sweep)"
 
 

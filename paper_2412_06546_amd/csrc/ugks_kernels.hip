@@ -1855,20 +1855,41 @@ __global__ __launch_bounds__(BS) void k_push_wall(Params p, const FT *__restrict
 
 template <int D, typename FT, int BS, bool TENSOR>
 __global__ __launch_bounds__(BS) void k_push(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
-                                             const int *__restrict__ cells, int ncell, int k0, int kn, int accv)
+                                             const int *__restrict__ cells, int ncell, int k0, int kn, int accv,
+                                             int ksplit)
 {
     const int b = xcd_cell(blockIdx.x);
     if (b >= ncell) return;
-    push_cell<D, FT, BS, TENSOR, false>(p, cells[b], fin, acc, k0, kn, accv);
+    // this workgroup's share of [k0, k0 + kn): ksplit velocities from
+    // k0 + blockIdx.y ksplit (the accumulator's velocity k0 is its column 0)
+    const int ka = k0 + (int)blockIdx.y * ksplit, kb = min(k0 + kn, ka + ksplit);
+    if (ka >= kb) return;
+    push_cell<D, FT, BS, TENSOR, false>(p, cells[b], fin, acc + (ka - k0), ka, kb - ka, accv);
 }
 
 template <int D, typename FT, int BS>
 __global__ __launch_bounds__(BS) void k_push_pf(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
-                                                const int *__restrict__ cells, int ncell, int k0, int kn, int accv)
+                                                const int *__restrict__ cells, int ncell, int k0, int kn, int accv,
+                                                int ksplit)
 {
     const int b = xcd_cell(blockIdx.x);
     if (b >= ncell) return;
-    push_cell<D, FT, BS, true, true>(p, cells[b], fin, acc, k0, kn, accv);
+    const int ka = k0 + (int)blockIdx.y * ksplit, kb = min(k0 + kn, ka + ksplit);
+    if (ka >= kb) return;
+    push_cell<D, FT, BS, true, true>(p, cells[b], fin, acc + (ka - k0), ka, kb - ka, accv);
+}
+
+// Velocity splits of a colour launch: a class of n cells gets up to enough
+// workgroups to fill the chip (kPushFill), each with a share of the kn
+// velocities that is a multiple of the workgroup size and at least
+// kPushMinIters iterations long (every workgroup repeats the cell's set-up).
+constexpr int kPushFill = 8192, kPushMinIters = 4;
+inline int push_ksplit(int n, int kn, int bs)
+{
+    const int iters = (kn + bs - 1) / bs;  // velocity iterations of one workgroup
+    const int split = std::max(1, std::min(iters / kPushMinIters, (kPushFill + n - 1) / n));
+    const int per = (iters + split - 1) / split;
+    return per * bs;
 }
 
 // After the last colour: W^{n+1}, tau^{n+1}, q^{n+1}, stage 2 into f and the
@@ -2928,12 +2949,14 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
         const int n = coff[c + 1] - coff[c];
         if (n <= 0) continue;
         const unsigned g = (unsigned)sweep_grid(n);
+        const int ks = push_ksplit(n, p.nv, BS);
+        const dim3 grid(g, (unsigned)((p.nv + ks - 1) / ks));
         if constexpr (TENSOR)
-            hipLaunchKernelGGL((k_push_pf<D, FT, BS>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c], n,
-                               0, p.nv, p.nv);
+            hipLaunchKernelGGL((k_push_pf<D, FT, BS>), grid, dim3(BS), tab + red, s, p, fin, acc, cells + coff[c], n, 0,
+                               p.nv, p.nv, ks);
         else
-            hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, fin, acc, cells + coff[c],
-                               n, 0, p.nv, p.nv);
+            hipLaunchKernelGGL((k_push<D, FT, BS, false>), grid, dim3(BS), tab + red, s, p, fin, acc, cells + coff[c],
+                               n, 0, p.nv, p.nv, ks);
     }
     if (reg_form) {
         if constexpr (sizeof(FT) == 8) {
@@ -2979,12 +3002,14 @@ hipError_t push_inplace_t(const Params &p, void *fv, const int *cells, const int
             const int n = coff[c + 1] - coff[c];
             if (n <= 0) continue;
             const unsigned g = (unsigned)sweep_grid(n);
+            const int ks = push_ksplit(n, cn, BS);
+            const dim3 grid(g, (unsigned)((cn + ks - 1) / ks));
             if constexpr (TENSOR)
-                hipLaunchKernelGGL((k_push_pf<D, FT, BS>), dim3(g), dim3(BS), tab + red, s, p, f, ring, cells + coff[c],
-                                   n, c0, cn, p.chunk);
+                hipLaunchKernelGGL((k_push_pf<D, FT, BS>), grid, dim3(BS), tab + red, s, p, f, ring, cells + coff[c], n,
+                                   c0, cn, p.chunk, ks);
             else
-                hipLaunchKernelGGL((k_push<D, FT, BS, false>), dim3(g), dim3(BS), tab + red, s, p, f, ring,
-                                   cells + coff[c], n, c0, cn, p.chunk);
+                hipLaunchKernelGGL((k_push<D, FT, BS, false>), grid, dim3(BS), tab + red, s, p, f, ring,
+                                   cells + coff[c], n, c0, cn, p.chunk, ks);
         }
         hipLaunchKernelGGL((k_push_chunk_end<D, FT>), dim3(gc), dim3(BS), lcell, s, p, f, ring, c0, cn, q);
     }
