@@ -588,6 +588,29 @@ def test_tetrahedral_sphere_reaches_steady_state():
     assert rel < 1e-6
 
 
+def test_fp32_storage_error_over_2000_cylinder_steps():
+    """FP32 f on the full cylinder (20,000 x 3,600, Ma 5) over the first
+    2,000 steps, while the bow shock forms, against FP64 f on the GPU (the
+    FP64 path is the oracle-pinned one; the oracle itself would take hours
+    here): relative L1 errors of rho, U and E below 1e-5."""
+    ugks = _gpu()
+    c = cases.case_cylinder()
+    _say(f"case {c['name']}: fp64 (gather) and fp32 (push), 2000 steps each")
+    res = {}
+    for fs in ("f64", "f32"):
+        s = ugks.Solver(c, fstore=fs)
+        s.step(2000)
+        res[fs] = s.macros()[0]
+        s.close()
+    W, W0 = res["f32"], res["f64"]
+    U, U0 = W[:, 1:3] / W[:, :1], W0[:, 1:3] / W0[:, :1]
+    l1 = {"rho": np.abs(W[:, 0] - W0[:, 0]).sum() / np.abs(W0[:, 0]).sum(),
+          "U": np.linalg.norm(U - U0, axis=1).sum() / np.linalg.norm(U0, axis=1).sum(),
+          "E": np.abs(W[:, 3] - W0[:, 3]).sum() / np.abs(W0[:, 3]).sum()}
+    _say(f"    relative L1 errors {l1}")
+    assert max(l1.values()) < 1e-5
+
+
 def test_lifting_body_cut_down_100k_fp64():
     """The lifting body at a tenth of its size: 107,118 hexahedra and prisms
     (16 x 16 points per cube face, 66 layers, the polar columns as prisms),

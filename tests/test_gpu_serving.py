@@ -1,10 +1,11 @@
 """Serving on the GPU: admission by footprint, overlapped cases, and each
-result equal to the same case run alone."""
+result equal to the same case run alone (and to the oracle)."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2412_06546_amd import cases
 
 pytestmark = pytest.mark.gpu
@@ -83,6 +84,13 @@ def test_each_result_in_the_mix_equals_the_result_alone(batched):
         alone.close()
         assert np.array_equal(r.W, W), r.rid
         assert np.array_equal(r.q, q), r.rid
+        # and the served result against the oracle
+        o = oracle.Oracle(c)
+        o.step(steps)
+        Wo, _ = o.macros()
+        scale = np.abs(Wo).max(axis=0)
+        scale[1:-1] = np.maximum(scale[1:-1], Wo[:, 0].max())
+        assert (np.abs(r.W - Wo).max(axis=0) / scale).max() <= 1e-12, r.rid
 
 
 def test_async_steps_match_synchronous_steps():
