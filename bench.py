@@ -210,6 +210,9 @@ def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers"
 
 def sweep_kernels(run, mem):
     """The kernels one timed sweep launch consists of."""
+    if mem == "in-place" and run.get("sweep") == "push":
+        return (f"push sweep in place: k_push_wall, then per velocity chunk k_push_chunk_turn and {run['n_colours']} "
+                f"colour launches of k_push_pf (k_push), a last k_push_chunk_turn, k_push_final_inplace, timed together")
     if mem == "in-place":
         return "k_sweep_chunk (every chunk) + k_sweep_finish"
     if run.get("sweep") == "push":

@@ -2669,10 +2669,11 @@ __global__ __launch_bounds__(256) void k_push_final_r(Params p, FT *__restrict__
 // Push sweep with one f buffer (the in-place mode).  The velocities are taken
 // in chunks; per chunk, the base of the chunk's velocities goes into a ring of
 // one chunk per cell (its moments added to the cell's running sum), the
-// colour launches push the chunk's face fluxes into the ring, and a chunk-end
-// kernel writes the stage-1 values back into f -- no later launch reads f^n at
-// those velocities -- adding their moments about U^n (orders 0-3 of h, 0-1 of
-// b) to a second running sum.  After the last chunk a final kernel forms
+// colour launches push the chunk's face fluxes into the ring, and the next
+// turn kernel writes the stage-1 values back into f -- no later launch reads
+// f^n at those velocities -- adding their moments about U^n (orders 0-3 of h,
+// 0-1 of b) to a second running sum, before it fills the ring with the next
+// chunk's base.  After the last chunk a final kernel forms
 // W^{n+1}, tau^{n+1}, q^{n+1} from the two sums and applies stage 2 in place.
 // The wall kernel runs first, while f still holds f^n at every velocity.
 // ------------------------------------------------------------------------
@@ -2756,92 +2757,82 @@ __device__ __forceinline__ void macro_from_shift(const Params &p, const double (
     }
 }
 
-// base of velocities [c0, c0 + cn) into the ring; its moments added to
-// mom_part (chunk 0 starts the sum)
+// The turn between two chunks, per cell: the previous chunk's stage-1
+// values from the ring back into f, their moments about U^n added to mom_s;
+// then the base of the next chunk's velocities into the ring, its moments
+// added to mom_part (a chunk index of -1 skips that half; chunk 0 starts
+// each sum).  Each cell's ring slice is touched only by its own workgroup.
 template <int D, typename FT, bool TENSOR>
-__global__ __launch_bounds__(256) void k_push_base_chunk(Params p, const FT *__restrict__ f, FT *__restrict__ ring,
-                                                         int c0, int cn, int ichunk)
-{
-    constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256;
-    extern __shared__ double smem[];
-    const int i = xcd_cell(blockIdx.x);
-    if (i >= p.nc) return;
-    const int nv = p.nv, ch = p.chunk, tid = threadIdx.x;
-    const CellStep<D> cs = cell_step<D>(p, i);
-    double *tb = smem;
-    double *red = smem + (TENSOR ? p.ntab : 0);
-    if constexpr (TENSOR) fill_group_table<D, BS>(p, cs.pn.lam, cs.pn.U[0], cs.pn.U[1], cs.pn.U[D - 1], tb);
-    const size_t fb = (size_t)i * NC * nv, rb = (size_t)i * NC * ch;
-    double mom[NW];
-#pragma unroll
-    for (int m = 0; m < NW; ++m) mom[m] = 0.0;
-#pragma unroll 2
-    for (int kk = tid; kk < cn; kk += BS) {
-        const int k = c0 + kk;
-        double u[D], u2;
-        velocity<D>(p, k, u, u2);
-        const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
-        double fp[2];
-        const double H = cs.pref_n * own_gauss<D, TENSOR>(p, tb, kx, u, cs.pn.lam, cs.pn.U);
-        shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
-        double bv[2] = {0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double fv = to_f64(f[fb + (size_t)c * nv + k]);
-            const FT sv = from_f64<FT>(fma(cs.hdt_tau, fp[c] - fv, fv));
-            ring[rb + (size_t)c * ch + kk] = sv;
-            bv[c] = to_f64(sv);
-        }
-        add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
-    }
-    block_reduce_wide<BS>(mom, red, OpAdd{});
-    if (tid == 0)
-#pragma unroll
-        for (int m = 0; m < NW; ++m)
-            p.mom_part[(size_t)i * NW + m] = (ichunk == 0 ? 0.0 : p.mom_part[(size_t)i * NW + m]) + mom[m];
-}
-
-// the chunk's stage-1 values from the ring back into f, their moments about
-// U^n added to mom_s (chunk 0 starts the sum)
-template <int D, typename FT>
-__global__ __launch_bounds__(256) void k_push_chunk_end(Params p, FT *__restrict__ f, const FT *__restrict__ ring,
-                                                        int c0, int cn, int ichunk)
+__global__ __launch_bounds__(256) void k_push_chunk_turn(Params p, FT *__restrict__ f, FT *__restrict__ ring, int pc0,
+                                                         int pcn, int pq, int nc0, int ncn, int nq)
 {
     constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256, N = Shift<D>::N;
     extern __shared__ double smem[];
     const int i = xcd_cell(blockIdx.x);
     if (i >= p.nc) return;
     const int nv = p.nv, ch = p.chunk, tid = threadIdx.x;
-    double Wn[NW];
-#pragma unroll
-    for (int m = 0; m < NW; ++m) Wn[m] = p.W[(size_t)i * NW + m];
-    const Prim<D> pn = to_prim<D>(Wn);
     const size_t fb = (size_t)i * NC * nv, rb = (size_t)i * NC * ch;
-    double mm[N];
+    double *tb = smem;
+    double *red = smem + (TENSOR ? p.ntab : 0);
+    const CellStep<D> cs = cell_step<D>(p, i);
+    if (pq >= 0) {
+        double mm[N];
 #pragma unroll
-    for (int t = 0; t < N; ++t) mm[t] = 0.0;
+        for (int t = 0; t < N; ++t) mm[t] = 0.0;
 #pragma unroll 4
-    for (int kk = tid; kk < cn; kk += BS) {
-        const int k = c0 + kk;
-        double v[2] = {0.0, 0.0};
+        for (int kk = tid; kk < pcn; kk += BS) {
+            const int k = pc0 + kk;
+            double v[2] = {0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const FT x = ring[rb + (size_t)c * ch + kk];
-            f[fb + (size_t)c * nv + k] = x;
-            v[c] = to_f64(x);
-        }
-        double c[D], c2 = 0.0;
+            for (int c = 0; c < NC; ++c) {
+                const FT x = ring[rb + (size_t)c * ch + kk];
+                f[fb + (size_t)c * nv + k] = x;
+                v[c] = to_f64(x);
+            }
+            double cv[D], c2 = 0.0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            c[d] = p.u[d * nv + k] - pn.U[d];
-            c2 = fma(c[d], c[d], c2);
+            for (int d = 0; d < D; ++d) {
+                cv[d] = p.u[d * nv + k] - cs.pn.U[d];
+                c2 = fma(cv[d], cv[d], c2);
+            }
+            add_shift_moments<D>(mm, p.w[k], cv, c2, v[0], NC > 1 ? v[NC - 1] : 0.0);
         }
-        add_shift_moments<D>(mm, p.w[k], c, c2, v[0], NC > 1 ? v[NC - 1] : 0.0);
+        block_reduce_wide<BS>(mm, red, OpAdd{});
+        if (tid == 0)
+#pragma unroll
+            for (int t = 0; t < N; ++t)
+                p.mom_s[(size_t)i * N + t] = (pq == 0 ? 0.0 : p.mom_s[(size_t)i * N + t]) + mm[t];
     }
-    block_reduce_wide<BS>(mm, smem, OpAdd{});
-    if (tid == 0)
+    if (nq >= 0) {
+        if constexpr (TENSOR) fill_group_table<D, BS>(p, cs.pn.lam, cs.pn.U[0], cs.pn.U[1], cs.pn.U[D - 1], tb);
+        double mom[NW];
 #pragma unroll
-        for (int t = 0; t < N; ++t) p.mom_s[(size_t)i * N + t] = (ichunk == 0 ? 0.0 : p.mom_s[(size_t)i * N + t]) + mm[t];
+        for (int m = 0; m < NW; ++m) mom[m] = 0.0;
+#pragma unroll 2
+        for (int kk = tid; kk < ncn; kk += BS) {
+            const int k = nc0 + kk;
+            double u[D], u2;
+            velocity<D>(p, k, u, u2);
+            const unsigned kx = TENSOR ? (unsigned)p.kidx[k] : 0u;
+            double fp[2];
+            const double H = cs.pref_n * own_gauss<D, TENSOR>(p, tb, kx, u, cs.pn.lam, cs.pn.U);
+            shakhov<D>(u, cs.pn.U, cs.pn.lam, cs.shk_n, cs.qn, cs.bh_n, H, fp[0], fp[1]);
+            double bv[2] = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double fv = to_f64(f[fb + (size_t)c * nv + k]);
+                const FT sv = from_f64<FT>(fma(cs.hdt_tau, fp[c] - fv, fv));
+                ring[rb + (size_t)c * ch + kk] = sv;
+                bv[c] = to_f64(sv);
+            }
+            add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
+        }
+        block_reduce_wide<BS>(mom, red, OpAdd{});
+        if (tid == 0)
+#pragma unroll
+            for (int m = 0; m < NW; ++m)
+                p.mom_part[(size_t)i * NW + m] = (nq == 0 ? 0.0 : p.mom_part[(size_t)i * NW + m]) + mom[m];
+    }
 }
 
 // after the last chunk: W^{n+1}, tau^{n+1}, q^{n+1}, stage 2 in place
@@ -2999,7 +2990,10 @@ hipError_t push_inplace_t(const Params &p, void *fv, const int *cells, const int
                            wall_cells, n_wall_cells);
     for (int q = 0; q < p.nchunk; ++q) {
         const int c0 = q * p.chunk, cn = std::min(p.chunk, p.nv - c0);
-        hipLaunchKernelGGL((k_push_base_chunk<D, FT, TENSOR>), dim3(gc), dim3(BS), lcell, s, p, f, ring, c0, cn, q);
+        // the previous chunk back into f, this chunk's base into the ring
+        const int pc0 = (q - 1) * p.chunk;
+        hipLaunchKernelGGL((k_push_chunk_turn<D, FT, TENSOR>), dim3(gc), dim3(BS), lcell, s, p, f, ring, pc0,
+                           q > 0 ? p.chunk : 0, q - 1, c0, cn, q);
         for (int c = 0; c < ncol; ++c) {
             const int n = coff[c + 1] - coff[c];
             if (n <= 0) continue;
@@ -3013,7 +3007,11 @@ hipError_t push_inplace_t(const Params &p, void *fv, const int *cells, const int
                 hipLaunchKernelGGL((k_push<D, FT, BS, false>), grid, dim3(BS), tab + red, s, p, f, ring,
                                    cells + coff[c], n, c0, cn, p.chunk, ks);
         }
-        hipLaunchKernelGGL((k_push_chunk_end<D, FT>), dim3(gc), dim3(BS), lcell, s, p, f, ring, c0, cn, q);
+    }
+    {
+        const int q = p.nchunk - 1, c0 = q * p.chunk;
+        hipLaunchKernelGGL((k_push_chunk_turn<D, FT, TENSOR>), dim3(gc), dim3(BS), lcell, s, p, f, ring, c0,
+                           p.nv - c0, q, 0, 0, -1);
     }
     hipLaunchKernelGGL((k_push_final_inplace<D, FT, TENSOR>), dim3(gc), dim3(BS), lcell, s, p, f);
     return hipGetLastError();
