@@ -208,6 +208,17 @@ def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers"
     return out
 
 
+def json_safe(x):
+    """NaN (a percentile of no cases) as null: JSON has no NaN."""
+    if isinstance(x, float) and x != x:
+        return None
+    if isinstance(x, dict):
+        return {k: json_safe(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [json_safe(v) for v in x]
+    return x
+
+
 def sweep_kernels(run, mem):
     """The kernels one timed sweep launch consists of."""
     if mem == "in-place" and run.get("sweep") == "push":
@@ -281,7 +292,7 @@ def run_serving_stream(args):
                                    f"20^2-64^2 velocities, tol 1e-6, cap {args.serving_steps} steps, f32",
                        "mode": args.serving_mode, "budget_bytes": srv.budget, "peak_bytes": srv.peak_used},
             "serving": summ}
-    print(json.dumps(line), flush=True)
+    print(json.dumps(json_safe(line)), flush=True)
 
 
 def main():
@@ -392,7 +403,7 @@ def main():
     if not args.no_cpu_baseline and args.workload == "liftingbody":
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    print(json.dumps(line), flush=True)
+    print(json.dumps(json_safe(line)), flush=True)
 
 
 if __name__ == "__main__":

@@ -51,3 +51,10 @@ def test_algorithmic_flops_per_update(dim, nf, expected):
     updates: the per-update counts the roofline is priced with (cylinder's mean
     of 3.9 faces, tetrahedra, hexahedra)."""
     assert bench.alg_flops_per_update(dim, nf) == pytest.approx(expected, abs=0.06)
+
+
+def test_json_line_has_no_nan():
+    """Percentiles of an empty set of cases are NaN; the JSON line carries null."""
+    import json
+    line = bench.json_safe({"a": float("nan"), "b": [1.0, float("nan")], "c": {"d": float("nan"), "e": 2}})
+    assert json.loads(json.dumps(line)) == {"a": None, "b": [1.0, None], "c": {"d": None, "e": 2}}
