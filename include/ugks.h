@@ -291,18 +291,20 @@ int ugks_is_tensor_grid(const ugks_t *h);
  * face fluxes of Alg. 1 lines 4-8 (batched steps always gather); -1 for a
  * NULL handle. */
 int ugks_sweep_kind(const ugks_t *h);
-/* The number of colour classes (launches per step) of the push sweep: cells
- * of one class share no neighbour and are not neighbours; 0 when the handle
- * gathers, -1 for a NULL handle. */
+/* The number of colour classes (launches per step, or per velocity chunk in
+ * place) into which the push sweep splits the face-flux loop of Alg. 1 lines
+ * 4-8: cells of one class share no neighbour and are not neighbours; 0 when
+ * the handle gathers, -1 for a NULL handle. */
 int ugks_sweep_colours(const ugks_t *h);
 
 /* Timing of the step's kernels with HIP events on the handle's stream (the
  * per-step wall time the paper reports in Table UGKSeff).
  * ugks_profile(h, 1) resets the counters and records events around every
  * launch from then on (0 stops).  ugks_profile_read gives ms_out[0] = total
- * milliseconds in the fused sweep kernel, ms_out[1] = total in the two
- * prologue kernels (macro gradients and interface equilibria), and the
- * number of steps timed. */
+ * milliseconds in the sweep (Alg. 1 lines 4-11: every kernel of it, e.g. the
+ * push sweep's wall, colour and final launches), ms_out[1] = total in the
+ * two prologue kernels (macro gradients and interface equilibria, lines
+ * 1-3), and the number of steps timed. */
 int ugks_profile(ugks_t *h, int enable);
 int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
 
