@@ -1437,14 +1437,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 }
 
 // ------------------------------------------------------------------------
-// Push sweep (two f buffers, FP64 or FP32 f): each face flux once.
+// Push sweep (FP64 or FP32 f; two f buffers, or in place one f and a ring of
+// one velocity chunk): each face flux once.
 //
 // Per velocity, the flux through an interior face needs the limited slope
 // of the upwind cell only (Eq. fullSolution).  The cells are split into
 // colours such that no two cells of a colour are neighbours or share a
 // neighbour (distance-2 colouring), and one launch per colour advances its
-// cells: a workgroup owns one cell's velocity slab, rebuilds that cell's
-// own limited slope, and for every face through which the cell is upwind
+// cells: a workgroup owns one cell's velocity slab (or a share of it, when
+// a class is too small to fill the chip), rebuilds that cell's own limited
+// slope, and for every face through which the cell is upwind
 // at a velocity it evaluates the time-integrated flux once and adds it to
 // the stage-1 accumulator of both cells (- F / |Omega_i| here, + F /
 // |Omega_n| there).  Faces through which the cell is downwind are added by
@@ -1565,7 +1567,7 @@ constexpr int kPushCellsPerGroup = 4;
 // Stage-1 base of cell i and its moments: acc = f + (dt / 2 tau)(f+ - f)
 // from f^n, W^n, q^n (after a start, a restart or a step of another kind).
 // V2: velocities in pairs (even velocity count).  Same lane order and
-// arithmetic as the final kernel's pass 3, so both give the same bits.
+// arithmetic as the final kernel's second pass, so both give the same bits.
 template <int D, typename FT, bool TENSOR, bool V2>
 __global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restrict__ fin, FT *__restrict__ acc)
 {
@@ -2576,7 +2578,7 @@ __global__ __launch_bounds__(256) void k_push_final_r(Params p, FT *__restrict__
 #pragma unroll
     for (int t = 0; t < NM; ++t) m2[t] = mm[1 + D + t];
 
-    // macro: as in k_push_final
+    // macro: as in k_push_final (and macro_from_shift)
     double mom[NW], trm2 = 0.0, um1 = 0.0, uu = 0.0;
     mom[0] = m0;
 #pragma unroll
@@ -2895,8 +2897,8 @@ __global__ __launch_bounds__(256) void k_push_final_inplace(Params p, FT *__rest
 }
 
 // ------------------------------------------------------------------------
-// push sweep launches: the stage-1 base (when stale), one launch per colour,
-// the final kernel
+// push sweep launches: the stage-1 base (when stale), the wall cells, one
+// launch per colour (split over velocities when small), the final kernel
 // ------------------------------------------------------------------------
 template <int D, typename FT, bool TENSOR>
 hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int *cells, const int *coff, int ncol,
