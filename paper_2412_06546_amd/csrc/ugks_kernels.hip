@@ -1449,7 +1449,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 // slope, and for every face through which the cell is upwind
 // at a velocity it evaluates the time-integrated flux once and adds it to
 // the stage-1 accumulator of both cells (- F / |Omega_i| here, + F /
-// |Omega_n| there).  Faces through which the cell is downwind are added by
+// |Omega_n| there) with hardware atomic adds that return nothing, so that
+// the velocity loop never waits on an accumulator load.  Faces through which the cell is downwind are added by
 // the neighbour in its own colour's launch.  No two workgroups of a launch
 // touch the same accumulator, and the colours run in a fixed order, so the
 // sums are deterministic; the accumulator holds, before the first colour,
@@ -1773,11 +1774,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
             const double uo = gi.side[j] ? -un : un;  // along this cell's outward normal
             if (F.bc == 0) {
                 if (!(uo > 0.0)) continue;  // the neighbour is upwind: it adds this flux
-                // the neighbour's accumulator first, so its load overlaps the arithmetic
                 FT *an = acc + (size_t)gi.nb[j] * NC * accv;
-                double av[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) av[c] = to_f64(an[(size_t)c * accv + (k - k0)]);
                 double val[NC], ug[NC], I[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -1797,7 +1794,10 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
                 for (int c = 0; c < NC; ++c) {
                     const double fl = sa * I[c];
                     out[c] += fl;
-                    an[(size_t)c * accv + (k - k0)] = from_f64<FT>(fma(fl, vn_inv, av[c]));
+                    // an atomic add without return: no load waits in the
+                    // velocity loop (no other workgroup of the launch adds
+                    // to this element, so the order of the sums stays fixed)
+                    unsafeAtomicAdd(an + (size_t)c * accv + (k - k0), from_f64<FT>(fl * vn_inv));
                 }
             } else {
                 double I[NC];
@@ -1827,7 +1827,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             FT *a = acc + base + (size_t)c * accv + (k - k0);
-            *a = from_f64<FT>(fma(-out[c], gi.inv_vol, to_f64(*a)));
+            unsafeAtomicAdd(a, from_f64<FT>(-out[c] * gi.inv_vol));
         }
     }
 }
