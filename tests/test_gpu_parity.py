@@ -743,7 +743,8 @@ def test_2d_unstructured_velocity_set_fp64():
 @pytest.mark.parametrize("sweep", ["push", "gather"])
 @pytest.mark.parametrize("name,chunk", [("periodic wave", 0), ("periodic wave", 100), ("periodic wave", 5000),
                                         ("periodic wave", 1), ("cylinder cut-down", 0), ("cylinder cut-down", 96),
-                                        ("3D channel", 64), ("3D channel", 1), ("scattered velocities", 10)])
+                                        ("3D channel", 64), ("3D channel", 1), ("scattered velocities", 10),
+                                        ("wide velocity set", 1100)])
 def test_in_place_mode_matches_the_oracle(name, chunk, sweep):
     """UGKS_MEM_IN_PLACE: one f buffer updated in place, velocities swept in
     chunks (two ragged chunks, several, one, one velocity per chunk), walls
@@ -758,6 +759,8 @@ def test_in_place_mode_matches_the_oracle(name, chunk, sweep):
         c = cases.case_cylinder_small()
     elif name == "3D channel":
         c = cases.case_channel_3d(n=3, kind="prism", nv=8)
+    elif name == "wide velocity set":   # 1,600 velocities: chunks wider than 1,024
+        c = cases.case_periodic_wave(nx=10, ny=6, nv=40, seed=5)
     else:
         c = cases.case_periodic_wave(nx=6, ny=6, nv=26, seed=4)
         rng = np.random.default_rng(9)
