@@ -9,7 +9,10 @@ cell-velocity updates per step, the size of the paper's only timed workload
 (Section 4.3, Table UGKSeff) and the largest single-GPU configuration.  A
 step is one full time step of the scheme (macro gradients, interface
 equilibria, fused sweep with wall, macro update, heat flux and both stages
-of the f update) on inputs resident in HBM.
+of the f update) on inputs resident in HBM.  The sweep is the unordered push
+(--sweep push_unordered: every face flux once, by its upwind cell, all cells
+in one launch in stored order; sums rounded in no fixed order); the
+deterministic coloured push is timed beside it.
 
 Prints one JSON line:
   value      cell-velocity updates/s of the headline (HIP events on the
@@ -21,6 +24,8 @@ Prints one JSON line:
              from the committed counter profile (when the kernel source is
              the one profiled); the vector-ALU figure beside it (the method's
              algorithmic FP64 flops against 78.6 TFLOP/s);
+  coloured_push   the headline step with the coloured (bitwise
+             reproducible) push sweep;
   other_precision   the same workload with f in FP32 and BF16;
   secondary_workloads   the 2D cylinder (20,000 cells x 3,600 velocities);
   serving    a bounded serving leg: a Poisson stream of 16 small 2D cases
@@ -48,8 +53,9 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, vector FP64
 KERNEL_SRC = os.path.join(ROOT, "paper_2412_06546_amd", "csrc", "ugks_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
+DEFAULT_SWEEP = "push_unordered"
 TRAFFIC_FILES = {"liftingbody": os.path.join(PROFILES, "k_push_sweep_liftingbody1m_traffic.txt"),
-                 "cylinder": os.path.join(PROFILES, "k_sweep_cylinder20k_traffic.txt")}
+                 "cylinder": os.path.join(PROFILES, "k_push_sweep_cylinder20k_traffic.txt")}
 
 WORKLOADS = {
     "liftingbody": "3D X38-sized lifting body Ma 8 AoA 20 Kn 0.01 Shakhov Pr 0.72, wall 5.39 T_inf, "
@@ -89,10 +95,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str, fstore: str, path: str | None = None):
+def measured_traffic(workload: str, fstore: str, path: str | None = None, sweep: str | None = None):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary of this workload, or None when there is none or the kernel
-    source changed since it was taken."""
+    summary of this workload, or None when there is none, the kernel
+    source changed since it was taken or it was taken with another sweep."""
     path = path or TRAFFIC_FILES.get(workload)
     if not path or not os.path.exists(path):
         return None
@@ -102,6 +108,8 @@ def measured_traffic(workload: str, fstore: str, path: str | None = None):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if sweep is not None and vals.get("sweep") != sweep:
         return None
     key = f"traffic_bytes_per_launch_{fstore}"
     return float(vals[key]) if key in vals else None
@@ -170,14 +178,17 @@ def cpu_baseline(target_s: float):
                       f"cells, gcc -O2); then 1 step of a {nc1}-cell cut-down on 1 thread ({t1:.1f} s)"}
 
 
-def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers", chunk: int = 0):
+def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers", chunk: int = 0,
+            sweep: str = "auto"):
     """Warm-up steps, then exactly `steps` timed steps between device
     synchronisations; HIP events on torch's current stream (the stream the
     library launches on) around the timed steps, and the library's own
     events around every sweep launch."""
     import torch
     from paper_2412_06546_amd import ugks
-    s = ugks.Solver(case, fstore=fstore, mem=mem, chunk=chunk)
+    if fstore == "bf16" and sweep in ("push", "push_unordered"):
+        sweep = "auto"          # BF16 f is gathered
+    s = ugks.Solver(case, fstore=fstore, mem=mem, chunk=chunk, sweep=sweep)
     nc, nv, ncomp = s.nc, s.nv, s.ncomp
     if warmup:
         s.step(warmup)
@@ -221,14 +232,17 @@ def json_safe(x):
 
 def sweep_kernels(run, mem):
     """The kernels one timed sweep launch consists of."""
-    if mem == "in-place" and run.get("sweep") == "push":
-        return (f"push sweep in place: k_push_wall, then per velocity chunk k_push_chunk_turn and {run['n_colours']} "
-                f"colour launches of k_push_pf (k_push), a last k_push_chunk_turn, k_push_final_inplace, timed together")
+    if run.get("sweep") == "push_unordered":
+        launches = "one launch of k_push_pf (k_push) over all cells in stored order"
+    else:
+        launches = f"{run.get('n_colours')} colour launches of k_push_pf (k_push)"
+    if mem == "in-place" and run.get("sweep", "").startswith("push"):
+        return (f"push sweep in place: k_push_wall, then per velocity chunk k_push_chunk_turn and {launches}, "
+                f"a last k_push_chunk_turn, k_push_final_inplace, timed together")
     if mem == "in-place":
         return "k_sweep_chunk (every chunk) + k_sweep_finish"
-    if run.get("sweep") == "push":
-        return (f"push sweep: k_push_wall, {run['n_colours']} colour launches of k_push_pf (k_push), "
-                f"k_push_final_r (k_push_final), timed together")
+    if run.get("sweep", "").startswith("push"):
+        return f"push sweep: k_push_wall, {launches}, k_push_final_r (k_push_final), timed together"
     return "k_sweep_pf (k_sweep)"
 
 
@@ -238,7 +252,7 @@ def roofline_of(case, run, workload, fstore, mem):
     alg_flops = fpu * run["nc"] * run["nv"]
     sweep_s = run["sweep_ms_avg"] / 1e3
     tflops = alg_flops / sweep_s / 1e12
-    traffic = measured_traffic(workload, fstore) if mem == "two-buffers" else None
+    traffic = measured_traffic(workload, fstore, sweep=run.get("sweep")) if mem == "two-buffers" else None
     return {"bound": "hbm", "achieved": round(run["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(run["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": sweep_kernels(run, mem),
@@ -305,8 +319,10 @@ def main():
     ap.add_argument("--mem", choices=["two-buffers", "in-place"], default="two-buffers",
                     help="f in two buffers (f^n, f^{n+1}) or one buffer updated in place by velocity chunks")
     ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = the library default)")
+    ap.add_argument("--sweep", choices=["auto", "gather", "push", "push_unordered"], default=DEFAULT_SWEEP,
+                    help="how the sweep evaluates the face fluxes (UGKS_SWEEP_*); BF16 f always gathers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-secondary", action="store_true", help="skip the other precisions and workloads")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the coloured push, the other precisions and workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-leg-cases", type=int, default=16)
@@ -340,7 +356,7 @@ def main():
     case = make_case(args.workload)
     nc, nv = len(case["mesh"]["cell_volume"]), len(case["vgrid"]["w"])
     print(f"# workload {case['name']}: {nc} cells x {nv} velocities, f {args.fstore}", file=sys.stderr, flush=True)
-    main_run = run_gpu(case, args.fstore, args.steps, args.warmup, args.mem, args.chunk)
+    main_run = run_gpu(case, args.fstore, args.steps, args.warmup, args.mem, args.chunk, args.sweep)
     print(f"# gpu {args.fstore}: {main_run['ms_per_step']:.3f} ms/step, sweep {main_run['sweep_ms_avg']:.3f} ms",
           file=sys.stderr, flush=True)
     line = {
@@ -359,7 +375,8 @@ def main():
         "config": {"workload": f"{case['name']}: {WORKLOADS[args.workload]}",
                    "n_cells": nc, "n_vel": nv, "f_storage": args.fstore, "macros": "f64", "mem": args.mem,
                    "prologue_ms": round(main_run["prologue_ms_avg"], 4),
-                   "footprint_bytes": main_run["footprint_bytes"], "all_cells_physical": main_run["finite"]},
+                   "footprint_bytes": main_run["footprint_bytes"], "all_cells_physical": main_run["finite"],
+                   "sweep": main_run["sweep"], "sweep_launches": main_run["n_colours"]},
         "roofline": roofline_of(case, main_run, args.workload, args.fstore, args.mem),
     }
     # the targets this build measures against, stated beside the figures
@@ -367,14 +384,22 @@ def main():
         "hbm_fraction": {"target": 0.60, "measured": line["roofline"]["frac"],
                          "met": line["roofline"]["frac"] >= 0.60},
     }
+    if main_run["sweep"] == "push_unordered" and not args.no_secondary:
+        # the same step with the deterministic (coloured) push sweep, beside it
+        r2 = run_gpu(case, args.fstore, max(4, args.steps // 2), min(args.warmup, 2), args.mem, args.chunk, "push")
+        line["coloured_push"] = {"sweep": r2["sweep"], "colour_launches": r2["n_colours"],
+                                 "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
+                                 "sweep_ms": round(r2["sweep_ms_avg"], 4),
+                                 "unordered_speedup": round(r2["ms_per_step"] / main_run["ms_per_step"], 3)}
+        print(f"# gpu {args.fstore} coloured push: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if args.mem == "in-place":
         from paper_2412_06546_amd.ugks import UGKS_DEFAULT_CHUNK
         line["config"]["chunk"] = min(args.chunk if args.chunk > 0 else UGKS_DEFAULT_CHUNK, nv)
     if not args.no_secondary:
         other = []
         for fs2 in [x for x in ("f64", "f32", "bf16") if x != args.fstore]:
-            r2 = run_gpu(case, fs2, max(4, args.steps // 2), min(args.warmup, 2), args.mem, args.chunk)
-            other.append({"f_storage": fs2, "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
+            r2 = run_gpu(case, fs2, max(4, args.steps // 2), min(args.warmup, 2), args.mem, args.chunk, args.sweep)
+            other.append({"f_storage": fs2, "sweep": r2["sweep"], "value": r2["updates_per_s"], "ms_per_step": r2["ms_per_step"],
                           "sweep_ms": round(r2["sweep_ms_avg"], 4), "alg_gbs": round(r2["achieved_gbs"], 1),
                           "speedup_over_headline": round(main_run["ms_per_step"] / r2["ms_per_step"], 3)})
             print(f"# gpu {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -387,9 +412,9 @@ def main():
             c2 = make_case(wl)
             entry = {"workload": f"{c2['name']}: {WORKLOADS[wl]}"}
             for fs2 in ("f64", "f32"):
-                r2 = run_gpu(c2, fs2, max(20, args.steps), 3)
+                r2 = run_gpu(c2, fs2, max(20, args.steps), 3, sweep=args.sweep)
                 rl = roofline_of(c2, r2, wl, fs2, "two-buffers")
-                entry[fs2] = {"value": r2["updates_per_s"], "ms_per_step": round(r2["ms_per_step"], 4),
+                entry[fs2] = {"value": r2["updates_per_s"], "sweep": r2["sweep"], "ms_per_step": round(r2["ms_per_step"], 4),
                               "sweep_ms": rl["kernel_ms"], "hbm_frac": rl["frac"], "alu_frac": rl["alu"]["frac"],
                               "traffic": rl["traffic"]}
                 print(f"# gpu {wl} {fs2}: {r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)

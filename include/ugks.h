@@ -109,10 +109,11 @@ typedef struct {
     const double *bc_prim; /* [n_bc][dim+2]: (rho, U, T); walls use (U_w, T_w) */
     int mem_mode;       /* UGKS_MEM_TWO_BUFFERS or UGKS_MEM_IN_PLACE (below) */
     int chunk;          /* in-place mode: velocities per chunk, 0 = UGKS_DEFAULT_CHUNK */
-    int sweep;          /* UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER or UGKS_SWEEP_PUSH (below) */
+    int sweep;          /* UGKS_SWEEP_AUTO, _GATHER, _PUSH or _PUSH_UNORDERED (below) */
 } ugks_gas_t;
 
-/* How the per-velocity sweep (Alg. 1 lines 4-8) evaluates the face fluxes.
+/* How the per-velocity sweep (the velocity loop of Algorithm 1) evaluates the
+ * face fluxes.
  * UGKS_SWEEP_PUSH: every face flux once per velocity, by the face's upwind
  * cell with its own limited slope; the cells are coloured so that no two
  * cells of a colour are neighbours or share one, one launch per colour adds
@@ -120,6 +121,14 @@ typedef struct {
  * holds them; in the in-place mode a ring of one velocity chunk does, chunk
  * after chunk), and a final kernel forms W^{n+1}, q^{n+1} and stage 2.
  * Needs FP64 or FP32 f.
+ * UGKS_SWEEP_PUSH_UNORDERED: the push sweep with every cell in one launch,
+ * in stored (space-filling-curve) order, so that neighbours run close
+ * together and their f and stage-1 values are found in cache.  Several
+ * workgroups may then add to one stage-1 value at once; the hardware adds
+ * are atomic, so the sum is complete, but its order, and so its rounding,
+ * can differ from run to run: results agree with the other sweeps to
+ * rounding, not bit for bit, and a restart from a checkpoint is not
+ * bitwise.  Needs FP64 or FP32 f; never chosen automatically.
  * UGKS_SWEEP_GATHER: one workgroup per cell evaluates every face of its cell,
  * rebuilding the upwind neighbour's limited slope where needed (each
  * interior face twice); BF16 f and batched steps use it.
@@ -130,6 +139,7 @@ typedef struct {
 #define UGKS_SWEEP_AUTO 0
 #define UGKS_SWEEP_GATHER 1
 #define UGKS_SWEEP_PUSH 2
+#define UGKS_SWEEP_PUSH_UNORDERED 3
 
 /* Storage of f.  UGKS_MEM_TWO_BUFFERS: f^n is read from one buffer and
  * f^{n+1} written to the other (2 f of memory; the fastest form).
@@ -244,7 +254,7 @@ size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgri
 /* Copy the conservative variables W [n_cells][dim+2] = (rho, rho U, rho E)
  * (the moments of f with psi = (1, u, (|u|^2 + |xi|^2)/2), Section 2.1) and
  * the heat flux q [n_cells][dim] (nullable; the Shakhov heat flux of
- * Section 2.1, carried from step to step as in Alg. 1 line 1) to host
+ * Section 2.1, carried from step to step as in Algorithm 1's first step) to host
  * memory. */
 int ugks_macros(ugks_t *h, double *W_out, double *q_out);
 
@@ -274,7 +284,7 @@ size_t ugks_state_bytes(const ugks_t *h);
 int ugks_get_state(ugks_t *h, void *buf, size_t bytes);
 int ugks_set_state(ugks_t *h, const void *buf, size_t bytes);
 
-/* Time step of Alg. 1 line 1 (from the CFL condition, fixed for the run),
+/* Time step of Algorithm 1's first step (from the CFL condition, fixed for the run),
  * or -1 for a NULL handle. */
 double ugks_dt(const ugks_t *h);
 /* Stored reduced distributions per (cell, velocity) (Section 2.2): 2 (h, b)
@@ -287,21 +297,22 @@ size_t ugks_footprint_bytes(const ugks_t *h);
 /* 1 if the Gaussians over the velocity set of Section 2.3 are tabulated per
  * axis (few distinct coordinate values per axis), 0 if evaluated directly. */
 int ugks_is_tensor_grid(const ugks_t *h);
-/* UGKS_SWEEP_PUSH or UGKS_SWEEP_GATHER: how the handle's steps evaluate the
- * face fluxes of Alg. 1 lines 4-8 (batched steps always gather); -1 for a
- * NULL handle. */
+/* UGKS_SWEEP_PUSH, UGKS_SWEEP_PUSH_UNORDERED or UGKS_SWEEP_GATHER: how the
+ * handle's steps evaluate the face fluxes in the velocity loop of Algorithm 1 (batched steps
+ * always gather); -1 for a NULL handle. */
 int ugks_sweep_kind(const ugks_t *h);
 /* The number of colour classes (launches per step, or per velocity chunk in
- * place) into which the push sweep splits the face-flux loop of Alg. 1 lines
- * 4-8: cells of one class share no neighbour and are not neighbours; 0 when
- * the handle gathers, -1 for a NULL handle. */
+ * place) into which the push sweep splits the face-flux loop of Algorithm 1
+ * (its velocity loop): cells of one class share no neighbour and are not neighbours; 1 for
+ * the unordered push (one class of all cells), 0 when the handle gathers, -1
+ * for a NULL handle. */
 int ugks_sweep_colours(const ugks_t *h);
 
 /* Timing of the step's kernels with HIP events on the handle's stream (the
  * per-step wall time the paper reports in Table UGKSeff).
  * ugks_profile(h, 1) resets the counters and records events around every
  * launch from then on (0 stops).  ugks_profile_read gives ms_out[0] = total
- * milliseconds in the sweep (Alg. 1 lines 4-11: every kernel of it, e.g. the
+ * milliseconds in the sweep (the velocity loop of Algorithm 1 and the updates after it: every kernel of it, e.g. the
  * push sweep's wall, colour and final launches), ms_out[1] = total in the
  * two prologue kernels (macro gradients and interface equilibria, lines
  * 1-3), and the number of steps timed. */

@@ -174,7 +174,7 @@ class Oracle:
         self._L.orc_set_f(self._h, p)
 
     def macro_gradients(self):
-        """Limited gradients of W for the current state (Alg. 1 line 2),
+        """Limited gradients of W for the current state (the macroscopic reconstruction of Algorithm 1),
         [nc][dim + 2][dim], and per cell whether it fell back to first
         order (a reconstructed face state not physical)."""
         g = np.zeros((self.nc, self.dim + 2, self.dim))

@@ -70,7 +70,7 @@ typedef struct {
     const double *prim0;
 } orc_input_t;
 
-/* interface data of Alg. 1 line 3 */
+/* interface data of Algorithm 1's interface-equilibrium step */
 typedef struct {
     double p[ORC_MAXW], tau; /* (rho, U, lambda) of g0 */
     double a[ORC_MAXD][ORC_MAXW]; /* spatial slopes of g0 per direction */
@@ -580,7 +580,7 @@ orc_t *orc_create(const orc_input_t *in)
         o->eps2[i] = kh * kh * kh;
     }
 
-    /* Alg. 1 line 1, time step: the largest dt with every cell's upwind
+    /* Algorithm 1's first step, time step: the largest dt with every cell's upwind
      * outflow no more than CFL times its volume, over all velocities. */
     if (in->dt_override > 0.0) {
         o->dt = in->dt_override;
@@ -683,7 +683,8 @@ void orc_wall_flux(const orc_t *o, double *out)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Alg. 1 line 2: limited least-squares gradients of the conservative       */
+/* Algorithm 1, macroscopic reconstruction: limited least-squares gradients  */
+/* of the conservative                                                      */
 /* variables [nc][NW][D].  A cell whose reconstructed state at any of its   */
 /* face centroids has rho <= 0 or internal energy <= 0 falls back to first  */
 /* order (zero gradient); fell_back[i] (if given) records it.               */
@@ -1032,7 +1033,7 @@ void orc_time_slope_of_g0(int D, const double *p, const double *a, double *A)
     time_slope_of_g0(D, 3 - D, p, (const double(*)[ORC_MAXW])aa, A);
 }
 double orc_venkat(double dm, double dp, double eps2) { return venkat(dm, dp, eps2); }
-/* line 2 of Algorithm 1 for the current state: gW [nc][D+2][D], and per
+/* the macroscopic reconstruction of Algorithm 1 for the current state: gW [nc][D+2][D], and per
  * cell whether it fell back to first order */
 void orc_macro_gradients(const orc_t *o, double *gW, int *fell_back) { macro_gradients(o, gW, fell_back); }
 /* the 4-point rule (returns the number of nodes written: 4) */

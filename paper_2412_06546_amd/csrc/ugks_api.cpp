@@ -40,7 +40,7 @@ struct ugks {
     // face -> wall ordinal; whether the second buffer holds the stage-1 base
     // of the current f, and whether the last step was a push step (the wall
     // flux of that step is then already in wallF)
-    int push = 0, base_ok = 0, last_push = 0;
+    int push = 0, unordered = 0, base_ok = 0, last_push = 0;
     int *colour_cells = nullptr, *wall_cells = nullptr, *wall_index = nullptr;
     int n_wall_cells = 0;
     std::vector<int> colour_off;
@@ -477,7 +477,13 @@ template <int D> void create_d(ugks_t *h, const StoredMesh &S, const ugks_gas_t 
     build_geometry<D>(S, cg, fgv, gas->limiter_k);
     if (h->push) {
         std::vector<int> cells;
-        push_colours<D>(cg, cells, h->colour_off);
+        if (h->unordered) {  // one class: every cell, in stored order
+            cells.resize(cg.size());
+            for (size_t c = 0; c < cells.size(); ++c) cells[c] = (int)c;
+            h->colour_off = {0, (int)cg.size()};
+        } else {
+            push_colours<D>(cg, cells, h->colour_off);
+        }
         h->colour_cells = dev_alloc<int>(h, cells.size());
         upload(h->colour_cells, cells.data(), sizeof(int) * cells.size(), h->stream);
         std::vector<int> wc;
@@ -514,10 +520,11 @@ int nchunk_of(int chunk, int nv) { return (nv + chunk - 1) / chunk; }
 // 3,600 velocities: 3.2 against 4.2 ms per step; FP32 f 2.7 push against 2.9
 // gather; the 3D lifting body 178 push against 295 ms gather in FP64).
 bool push_applies(const ugks_gas_t *gas) { return gas->fstore != UGKS_BF16; }
+bool asks_push(const ugks_gas_t *gas) { return gas->sweep == UGKS_SWEEP_PUSH || gas->sweep == UGKS_SWEEP_PUSH_UNORDERED; }
 bool uses_push(int dim, const ugks_gas_t *gas)
 {
     if (!push_applies(gas) || gas->sweep == UGKS_SWEEP_GATHER) return false;
-    if (gas->sweep == UGKS_SWEEP_PUSH || gas->mem_mode == UGKS_MEM_IN_PLACE) return true;
+    if (asks_push(gas) || gas->mem_mode == UGKS_MEM_IN_PLACE) return true;
     return !(dim == 2 && gas->fstore == UGKS_F64);
 }
 // the push sweep's running moment sums about U^n, per cell (in place)
@@ -640,11 +647,12 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (gas->mem_mode != UGKS_MEM_TWO_BUFFERS && gas->mem_mode != UGKS_MEM_IN_PLACE)
             throw Fail{UGKS_ERR_ARG, "mem_mode must be UGKS_MEM_TWO_BUFFERS or UGKS_MEM_IN_PLACE"};
         if (gas->chunk < 0) throw Fail{UGKS_ERR_ARG, "chunk must be >= 0"};
-        if (gas->sweep < UGKS_SWEEP_AUTO || gas->sweep > UGKS_SWEEP_PUSH)
-            throw Fail{UGKS_ERR_ARG, "sweep must be UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER or UGKS_SWEEP_PUSH"};
-        if (gas->sweep == UGKS_SWEEP_PUSH && !push_applies(gas))
-            throw Fail{UGKS_ERR_ARG, "the push sweep needs FP64 or FP32 f"};
+        if (gas->sweep < UGKS_SWEEP_AUTO || gas->sweep > UGKS_SWEEP_PUSH_UNORDERED)
+            throw Fail{UGKS_ERR_ARG,
+                       "sweep must be UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH or UGKS_SWEEP_PUSH_UNORDERED"};
+        if (asks_push(gas) && !push_applies(gas)) throw Fail{UGKS_ERR_ARG, "the push sweep needs FP64 or FP32 f"};
         h->push = uses_push(D, gas) ? 1 : 0;
+        h->unordered = gas->sweep == UGKS_SWEEP_PUSH_UNORDERED ? 1 : 0;
         for (int k = 0; k < vgrid->n_vel; ++k) {
             bool ok = vgrid->w[k] > 0.0 && std::isfinite(vgrid->w[k]);
             for (int d = 0; d < D; ++d) ok = ok && std::isfinite(vgrid->u[(size_t)k * D + d]);
@@ -792,7 +800,7 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         P.wflux = h->wallF;
         P.mom_s = h->mom_s;
 
-        // time step (Alg. 1 line 1), fixed for the run
+        // time step (Algorithm 1's first step), fixed for the run
         hip_check(launch_cfl(P, h->cell_dt, h->stream), "k_cfl launch");
         std::vector<double> cdt(nc);
         hip_check(hipMemcpyAsync(cdt.data(), h->cell_dt, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream), "copy dt");
@@ -959,7 +967,7 @@ extern "C" size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vg
     size_t nwallf = 0;
     if (mesh->face_bc)
         for (int f = 0; f < mesh->n_faces; ++f) nwallf += mesh->face_bc[f] == UGKS_BC_WALL;
-    if (gas->sweep == UGKS_SWEEP_PUSH && !push_applies(gas)) return 0;
+    if (asks_push(gas) && !push_applies(gas)) return 0;
     return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab, nwallf,
                       gas->mem_mode, gas->chunk, uses_push(mesh->dim, gas));
 }
@@ -1251,7 +1259,11 @@ extern "C" double ugks_dt(const ugks_t *h) { return h ? h->dt : -1.0; }
 extern "C" int ugks_n_comp(const ugks_t *h) { return h ? h->ncomp : 0; }
 extern "C" long ugks_step_count(const ugks_t *h) { return h ? h->nstep : -1; }
 extern "C" size_t ugks_footprint_bytes(const ugks_t *h) { return h ? h->bytes : 0; }
-extern "C" int ugks_sweep_kind(const ugks_t *h) { return h ? (h->push ? UGKS_SWEEP_PUSH : UGKS_SWEEP_GATHER) : -1; }
+extern "C" int ugks_sweep_kind(const ugks_t *h)
+{
+    if (!h) return -1;
+    return h->push ? (h->unordered ? UGKS_SWEEP_PUSH_UNORDERED : UGKS_SWEEP_PUSH) : UGKS_SWEEP_GATHER;
+}
 
 extern "C" int ugks_sweep_colours(const ugks_t *h)
 {

@@ -46,7 +46,7 @@ template <int D> struct alignas(16) FaceGeo {
     double dr[D];  // right centroid (its periodic image) -> face centroid
 };
 
-// Interface equilibrium (Alg. 1 line 3).  For boundary faces only
+// Interface equilibrium (Algorithm 1's third step).  For boundary faces only
 // (rho, U, lam) and pref are used: ghost Maxwellian (inflow), wall Maxwellian
 // with unit density (wall).
 template <int D> struct alignas(16) FaceEq {

@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void k_moments(Params p, const FT *__restrict_
 }
 
 // ------------------------------------------------------------------------
-// Alg. 1 line 2: limited gradients of the conservative variables
+// Algorithm 1, macroscopic reconstruction: limited gradients of the conservative variables
 // ------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ void cell_grad(const Params p, int i)
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_cell_grad(Params p)
 }
 
 // ------------------------------------------------------------------------
-// Alg. 1 line 3: interface equilibrium state and time coefficients
+// Algorithm 1, interface equilibrium state and time coefficients
 // ------------------------------------------------------------------------
 // Solve <psi (a . psi)>_{g} = Delta for a Maxwellian (rho-normalised
 // moments, N = 3 degrees of freedom), in closed form.
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(128) void k_face_eq(Params p)
 }
 
 // ------------------------------------------------------------------------
-// Alg. 1 lines 4-11, fused: the sweep over one cell's velocity slab
+// Algorithm 1 from the velocity loop on, fused: the sweep over one cell's velocity slab
 // ------------------------------------------------------------------------
 // Unit-density Gaussian exp(-lam |u_k - U|^2).  On a Cartesian velocity grid
 // it is the product of one-dimensional factors, tabulated in LDS once per
@@ -861,7 +861,7 @@ template <int D> __device__ __forceinline__ int has_wall_face(const Params &p, c
     return w;
 }
 
-// Alg. 1 line 9 (wall density), for a cell with a wall face: the incident
+// Algorithm 1's boundary flux (wall density), for a cell with a wall face: the incident
 // particles' mass flux and the unit-density reflected flux, summed over
 // velocities; rho_w makes the net mass flux through the wall vanish
 // (Eq. maxWalldes).  Knowing rho_w up front, the sweep adds the reflected
@@ -928,7 +928,7 @@ __device__ __forceinline__ void finish_cell(const Params &p, int i, const CellSt
     const double dt = p.dt, Pr = p.Pr;
     const size_t base = (size_t)i * NC * nv;
 
-    // Alg. 1 line 10: Eq. macroscopicUpdata, then tau at t^{n+1}
+    // Algorithm 1's macroscopic update: Eq. macroscopicUpdata, then tau at t^{n+1}
     block_reduce<BS>(mom, red, OpAdd{});
     double W1[NW];
 #pragma unroll
@@ -973,7 +973,7 @@ __device__ __forceinline__ void finish_cell(const Params &p, int i, const CellSt
         __syncthreads();
     }
 
-    // Alg. 1 line 11: Eq. microS2
+    // Algorithm 1's last step: Eq. microS2
     const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
     const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
     const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
@@ -1094,7 +1094,7 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
     }
     __syncthreads();
 
-    // Alg. 1 line 9 (wall density) first, for wall cells only: the incident
+    // Algorithm 1's boundary flux (wall density) first, for wall cells only: the incident
     // particles' mass flux and the unit-density reflected flux, summed over
     // velocities; rho_w makes the net mass flux through the wall vanish
     // (Eq. maxWalldes).  Knowing rho_w up front, the sweep below adds the
@@ -1141,7 +1141,7 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
         for (int j = 0; j < MF; ++j) rho_w[j] = (j < nf && wsum[2 * j + 1] != 0.0) ? -wsum[2 * j] / wsum[2 * j + 1] : 0.0;
     }
 
-    // Alg. 1 lines 4-8: per velocity, limited slopes, interface fluxes,
+    // Algorithm 1's velocity loop: per velocity, limited slopes, interface fluxes,
     // stage 1; the moments of the net outflow give W^{n+1}
     double mom[NW];
 #pragma unroll
@@ -1255,7 +1255,7 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
         mom[NW - 1] += wk * 0.5 * (u2 * out[0] + (NC > 1 ? out[NC - 1] : 0.0));
     }
 
-    // Alg. 1 line 10: Eq. macroscopicUpdata, then tau at t^{n+1}
+    // Algorithm 1's macroscopic update: Eq. macroscopicUpdata, then tau at t^{n+1}
     block_reduce<BS>(mom, red, OpAdd{});
     if constexpr (CHUNK) {
         // add this chunk's moments to the cell's sum; the chunks run one
@@ -1309,7 +1309,7 @@ __device__ __forceinline__ void sweep_cell(const Params p, int i, const FT *__re
         __syncthreads();
     }
 
-    // Alg. 1 line 11: Eq. microS2
+    // Algorithm 1's last step: Eq. microS2
     const double pref_1 = p1.rho * pow_lam_pi<D>(p1.lam);
     const double shk_1 = 4.0 * (1.0 - Pr) * p1.lam * p1.lam / (5.0 * p1.rho);
     const double a1 = 0.5 * dt / tau1, inv1 = 1.0 / (1.0 + a1);
@@ -1795,8 +1795,9 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
                     const double fl = sa * I[c];
                     out[c] += fl;
                     // an atomic add without return: no load waits in the
-                    // velocity loop (no other workgroup of the launch adds
-                    // to this element, so the order of the sums stays fixed)
+                    // velocity loop (in a colour launch no other workgroup
+                    // adds to this element, so the order of the sums stays
+                    // fixed; the one-class unordered sweep gives that up)
                     unsafeAtomicAdd(an + (size_t)c * accv + (k - k0), from_f64<FT>(fl * vn_inv));
                 }
             } else {

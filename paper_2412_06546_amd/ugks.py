@@ -23,8 +23,9 @@ UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE = 0, 1
 _MEM = {"two-buffers": UGKS_MEM_TWO_BUFFERS, "in-place": UGKS_MEM_IN_PLACE}
 UGKS_DEFAULT_CHUNK = 1024
 UGKS_STATIC_BATCH_MAX = 64
-UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH = 0, 1, 2
-_SWEEP = {"auto": UGKS_SWEEP_AUTO, "gather": UGKS_SWEEP_GATHER, "push": UGKS_SWEEP_PUSH}
+UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH, UGKS_SWEEP_PUSH_UNORDERED = 0, 1, 2, 3
+_SWEEP = {"auto": UGKS_SWEEP_AUTO, "gather": UGKS_SWEEP_GATHER, "push": UGKS_SWEEP_PUSH,
+          "push_unordered": UGKS_SWEEP_PUSH_UNORDERED}
 _ERRNAMES = {-1: "UGKS_ERR_ARG", -2: "UGKS_ERR_ALLOC", -3: "UGKS_ERR_HIP", -4: "UGKS_ERR_NONPHYSICAL",
              -5: "UGKS_ERR_STATE"}
 
@@ -205,7 +206,7 @@ class Solver:
                  sweep: str = "auto"):
         """mem: 'two-buffers' (f^n and f^{n+1} in separate buffers) or
         'in-place' (one f buffer plus a ring of `chunk` velocities per cell);
-        sweep: 'auto', 'gather' or 'push' (UGKS_SWEEP_*)."""
+        sweep: 'auto', 'gather', 'push' or 'push_unordered' (UGKS_SWEEP_*)."""
         L = self._L = load_library()
         self.dim = int(case["mesh"]["dim"])
         self.nc = len(case["mesh"]["cell_volume"])
@@ -247,8 +248,9 @@ class Solver:
 
     @property
     def sweep(self) -> str:
-        """'push' or 'gather': how this handle's steps evaluate the face fluxes."""
-        return {UGKS_SWEEP_PUSH: "push", UGKS_SWEEP_GATHER: "gather"}[self._L.ugks_sweep_kind(self._h)]
+        """'push', 'push_unordered' or 'gather': how this handle's steps evaluate the face fluxes."""
+        return {UGKS_SWEEP_PUSH: "push", UGKS_SWEEP_PUSH_UNORDERED: "push_unordered",
+                UGKS_SWEEP_GATHER: "gather"}[self._L.ugks_sweep_kind(self._h)]
 
     @property
     def n_colours(self) -> int:

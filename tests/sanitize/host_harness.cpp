@@ -239,7 +239,7 @@ int main()
     // valid inputs: every storage, memory mode and sweep, tabulated and scattered velocities
     for (int fs : {UGKS_F64, UGKS_F32, UGKS_BF16})
         for (int mem : {UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE})
-            for (int sw : {UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH}) {
+            for (int sw : {UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH, UGKS_SWEEP_PUSH_UNORDERED}) {
                 const bool push_ok = fs != UGKS_BF16;
                 const std::string tag = "fs" + std::to_string(fs) + " mem" + std::to_string(mem) + " sweep" +
                                         std::to_string(sw);
@@ -256,7 +256,7 @@ int main()
                     const ugks_mesh_t mv = c.m->view();
                     const ugks_vgrid_t vv = c.v->view();
                     const size_t est = ugks_footprint_estimate(&mv, &vv, &g);
-                    if (sw == UGKS_SWEEP_PUSH && !push_ok) {
+                    if ((sw == UGKS_SWEEP_PUSH || sw == UGKS_SWEEP_PUSH_UNORDERED) && !push_ok) {
                         expect(est == 0, std::string(c.name) + " " + tag + ": no footprint for an invalid push");
                         create_invalid(*c.m, *c.v, g, prim(*c.m), std::string(c.name) + " " + tag);
                     } else {
@@ -335,7 +335,8 @@ int main()
     bad_gas("limiter constant", [](ugks_gas_t &g) { g.limiter_k = -1.0; });
     bad_gas("memory mode", [](ugks_gas_t &g) { g.mem_mode = 5; });
     bad_gas("chunk", [](ugks_gas_t &g) { g.chunk = -2; });
-    bad_gas("sweep", [](ugks_gas_t &g) { g.sweep = 3; });
+    bad_gas("sweep", [](ugks_gas_t &g) { g.sweep = 4; });
+    bad_gas("negative sweep", [](ugks_gas_t &g) { g.sweep = -1; });
     bad_gas("boundary rows missing", [](ugks_gas_t &g) { g.n_bc = 2; });
 
     // the static batch refuses before touching the device

@@ -1,5 +1,6 @@
 """Host-side logic of bench.py (no GPU): the one-GPU contract, the gate that
-reports measured HBM traffic only for the kernel source it was measured on,
+reports measured HBM traffic only for the kernel source and sweep it was
+measured on,
 and the algorithmic flop counts the roofline divides by."""
 import os
 import subprocess
@@ -26,6 +27,11 @@ def test_traffic_is_reported_only_for_the_measured_kernel_source(tmp_path):
                  "traffic_bytes_per_launch_f64: 12345\n")
     assert bench.measured_traffic("liftingbody", "f64", str(f)) == 12345.0
     assert bench.measured_traffic("liftingbody", "f32", str(f)) is None   # not measured for this storage
+    assert bench.measured_traffic("liftingbody", "f64", str(f), sweep="push") is None   # sweep not stated
+    f.write_text(f"kernel_source_sha256_16: {bench.kernel_source_hash()}\nsweep: push_unordered\n"
+                 "traffic_bytes_per_launch_f64: 12345\n")
+    assert bench.measured_traffic("liftingbody", "f64", str(f), sweep="push_unordered") == 12345.0
+    assert bench.measured_traffic("liftingbody", "f64", str(f), sweep="push") is None   # another sweep
     f.write_text("kernel_source_sha256_16: 0000000000000000\ntraffic_bytes_per_launch_f64: 12345\n")
     assert bench.measured_traffic("liftingbody", "f64", str(f)) is None   # the kernel changed since
     assert bench.measured_traffic("liftingbody", "f64", str(tmp_path / "missing.txt")) is None

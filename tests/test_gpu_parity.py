@@ -532,9 +532,10 @@ def test_full_size_sphere_3d():
 
 @pytest.mark.parametrize("which", ["periodic_wave", "cylinder_small", "sphere_hex", "channel3d", "box_tet"])
 def test_push_and_gather_sweeps_both_match_oracle(which):
-    """The two ways of evaluating the face fluxes (each face once by its
-    upwind cell, coloured launches: the default; or each cell gathering all
-    its faces) against the oracle on the same case: periodic triangles,
+    """The ways of evaluating the face fluxes (each face once by its upwind
+    cell, in coloured launches -- the default -- or in one launch of all
+    cells in stored order; or each cell gathering all its faces) against the
+    oracle on the same case: periodic triangles,
     the cylinder cut-down (wall, far field, triangles), a hexahedral
     sphere shell, the 3D channel with a sliding wall, periodic tetrahedra."""
     ugks = _gpu()
@@ -546,9 +547,10 @@ def test_push_and_gather_sweeps_both_match_oracle(which):
     steps = 8
     o = oracle.Oracle(c)
     o.step(steps)
-    for sweep in ("push", "gather"):
+    for sweep in ("push", "push_unordered", "gather"):
         _say(f"case {c['name']}: {sweep} sweep, fp64, {steps} steps")
         s = ugks.Solver(c, sweep=sweep)
+        assert s.sweep == sweep
         s.step(steps)
         _compare(s, o)
         s.close()
@@ -627,7 +629,37 @@ def test_lifting_body_cut_down_100k_fp64():
     _compare(s, o)
 
 
-def test_full_size_lifting_body_conserves_mass():
+def test_unordered_push_agrees_with_the_colour_launches():
+    """The unordered push sweep (every cell in one launch; the adds into a
+    stage-1 value come in no fixed order) against the coloured push sweep on
+    the 107,118-cell lifting body with its full 4,548-point velocity set, in
+    FP64 and FP32 f: the two differ only in the order of each value's sum
+    of at most seven terms, so they agree to a few units of rounding; after
+    one step the FP64 state also agrees with the oracle's on every cell."""
+    ugks = _gpu()
+    c = cases.case_lifting_body(n=16, n_r=66, n_prism_columns=87)
+    for fs, tol in (("f64", 1e-13), ("f32", 1e-5)):
+        _say(f"case {c['name']}: unordered and coloured push, {fs}, 3 steps")
+        a, b = ugks.Solver(c, fstore=fs, sweep="push"), ugks.Solver(c, fstore=fs, sweep="push_unordered")
+        assert b.sweep == "push_unordered" and b.n_colours == 1 and a.n_colours > 1
+        a.step(3)
+        b.step(3)
+        Wa, qa = a.macros()
+        Wb, qb = b.macros()
+        eW, eq = macro_rel_err(Wb, qb, Wa, qa)
+        ef = f_rel_err(b.f(), a.f())
+        _say(f"    unordered vs coloured: W {eW:.2e} q {eq:.2e} f {ef:.2e}")
+        assert eW <= tol and eq <= tol * 100 and ef <= tol * 100, (fs, eW, eq, ef)
+        a.close()
+        b.close()
+    s, o = ugks.Solver(c, sweep="push_unordered"), oracle.Oracle(c)
+    s.step(1)
+    o.step(1)
+    _compare(s, o)
+
+
+@pytest.mark.parametrize("sweep", ["push", "push_unordered"])
+def test_full_size_lifting_body_conserves_mass(sweep):
     """The X38-sized case at its full size (1,058,685 hexahedra and prisms x
     4,548 unstructured velocities, 77 GB of f in FP64), closed: the far field
     is a resting wall at T_inf and the body a wall at 5.39 T_inf, gas at
@@ -636,9 +668,10 @@ def test_full_size_lifting_body_conserves_mass():
     total mass is conserved to round-off."""
     ugks = _gpu()
     c = cases.case_lifting_body(closed=True, start="rest")
-    _say(f"case {c['name']}: full size, closed, fp64, 3 steps")
+    _say(f"case {c['name']}: full size, closed, fp64, {sweep} sweep, 3 steps")
     vol = c["mesh"]["cell_volume"]
-    s = ugks.Solver(c)
+    s = ugks.Solver(c, sweep=sweep)
+    assert s.sweep == sweep
     W0, _ = s.macros()
     m0 = (W0[:, 0] * vol).sum()
     s.step(3)
@@ -740,7 +773,7 @@ def test_2d_unstructured_velocity_set_fp64():
     _compare(s, o)
 
 
-@pytest.mark.parametrize("sweep", ["push", "gather"])
+@pytest.mark.parametrize("sweep", ["push", "push_unordered", "gather"])
 @pytest.mark.parametrize("name,chunk", [("periodic wave", 0), ("periodic wave", 100), ("periodic wave", 5000),
                                         ("periodic wave", 1), ("cylinder cut-down", 0), ("cylinder cut-down", 96),
                                         ("3D channel", 64), ("3D channel", 1), ("scattered velocities", 10),

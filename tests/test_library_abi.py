@@ -150,7 +150,7 @@ def test_in_place_footprint_is_one_f_plus_the_ring(dim):
     # beyond one f and the ring: gather -- the moment sum and the wall
     # densities; push -- also the colour lists, the face -> wall ordinal and
     # the running moments about U^n: a few tens of doubles per cell at most
-    for sweep, per_cell in (("gather", 16), ("push", 28)):
+    for sweep, per_cell in (("gather", 16), ("push", 28), ("push_unordered", 28)):
         one = {ch: ugks.footprint_estimate(c, "f64", "in-place", ch, sweep=sweep) for ch in (1, 2, nv, 10 * nv)}
         assert one[1] < one[2] < one[nv] == one[10 * nv]
         assert one[1] < two
@@ -159,3 +159,18 @@ def test_in_place_footprint_is_one_f_plus_the_ring(dim):
         # the ring is the only part that grows with the chunk
         ring_growth = nc * ncomp * (nv - 1) * 8
         assert ring_growth <= one[nv] - one[1] <= ring_growth + 4096
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_unordered_push_allocates_what_the_push_sweep_does(dim):
+    """The unordered push sweep keeps the push sweep's buffers (its one class
+    lists every cell, as the colour lists do) and, like it, refuses BF16 f
+    (no footprint for a handle that cannot be created)."""
+    from paper_2412_06546_amd import cases, ugks
+    c = cases.case_periodic_wave() if dim == 2 else cases.case_channel_3d(n=3, kind="prism", nv=8)
+    for fs in ("f64", "f32"):
+        for mem in ("two-buffers", "in-place"):
+            a = ugks.footprint_estimate(c, fs, mem, sweep="push")
+            b = ugks.footprint_estimate(c, fs, mem, sweep="push_unordered")
+            assert a == b > 0, (fs, mem)
+    assert ugks.footprint_estimate(c, "bf16", "two-buffers", sweep="push_unordered") == 0

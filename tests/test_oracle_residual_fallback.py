@@ -6,7 +6,7 @@ norm over cells of W^{n+1} - W^n (the convergence measure of a run to steady
 state).  Here it is recomputed by definition from two reads of W around one
 step.
 
-The macroscopic reconstruction (Alg. 1 line 2) drops a cell's gradient of W
+The macroscopic reconstruction (Algorithm 1) drops a cell's gradient of W
 to zero when its limited reconstruction at one of its face centroids has
 rho <= 0 or a non-positive internal energy.  A cold gas with a strong
 velocity wave triggers it: the limiter bounds each conservative component
