@@ -658,6 +658,60 @@ def test_unordered_push_agrees_with_the_colour_launches():
     _compare(s, o)
 
 
+@pytest.mark.parametrize("sweep", ["push_unordered", "push"])
+def test_full_size_lifting_body_matches_the_oracle_on_sampled_cells(sweep):
+    """The benchmarked case at its full size (1,058,685 hexahedra and prisms
+    x 4,548 velocities, FP64, the bench's unordered push sweep, and the
+    coloured one): one step on the GPU, then the oracle on the cells within
+    two faces of sampled cells, with the GPU's time step, which gives those
+    cells exactly the full mesh's step (tests/patches.py, pinned on the CPU
+    in tests/test_patches.py).  Sampled: first-layer wall cells on the
+    windward and leeward sides, prisms at the poles, far-field cells and
+    seeded interior cells.  W, q and f of the sampled cells to 1e-12."""
+    ugks = _gpu()
+    from patches import patch_case
+    c = cases.case_lifting_body()
+    m = c["mesh"]
+    nc = len(m["cell_volume"])
+    fcl, fb = np.asarray(m["face_cells"]), np.asarray(m["face_bc"])
+    nfaces = np.bincount(np.concatenate([fcl[:, 0], fcl[fcl[:, 1] >= 0, 1]]), minlength=nc)
+    wall = np.unique(fcl[fb == cases.BC_WALL, 0])
+    far = np.unique(fcl[(fb == cases.BC_INFLOW) | (fb == cases.BC_OUTFLOW), 0])
+    prisms = np.nonzero(nfaces == 5)[0]
+    x = np.asarray(m["cell_centroid"])
+    rng = np.random.default_rng(7)
+    centres = [int(wall[np.argmin(x[wall, 2])]), int(wall[np.argmax(x[wall, 2])]), int(wall[len(wall) // 3]),
+               int(prisms[0]), int(prisms[-1]), int(far[0]), int(far[len(far) // 2])]
+    centres += [int(v) for v in rng.choice(nc, 5, replace=False)]
+    centres = list(dict.fromkeys(centres))
+    _say(f"case {c['name']}: full size, {sweep} sweep, 1 step; oracle on patches around cells {centres}")
+    s = ugks.Solver(c, sweep=sweep)
+    assert s.sweep == sweep
+    dt = s.dt
+    s.step(1)
+    Wg, qg = s.macros()
+    Wg, qg = Wg[centres], qg[centres]
+    fg = s.f()[centres] if sweep == "push_unordered" else None
+    s.close()
+    p, cells = patch_case(c, centres, dt)
+    _say(f"    patch of {len(cells)} cells")
+    o = oracle.Oracle(p)
+    assert o.dt == dt
+    W0, _ = o.macros()
+    o.step(1)
+    Wo, qo = o.macros()
+    k = len(centres)
+    eW, eq = macro_rel_err(Wg, qg, Wo[:k], qo[:k])
+    out = {"W": eW, "q": eq}
+    if fg is not None:
+        out["f"] = f_rel_err(fg, o.f()[:k])
+    _say(f"    rel err {out}")
+    for key, v in out.items():
+        assert v <= TOL, (key, v)
+    # the step moves the sampled cells (the comparison is not of initial states)
+    assert np.abs(Wo[:k] - W0[:k]).max() > 1e-6 * np.abs(W0[:k]).max()
+
+
 @pytest.mark.parametrize("sweep", ["push", "push_unordered"])
 def test_full_size_lifting_body_conserves_mass(sweep):
     """The X38-sized case at its full size (1,058,685 hexahedra and prisms x
