@@ -38,17 +38,29 @@ def test_traffic_is_reported_only_for_the_measured_kernel_source(tmp_path):
     assert bench.measured_traffic("sphere", "f64") is None                # no profile for this workload
 
 
-def test_roofline_is_priced_on_hbm_with_the_alu_figure_beside_it():
+def test_roofline_bound_is_the_roof_with_the_longer_least_time():
+    """The bound is whichever roof gives the longer least time for the
+    sweep: the vector ALUs when the method's flops per byte exceed the FP64
+    ridge of 9.8 (2D FP64 f: about 407 flops per 32 B), HBM below it (the
+    same flops over 4x the bytes); both figures are reported beside."""
     from paper_2412_06546_amd import cases
     c = cases.case_periodic_wave(nx=6, ny=4, nv=4)
     nc, nv = 20000, 3600
-    run = dict(nc=nc, nv=nv, sweep_ms_avg=3.0, achieved_gbs=nc * nv * 32 / 3e-3 / 1e9, bytes_per_update=32,
-               alg_bytes=nc * nv * 32)
-    r = bench.roofline_of(c, run, "cylinder", "f64", "in-place")
-    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
-    assert r["frac"] == pytest.approx(768.0 / 8000.0, abs=1e-4) and r["traffic"] is None
-    assert r["alu"]["unit"] == "TFLOP/s" and r["alu"]["peak"] == 78.6
-    assert r["alu"]["achieved"] == pytest.approx(r["alu"]["alg_flops_per_update"] * nc * nv / 3e-3 / 1e12, rel=1e-3)
+    fpu = bench.alg_flops_per_update(2, bench.mean_faces_per_cell(c))
+    for bpu, bound in ((32, "alu"), (128, "hbm")):
+        run = dict(nc=nc, nv=nv, sweep_ms_avg=3.0, achieved_gbs=nc * nv * bpu / 3e-3 / 1e9, bytes_per_update=bpu,
+                   alg_bytes=nc * nv * bpu)
+        assert (fpu / bpu > 78.6e12 / 8e12) == (bound == "alu")
+        r = bench.roofline_of(c, run, "cylinder", "f64", "in-place")
+        assert r["bound"] == bound and r["traffic"] is None
+        assert r["hbm"]["unit"] == "GB/s" and r["hbm"]["peak"] == 8000.0
+        assert r["hbm"]["frac"] == pytest.approx(nc * nv * bpu / 3e-3 / 1e9 / 8000.0, abs=1e-4)
+        assert r["alu"]["unit"] == "TFLOP/s" and r["alu"]["peak"] == 78.6
+        assert r["alu"]["achieved"] == pytest.approx(fpu * nc * nv / 3e-3 / 1e12, rel=1e-3)
+        top = r[bound]
+        assert (r["achieved"], r["peak"], r["unit"], r["frac"]) == (top["achieved"], top["peak"], top["unit"],
+                                                                    top["frac"])
+        assert r["least_ms"][bound] >= max(r["least_ms"].values())
 
 
 @pytest.mark.parametrize("dim,nf,expected", [(2, 3.9, 407.1), (3, 4.0, 267.0), (3, 6.0, 368.0)])
