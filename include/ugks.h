@@ -120,7 +120,9 @@ typedef struct {
  * each flux to the stage-1 values of both of its cells (the second f buffer
  * holds them; in the in-place mode a ring of one velocity chunk does, chunk
  * after chunk), and a final kernel forms W^{n+1}, q^{n+1} and stage 2.
- * Needs FP64 or FP32 f.
+ * Needs FP64 or FP32 f, or BF16 f in two buffers when asked for explicitly:
+ * its second buffer then holds FP32 stage-1 sums (6 bytes per value in all,
+ * against the gather sweep's 4), and such a handle cannot be batched.
  * UGKS_SWEEP_PUSH_UNORDERED: the push sweep with every cell in one launch,
  * in stored (space-filling-curve) order, so that neighbours run close
  * together and their f and stage-1 values are found in cache.  Several
@@ -128,21 +130,25 @@ typedef struct {
  * are atomic, so the sum is complete, but its order, and so its rounding,
  * can differ from run to run: results agree with the other sweeps to
  * rounding, not bit for bit, and a restart from a checkpoint is not
- * bitwise.  Needs FP64 or FP32 f; never chosen automatically.
+ * bitwise.  Same storage rules as UGKS_SWEEP_PUSH; never chosen
+ * automatically.
  * UGKS_SWEEP_GATHER: one workgroup per cell evaluates every face of its cell,
  * rebuilding the upwind neighbour's limited slope where needed (each
- * interior face twice); BF16 f and batched steps use it.
- * UGKS_SWEEP_AUTO (0): push where it applies, except 2D with FP64 f in two
- * buffers (there gathering measured faster on MI355X); else gather.  Both
- * give the same results up to the order of sums; ugks_sweep_kind tells which
- * a handle uses. */
+ * interior face twice); BF16 f (unless a push is asked for) and batched
+ * steps use it.
+ * UGKS_SWEEP_AUTO (0): push for FP64 and FP32 f, except 2D with FP64 f in
+ * two buffers (there gathering measured faster on MI355X); gather for BF16
+ * f.  All give the same results up to the order of sums (BF16 f: and the
+ * precision of the stage-1 sums); ugks_sweep_kind tells which a handle
+ * uses. */
 #define UGKS_SWEEP_AUTO 0
 #define UGKS_SWEEP_GATHER 1
 #define UGKS_SWEEP_PUSH 2
 #define UGKS_SWEEP_PUSH_UNORDERED 3
 
 /* Storage of f.  UGKS_MEM_TWO_BUFFERS: f^n is read from one buffer and
- * f^{n+1} written to the other (2 f of memory; the fastest form).
+ * f^{n+1} written to the other (2 f of memory, the second in FP32 when BF16
+ * f takes the push sweep; the fastest form).
  * UGKS_MEM_IN_PLACE: one buffer, updated in place as in the paper's
  * two-stage form (Section 3.2): the velocities are swept in chunks, the
  * stage-1 values of a chunk wait in a ring of n_cells x n_comp x chunk

@@ -519,11 +519,17 @@ int nchunk_of(int chunk, int nv) { return (nv + chunk - 1) / chunk; }
 // gathering is faster on MI355X (2D hypersonic cylinder, 20,000 cells x
 // 3,600 velocities: 3.2 against 4.2 ms per step; FP32 f 2.7 push against 2.9
 // gather; the 3D lifting body 178 push against 295 ms gather in FP64).
-bool push_applies(const ugks_gas_t *gas) { return gas->fstore != UGKS_BF16; }
+// BF16 f pushes only in two buffers and only when asked: its accumulator is
+// an FP32 second buffer (6 bytes per value against the gather sweep's 4).
+bool push_applies(const ugks_gas_t *gas)
+{
+    return gas->fstore != UGKS_BF16 || gas->mem_mode == UGKS_MEM_TWO_BUFFERS;
+}
 bool asks_push(const ugks_gas_t *gas) { return gas->sweep == UGKS_SWEEP_PUSH || gas->sweep == UGKS_SWEEP_PUSH_UNORDERED; }
 bool uses_push(int dim, const ugks_gas_t *gas)
 {
     if (!push_applies(gas) || gas->sweep == UGKS_SWEEP_GATHER) return false;
+    if (gas->fstore == UGKS_BF16) return asks_push(gas);
     if (asks_push(gas) || gas->mem_mode == UGKS_MEM_IN_PLACE) return true;
     return !(dim == 2 && gas->fstore == UGKS_F64);
 }
@@ -545,8 +551,8 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
         b += nc * ncomp * nv * fvalue_bytes(fstore);                      // f
         b += nbytes<char>(nc * ncomp * (size_t)ch * fvalue_bytes(fstore));  // ring
         b += nbytes<double>(nc * (size_t)NW) + nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
-    } else {
-        b += 2 * nc * ncomp * nv * fvalue_bytes(fstore);
+    } else {  // f, and the second buffer (FP32 stage-1 sums when BF16 f pushes)
+        b += nc * ncomp * nv * (fvalue_bytes(fstore) + (push && fstore == UGKS_BF16 ? 4 : fvalue_bytes(fstore)));
     }
     if (push) {  // colour lists, wall cells, face -> wall ordinal
         b += nbytes<int>(nc) + nbytes<int>(nwallf) + nbytes<int>(nf);
@@ -650,7 +656,8 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (gas->sweep < UGKS_SWEEP_AUTO || gas->sweep > UGKS_SWEEP_PUSH_UNORDERED)
             throw Fail{UGKS_ERR_ARG,
                        "sweep must be UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH or UGKS_SWEEP_PUSH_UNORDERED"};
-        if (asks_push(gas) && !push_applies(gas)) throw Fail{UGKS_ERR_ARG, "the push sweep needs FP64 or FP32 f"};
+        if (asks_push(gas) && !push_applies(gas))
+            throw Fail{UGKS_ERR_ARG, "the push sweep needs FP64 or FP32 f, or BF16 f in two buffers"};
         h->push = uses_push(D, gas) ? 1 : 0;
         h->unordered = gas->sweep == UGKS_SWEEP_PUSH_UNORDERED ? 1 : 0;
         for (int k = 0; k < vgrid->n_vel; ++k) {
@@ -741,9 +748,12 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         const size_t fbytes = nc * h->ncomp * nv * fvalue_bytes(h->fstore);
         h->mem_mode = gas->mem_mode;
         for (int b = 0; b < (h->mem_mode == UGKS_MEM_IN_PLACE ? 1 : 2); ++b) {
-            if (hipMalloc(&h->f[b], fbytes) != hipSuccess)
-                throw Fail{UGKS_ERR_ALLOC, "hipMalloc of f (" + std::to_string(fbytes) + " bytes) failed"};
-            h->bytes += fbytes;
+            // the push sweep of BF16 f keeps FP32 stage-1 sums in the second
+            // buffer (f stays in the first: push steps never swap them)
+            const size_t nb = b == 1 && h->push && h->fstore == UGKS_BF16 ? nc * h->ncomp * nv * sizeof(float) : fbytes;
+            if (hipMalloc(&h->f[b], nb) != hipSuccess)
+                throw Fail{UGKS_ERR_ALLOC, "hipMalloc of f (" + std::to_string(nb) + " bytes) failed"};
+            h->bytes += nb;
         }
         int chunk = 0, nchunk = 0;
         if (h->mem_mode == UGKS_MEM_IN_PLACE) {
@@ -1338,7 +1348,7 @@ struct SweepGroup {
 constexpr int kMaxSweepGroups = 12;  // storage (3) x per-axis tables (2) x stage-1 place (2)
 
 // Checks of a batch: NULL, stream, dimension, pending steps, memory mode,
-// duplicates.  0 or an error code, with the reason in why (static text).
+// BF16 push handles (whose two buffers differ in size), duplicates.  0 or an error code, with the reason in why (static text).
 int batch_check(ugks_t *const *hs, int n, hipStream_t stream, const char **why)
 {
     const int D = hs[0] ? hs[0]->dim : 0;
@@ -1349,6 +1359,8 @@ int batch_check(ugks_t *const *hs, int n, hipStream_t stream, const char **why)
         if (h->dim != D) return *why = "cases of one batch must have the same dimension", UGKS_ERR_ARG;
         if (h->pending) return *why = "a handle still has asynchronous steps outstanding", UGKS_ERR_STATE;
         if (h->mem_mode == UGKS_MEM_IN_PLACE) return *why = "in-place handles cannot be batched", UGKS_ERR_ARG;
+        if (h->push && h->fstore == UGKS_BF16)
+            return *why = "BF16 handles with the push sweep cannot be batched (FP32 stage-1 sums)", UGKS_ERR_ARG;
         if (!h->h_err) return *why = "handle without its pinned status copies", UGKS_ERR_STATE;
         for (int e = 0; e < c; ++e)
             if (hs[e] == h) return *why = "a handle appears twice in the batch", UGKS_ERR_ARG;

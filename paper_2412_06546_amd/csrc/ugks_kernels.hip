@@ -1496,6 +1496,27 @@ template <typename FT> __device__ __forceinline__ void store2(FT *__restrict__ q
     v.y = b;
     *reinterpret_cast<typename Vec2<FT>::T *>(q) = v;
 }
+// bfloat16 pairs: one 32-bit word, the first value in its lower half
+template <> __device__ __forceinline__ void load2<bf16s>(const bf16s *__restrict__ q, double &a, double &b)
+{
+    const unsigned v = *reinterpret_cast<const unsigned *>(q);
+    a = to_f64(bf16s{(unsigned short)(v & 0xffffu)});
+    b = to_f64(bf16s{(unsigned short)(v >> 16)});
+}
+template <> __device__ __forceinline__ void store2<bf16s>(bf16s *__restrict__ q, bf16s a, bf16s b)
+{
+    *reinterpret_cast<unsigned *>(q) = (unsigned)a.bits | ((unsigned)b.bits << 16);
+}
+
+// The push sweep's accumulator (the stage-1 sums) is kept in f's storage
+// type, except with bfloat16 f: there it holds FP32, since a bfloat16 sum
+// would round away most of every flux added to it.
+template <typename FT> struct AccOf {
+    using T = FT;
+};
+template <> struct AccOf<bf16s> {
+    using T = float;
+};
 
 // velocity k's components of the velocity set
 template <int D>
@@ -1570,8 +1591,9 @@ constexpr int kPushCellsPerGroup = 4;
 // V2: velocities in pairs (even velocity count).  Same lane order and
 // arithmetic as the final kernel's second pass, so both give the same bits.
 template <int D, typename FT, bool TENSOR, bool V2>
-__global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restrict__ fin, FT *__restrict__ acc)
+__global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restrict__ fin, typename AccOf<FT>::T *__restrict__ acc)
 {
+    using AT = typename AccOf<FT>::T;
     constexpr int NC = Dim<D>::NC, NW = D + 2, VW = V2 ? 2 : 1;
     extern __shared__ double smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1595,7 +1617,7 @@ __global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restric
             else
                 f[0][c] = to_f64(fin[base + (size_t)c * nv + k0]);
         }
-        FT sv[VW][2];
+        AT sv[VW][2];
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int k = k0 + e;
@@ -1608,7 +1630,7 @@ __global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restric
             double bv[2] = {0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                sv[e][c] = from_f64<FT>(fma(cs.hdt_tau, fp[c] - f[e][c], f[e][c]));
+                sv[e][c] = from_f64<AT>(fma(cs.hdt_tau, fp[c] - f[e][c], f[e][c]));
                 bv[c] = to_f64(sv[e][c]);
             }
             add_moments<D>(mom, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
@@ -1616,7 +1638,7 @@ __global__ __launch_bounds__(256) void k_push_base(Params p, const FT *__restric
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if constexpr (V2)
-                store2<FT>(acc + base + (size_t)c * nv + k0, sv[0][c], sv[1][c]);
+                store2<AT>(acc + base + (size_t)c * nv + k0, sv[0][c], sv[1][c]);
             else
                 acc[base + (size_t)c * nv + k0] = sv[0][c];
         }
@@ -1713,9 +1735,10 @@ __device__ __forceinline__ void push_wall(const Params &p, const CellGeo<D> &gi,
 // the XCDs in runs as for the gather sweep.  PF: the own stencil of the
 // next velocity is loaded one iteration ahead.
 template <int D, typename FT, int BS, bool TENSOR, bool PF>
-__device__ __forceinline__ void push_cell(const Params p, int i, const FT *__restrict__ fin, FT *__restrict__ acc,
-                                          int k0, int kn, int accv)
+__device__ __forceinline__ void push_cell(const Params p, int i, const FT *__restrict__ fin,
+                                          typename AccOf<FT>::T *__restrict__ acc, int k0, int kn, int accv)
 {
+    using AT = typename AccOf<FT>::T;
     constexpr int NC = Dim<D>::NC, MF = Dim<D>::MF, NT = MF + 1;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
@@ -1774,7 +1797,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
             const double uo = gi.side[j] ? -un : un;  // along this cell's outward normal
             if (F.bc == 0) {
                 if (!(uo > 0.0)) continue;  // the neighbour is upwind: it adds this flux
-                FT *an = acc + (size_t)gi.nb[j] * NC * accv;
+                AT *an = acc + (size_t)gi.nb[j] * NC * accv;
                 double val[NC], ug[NC], I[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -1798,7 +1821,7 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
                     // velocity loop (in a colour launch no other workgroup
                     // adds to this element, so the order of the sums stays
                     // fixed; the one-class unordered sweep gives that up)
-                    unsafeAtomicAdd(an + (size_t)c * accv + (k - k0), from_f64<FT>(fl * vn_inv));
+                    unsafeAtomicAdd(an + (size_t)c * accv + (k - k0), from_f64<AT>(fl * vn_inv));
                 }
             } else {
                 double I[NC];
@@ -1827,8 +1850,8 @@ __device__ __forceinline__ void push_cell(const Params p, int i, const FT *__res
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            FT *a = acc + base + (size_t)c * accv + (k - k0);
-            unsafeAtomicAdd(a, from_f64<FT>(-out[c] * gi.inv_vol));
+            AT *a = acc + base + (size_t)c * accv + (k - k0);
+            unsafeAtomicAdd(a, from_f64<AT>(-out[c] * gi.inv_vol));
         }
     }
 }
@@ -1857,7 +1880,7 @@ __global__ __launch_bounds__(BS) void k_push_wall(Params p, const FT *__restrict
 }
 
 template <int D, typename FT, int BS, bool TENSOR>
-__global__ __launch_bounds__(BS) void k_push(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
+__global__ __launch_bounds__(BS) void k_push(Params p, const FT *__restrict__ fin, typename AccOf<FT>::T *__restrict__ acc,
                                              const int *__restrict__ cells, int ncell, int k0, int kn, int accv,
                                              int ksplit)
 {
@@ -1873,7 +1896,7 @@ __global__ __launch_bounds__(BS) void k_push(Params p, const FT *__restrict__ fi
 // (3D: held to 6 waves per SIMD, which fits without spills and measured 2 %
 // faster than the 5 the compiler chooses; 2D would spill)
 template <int D, typename FT, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(D == 3 ? 6 : 1))) void k_push_pf(Params p, const FT *__restrict__ fin, FT *__restrict__ acc,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(D == 3 ? 6 : 1))) void k_push_pf(Params p, const FT *__restrict__ fin, typename AccOf<FT>::T *__restrict__ acc,
                                                 const int *__restrict__ cells, int ncell, int k0, int kn, int accv,
                                                 int ksplit)
 {
@@ -1914,8 +1937,9 @@ template <int D> constexpr int sym_index(int a, int b)
 }
 
 template <int D, typename FT, bool TENSOR, bool V2>
-__global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ fout, FT *__restrict__ acc)
+__global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ fout, typename AccOf<FT>::T *__restrict__ acc)
 {
+    using AT = typename AccOf<FT>::T;
     constexpr int NC = Dim<D>::NC, NW = D + 2, VW = V2 ? 2 : 1, NM = D * (D + 1) / 2;
     extern __shared__ double smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1941,7 +1965,7 @@ __global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ f
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if constexpr (V2)
-                load2<FT>(acc + base + (size_t)c * nv + k0, v[0][c], v[1][c]);
+                load2<AT>(acc + base + (size_t)c * nv + k0, v[0][c], v[1][c]);
             else
                 v[0][c] = to_f64(acc[base + (size_t)c * nv + k0]);
         }
@@ -2037,11 +2061,12 @@ __global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ f
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if constexpr (V2)
-                load2<FT>(acc + base + (size_t)c * nv + k0, sv[0][c], sv[1][c]);
+                load2<AT>(acc + base + (size_t)c * nv + k0, sv[0][c], sv[1][c]);
             else
                 sv[0][c] = to_f64(acc[base + (size_t)c * nv + k0]);
         }
-        FT fo[VW][2], bo[VW][2];
+        FT fo[VW][2];
+        AT bo[VW][2];
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int k = k0 + e;
@@ -2058,7 +2083,7 @@ __global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ f
                 // the base from f^{n+1} as stored (bitwise what the base
                 // kernel computes from it after a restart)
                 const double fd = opaque(to_f64(fo[e][c]));
-                bo[e][c] = from_f64<FT>(fma(a1, fp[c] - fd, fd));
+                bo[e][c] = from_f64<AT>(fma(a1, fp[c] - fd, fd));
                 bv[c] = to_f64(bo[e][c]);
             }
             add_moments<D>(mb, p.w[k], u, u2, bv[0], NC > 1 ? bv[NC - 1] : 0.0);
@@ -2067,7 +2092,7 @@ __global__ __launch_bounds__(256) void k_push_final(Params p, FT *__restrict__ f
         for (int c = 0; c < NC; ++c) {
             if constexpr (V2) {
                 store2<FT>(fout + base + (size_t)c * nv + k0, fo[0][c], fo[1][c]);
-                store2<FT>(acc + base + (size_t)c * nv + k0, bo[0][c], bo[1][c]);
+                store2<AT>(acc + base + (size_t)c * nv + k0, bo[0][c], bo[1][c]);
             } else {
                 fout[base + (size_t)c * nv + k0] = fo[0][c];
                 acc[base + (size_t)c * nv + k0] = bo[0][c];
@@ -2906,8 +2931,10 @@ hipError_t push_t(const Params &p, void *fv, void *av, bool need_base, const int
                   const int *wall_cells, int n_wall_cells, hipStream_t s)
 {
     constexpr int MF = Dim<D>::MF, NW = D + 2, NC = Dim<D>::NC, BS = 256;
+    using AT = typename AccOf<FT>::T;
     const FT *fin = static_cast<const FT *>(fv);
-    FT *f = static_cast<FT *>(fv), *acc = static_cast<FT *>(av);
+    FT *f = static_cast<FT *>(fv);
+    AT *acc = static_cast<AT *>(av);
     const size_t tab = sizeof(double) * (size_t)(MF + 1) * (TENSOR ? p.ntab : 0);
     const size_t red = sizeof(double) * ((BS / 64) * (2 * NW + 2) + MF);
     const unsigned gc = (unsigned)sweep_grid(p.nc);
@@ -3042,12 +3069,14 @@ hipError_t launch_push_inplace(const Params &p, void *f, const int *cells, const
 hipError_t launch_push_step(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff,
                             int ncol, const int *wall_cells, int n_wall_cells, hipStream_t s)
 {
-    if (p.fstore == 2) return hipErrorInvalidValue;  // bfloat16 f takes the gather sweep
+    // bfloat16 f: acc holds FP32 stage-1 sums
     if (p.dim == 2)
-        return p.fstore ? push_d<2, float>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
-                        : push_d<2, double>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s);
-    return p.fstore ? push_d<3, float>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
-                    : push_d<3, double>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s);
+        return p.fstore == 2 ? push_d<2, bf16s>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
+               : p.fstore    ? push_d<2, float>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                             : push_d<2, double>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s);
+    return p.fstore == 2 ? push_d<3, bf16s>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
+           : p.fstore    ? push_d<3, float>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                         : push_d<3, double>(p, f, acc, need_base, cells, coff, ncol, wall_cells, n_wall_cells, s);
 }
 
 // Surface quantities of Section 2.5 from the wall flux of the last step (per

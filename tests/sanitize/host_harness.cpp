@@ -240,7 +240,7 @@ int main()
     for (int fs : {UGKS_F64, UGKS_F32, UGKS_BF16})
         for (int mem : {UGKS_MEM_TWO_BUFFERS, UGKS_MEM_IN_PLACE})
             for (int sw : {UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH, UGKS_SWEEP_PUSH_UNORDERED}) {
-                const bool push_ok = fs != UGKS_BF16;
+                const bool push_ok = fs != UGKS_BF16 || mem == UGKS_MEM_TWO_BUFFERS;
                 const std::string tag = "fs" + std::to_string(fs) + " mem" + std::to_string(mem) + " sweep" +
                                         std::to_string(sw);
                 struct {

@@ -249,19 +249,21 @@ def test_set_f_restart_is_bitwise():
     assert np.array_equal(b.f(), c2.f())
 
 
-@pytest.mark.parametrize("fstore", ["f64", "f32", "bf16"])
-def test_checkpoint_restart_is_exact(fstore):
+@pytest.mark.parametrize("fstore,sweep", [("f64", "auto"), ("f32", "auto"), ("bf16", "auto"), ("bf16", "push")])
+def test_checkpoint_restart_is_exact(fstore, sweep):
     """ugks_get_state / ugks_set_state: a run saved after 6 steps and
     restarted in a fresh handle continues bit for bit as the run that was
-    never interrupted (W, q and f); a state of another case is refused."""
+    never interrupted (W, q and f); a state of another case is refused.
+    (BF16 f with the push sweep: the FP32 stage-1 base is rebuilt from the
+    restored f.)"""
     ugks = _gpu()
     c = cases.case_cylinder_small()
-    _say(f"case {c['name']}: {fstore} checkpoint after 6 of 12 steps")
-    a = ugks.Solver(c, fstore=fstore)
+    _say(f"case {c['name']}: {fstore} ({sweep} sweep) checkpoint after 6 of 12 steps")
+    a = ugks.Solver(c, fstore=fstore, sweep=sweep)
     a.step(6)
     st = a.get_state()
     a.step(6)
-    b = ugks.Solver(c, fstore=fstore)
+    b = ugks.Solver(c, fstore=fstore, sweep=sweep)
     b.set_state(st)
     assert b.step_count == 6
     b.step(6)
@@ -269,7 +271,7 @@ def test_checkpoint_restart_is_exact(fstore):
     Wb, qb = b.macros()
     assert np.array_equal(Wa, Wb) and np.array_equal(qa, qb)
     assert np.array_equal(a.f(), b.f())
-    other = ugks.Solver(cases.case_cylinder_small(n_theta=24, n_r=8, nv=20), fstore=fstore)
+    other = ugks.Solver(cases.case_cylinder_small(n_theta=24, n_r=8, nv=20), fstore=fstore, sweep=sweep)
     with pytest.raises(ugks.UgksError) as e:
         other.set_state(st)
     assert e.value.code == ugks.UGKS_ERR_ARG
@@ -358,6 +360,42 @@ def test_storage_precision_error_per_quantity(fstore, tol):
     _say(f"    {fstore}-f relative errors: rho {e['rho']:.3e}  U {e['U']:.3e}  T {e['T']:.3e}; "
          f"residual {np.array2string(rg, precision=3)}")
     assert max(e.values()) <= tol
+
+
+@pytest.mark.parametrize("which", ["cylinder_small", "sphere_hex"])
+def test_bf16_push_sweep_matches_the_oracle(which):
+    """BF16 f with the push sweep (coloured and unordered; FP32 stage-1 sums
+    in the second buffer) against the FP64 oracle after 20 steps, beside the
+    BF16 gather sweep on the same case: both within the BF16 bound, the push
+    sweep's footprint the estimate's, 2 bytes per value above the gather
+    sweep's; a BF16 push handle is refused by the batched step."""
+    ugks = _gpu()
+    c = {"cylinder_small": lambda: cases.case_cylinder_small(),
+         "sphere_hex": lambda: cases.case_sphere(n=4, n_r=8, nv=12, half_width=8.0, kind="hex")}[which]()
+    o = oracle.Oracle(c)
+    o.step(20)
+    Wo, _ = o.macros()
+    g = ugks.Solver(c, fstore="bf16")
+    assert g.sweep == "gather"
+    g.step(20)
+    eg = prim_errors(g.macros()[0], Wo)
+    _say(f"case {c['name']}: bf16 gather errors {eg}")
+    assert max(eg.values()) <= 5e-2
+    nvals = g.nc * g.ncomp * g.nv
+    for sweep in ("push", "push_unordered"):
+        s = ugks.Solver(c, fstore="bf16", sweep=sweep)
+        assert s.sweep == sweep
+        assert s.footprint_bytes == ugks.footprint_estimate(c, "bf16", sweep=sweep)
+        assert s.footprint_bytes - g.footprint_bytes >= 2 * nvals
+        s.step(20)
+        e = prim_errors(s.macros()[0], Wo)
+        _say(f"    bf16 {sweep} errors {e}")
+        assert max(e.values()) <= 5e-2
+        b = ugks.Batch(2)
+        with pytest.raises(ugks.UgksError):
+            b.step([s], 1)
+        b.close()
+        s.close()
 
 
 def test_impulsive_start_cylinder_fp64():

@@ -41,7 +41,7 @@ def test_footprint_estimate_matches_allocation():
     for c in cs:
         dim = c["mesh"]["dim"]
         for fs in ("f64", "f32", "bf16"):
-            for sw in ("auto", "gather", "push") if fs != "bf16" else ("auto", "gather"):
+            for sw in ("auto", "gather", "push"):
                 est = ugks.footprint_estimate(c, fs, sweep=sw)
                 s = ugks.Solver(c, fstore=fs, sweep=sw)
                 assert s.footprint_bytes == est, (c.get("name"), fs, sw)
@@ -50,10 +50,10 @@ def test_footprint_estimate_matches_allocation():
                 assert s.sweep == (auto if sw == "auto" else sw), (c.get("name"), fs, sw)
                 assert (s.n_colours > 0) == (s.sweep == "push")
                 s.close()
-    # the push sweep needs two buffers and FP64 or FP32 f
-    assert ugks.footprint_estimate(cs[0], "bf16", sweep="push") == 0
+    # BF16 f pushes only in two buffers
+    assert ugks.footprint_estimate(cs[0], "bf16", "in-place", sweep="push") == 0
     with pytest.raises(ugks.UgksError) as e:
-        ugks.Solver(cs[0], fstore="bf16", sweep="push")
+        ugks.Solver(cs[0], fstore="bf16", mem="in-place", sweep="push")
     assert e.value.code == ugks.UGKS_ERR_ARG
 
 

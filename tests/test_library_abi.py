@@ -164,8 +164,10 @@ def test_in_place_footprint_is_one_f_plus_the_ring(dim):
 @pytest.mark.parametrize("dim", [2, 3])
 def test_unordered_push_allocates_what_the_push_sweep_does(dim):
     """The unordered push sweep keeps the push sweep's buffers (its one class
-    lists every cell, as the colour lists do) and, like it, refuses BF16 f
-    (no footprint for a handle that cannot be created)."""
+    lists every cell, as the colour lists do).  With BF16 f both push in two
+    buffers only, the second buffer in FP32 (2 more bytes per value than the
+    gather sweep), and refuse the in-place mode (no footprint for a handle
+    that cannot be created); the automatic choice gathers BF16 f."""
     from paper_2412_06546_amd import cases, ugks
     c = cases.case_periodic_wave() if dim == 2 else cases.case_channel_3d(n=3, kind="prism", nv=8)
     for fs in ("f64", "f32"):
@@ -173,4 +175,12 @@ def test_unordered_push_allocates_what_the_push_sweep_does(dim):
             a = ugks.footprint_estimate(c, fs, mem, sweep="push")
             b = ugks.footprint_estimate(c, fs, mem, sweep="push_unordered")
             assert a == b > 0, (fs, mem)
-    assert ugks.footprint_estimate(c, "bf16", "two-buffers", sweep="push_unordered") == 0
+    nc, nv = len(c["mesh"]["cell_volume"]), len(c["vgrid"]["w"])
+    ncomp = 2 if dim == 2 else 1
+    gather = ugks.footprint_estimate(c, "bf16", "two-buffers", sweep="gather")
+    assert ugks.footprint_estimate(c, "bf16", "two-buffers") == gather
+    for sw in ("push", "push_unordered"):
+        bf = ugks.footprint_estimate(c, "bf16", "two-buffers", sweep=sw)
+        f64push = ugks.footprint_estimate(c, "f64", "two-buffers", sweep=sw)
+        assert bf == f64push - nc * ncomp * nv * (16 - 6), sw
+        assert ugks.footprint_estimate(c, "bf16", "in-place", sweep=sw) == 0
