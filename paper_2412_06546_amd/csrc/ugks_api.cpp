@@ -1348,7 +1348,8 @@ struct SweepGroup {
 constexpr int kMaxSweepGroups = 12;  // storage (3) x per-axis tables (2) x stage-1 place (2)
 
 // Checks of a batch: NULL, stream, dimension, pending steps, memory mode,
-// BF16 push handles (whose two buffers differ in size), duplicates.  0 or an error code, with the reason in why (static text).
+// BF16 push handles (whose two buffers differ in size), duplicates.  0 or
+// an error code, with the reason in why (static text).
 int batch_check(ugks_t *const *hs, int n, hipStream_t stream, const char **why)
 {
     const int D = hs[0] ? hs[0]->dim : 0;
