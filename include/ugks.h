@@ -120,9 +120,9 @@ typedef struct {
  * each flux to the stage-1 values of both of its cells (the second f buffer
  * holds them; in the in-place mode a ring of one velocity chunk does, chunk
  * after chunk), and a final kernel forms W^{n+1}, q^{n+1} and stage 2.
- * Needs FP64 or FP32 f, or BF16 f in two buffers when asked for explicitly:
- * its second buffer then holds FP32 stage-1 sums (6 bytes per value in all,
- * against the gather sweep's 4), and such a handle cannot be batched.
+ * Takes BF16 f only when asked for explicitly: its stage-1 sums (the second
+ * buffer, or the ring in place) are then FP32, 2 more bytes per value than
+ * the gather sweep keeps, and such a handle cannot be batched.
  * UGKS_SWEEP_PUSH_UNORDERED: the push sweep with every cell in one launch,
  * in stored (space-filling-curve) order, so that neighbours run close
  * together and their f and stage-1 values are found in cache.  Several
@@ -148,7 +148,7 @@ typedef struct {
 
 /* Storage of f.  UGKS_MEM_TWO_BUFFERS: f^n is read from one buffer and
  * f^{n+1} written to the other (2 f of memory, the second in FP32 when BF16
- * f takes the push sweep; the fastest form).
+ * f takes the push sweep, as is the ring in place; the fastest form).
  * UGKS_MEM_IN_PLACE: one buffer, updated in place as in the paper's
  * two-stage form (Section 3.2): the velocities are swept in chunks, the
  * stage-1 values of a chunk wait in a ring of n_cells x n_comp x chunk

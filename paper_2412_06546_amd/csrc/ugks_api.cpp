@@ -519,16 +519,12 @@ int nchunk_of(int chunk, int nv) { return (nv + chunk - 1) / chunk; }
 // gathering is faster on MI355X (2D hypersonic cylinder, 20,000 cells x
 // 3,600 velocities: 3.2 against 4.2 ms per step; FP32 f 2.7 push against 2.9
 // gather; the 3D lifting body 178 push against 295 ms gather in FP64).
-// BF16 f pushes only in two buffers and only when asked: its accumulator is
-// an FP32 second buffer (6 bytes per value against the gather sweep's 4).
-bool push_applies(const ugks_gas_t *gas)
-{
-    return gas->fstore != UGKS_BF16 || gas->mem_mode == UGKS_MEM_TWO_BUFFERS;
-}
+// BF16 f pushes only when asked: its accumulator (the second buffer, or the
+// ring in place) holds FP32 stage-1 sums, 2 more bytes per value.
 bool asks_push(const ugks_gas_t *gas) { return gas->sweep == UGKS_SWEEP_PUSH || gas->sweep == UGKS_SWEEP_PUSH_UNORDERED; }
 bool uses_push(int dim, const ugks_gas_t *gas)
 {
-    if (!push_applies(gas) || gas->sweep == UGKS_SWEEP_GATHER) return false;
+    if (gas->sweep == UGKS_SWEEP_GATHER) return false;
     if (gas->fstore == UGKS_BF16) return asks_push(gas);
     if (asks_push(gas) || gas->mem_mode == UGKS_MEM_IN_PLACE) return true;
     return !(dim == 2 && gas->fstore == UGKS_F64);
@@ -549,7 +545,7 @@ size_t plan_bytes(int D, size_t nc, size_t nf, size_t nv, int nbc, int fstore, s
     if (mem_mode == UGKS_MEM_IN_PLACE) {
         const int ch = chunk_of(chunk, (int)nv);
         b += nc * ncomp * nv * fvalue_bytes(fstore);                      // f
-        b += nbytes<char>(nc * ncomp * (size_t)ch * fvalue_bytes(fstore));  // ring
+        b += nbytes<char>(nc * ncomp * (size_t)ch * (push && fstore == UGKS_BF16 ? 4 : fvalue_bytes(fstore)));  // ring
         b += nbytes<double>(nc * (size_t)NW) + nbytes<double>(nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF));
     } else {  // f, and the second buffer (FP32 stage-1 sums when BF16 f pushes)
         b += nc * ncomp * nv * (fvalue_bytes(fstore) + (push && fstore == UGKS_BF16 ? 4 : fvalue_bytes(fstore)));
@@ -656,8 +652,6 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (gas->sweep < UGKS_SWEEP_AUTO || gas->sweep > UGKS_SWEEP_PUSH_UNORDERED)
             throw Fail{UGKS_ERR_ARG,
                        "sweep must be UGKS_SWEEP_AUTO, UGKS_SWEEP_GATHER, UGKS_SWEEP_PUSH or UGKS_SWEEP_PUSH_UNORDERED"};
-        if (asks_push(gas) && !push_applies(gas))
-            throw Fail{UGKS_ERR_ARG, "the push sweep needs FP64 or FP32 f, or BF16 f in two buffers"};
         h->push = uses_push(D, gas) ? 1 : 0;
         h->unordered = gas->sweep == UGKS_SWEEP_PUSH_UNORDERED ? 1 : 0;
         for (int k = 0; k < vgrid->n_vel; ++k) {
@@ -759,7 +753,9 @@ extern "C" int ugks_create(const ugks_mesh_t *mesh, const ugks_vgrid_t *vgrid, c
         if (h->mem_mode == UGKS_MEM_IN_PLACE) {
             chunk = chunk_of(gas->chunk, h->nv);
             nchunk = nchunk_of(chunk, h->nv);
-            h->ring = dev_alloc<char>(h, nc * h->ncomp * (size_t)chunk * fvalue_bytes(h->fstore));
+            // FP32 stage-1 sums when BF16 f takes the push sweep
+            h->ring = dev_alloc<char>(h, nc * h->ncomp * (size_t)chunk *
+                                             (h->push && h->fstore == UGKS_BF16 ? sizeof(float) : fvalue_bytes(h->fstore)));
             h->mom_part = dev_alloc<double>(h, nc * (size_t)(D + 2));
             h->rho_w = dev_alloc<double>(h, nc * (size_t)(D == 2 ? Dim<2>::MF : Dim<3>::MF));
             hip_check(hipMemsetAsync(h->rho_w, 0, sizeof(double) * nc * (D == 2 ? Dim<2>::MF : Dim<3>::MF),
@@ -977,7 +973,6 @@ extern "C" size_t ugks_footprint_estimate(const ugks_mesh_t *mesh, const ugks_vg
     size_t nwallf = 0;
     if (mesh->face_bc)
         for (int f = 0; f < mesh->n_faces; ++f) nwallf += mesh->face_bc[f] == UGKS_BC_WALL;
-    if (asks_push(gas) && !push_applies(gas)) return 0;
     return plan_bytes(mesh->dim, mesh->n_cells, mesh->n_faces, vgrid->n_vel, gas->n_bc, gas->fstore, ntab, nwallf,
                       gas->mem_mode, gas->chunk, uses_push(mesh->dim, gas));
 }

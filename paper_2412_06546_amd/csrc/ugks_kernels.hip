@@ -2791,9 +2791,11 @@ __device__ __forceinline__ void macro_from_shift(const Params &p, const double (
 // added to mom_part (a chunk index of -1 skips that half; chunk 0 starts
 // each sum).  Each cell's ring slice is touched only by its own workgroup.
 template <int D, typename FT, bool TENSOR>
-__global__ __launch_bounds__(256) void k_push_chunk_turn(Params p, FT *__restrict__ f, FT *__restrict__ ring, int pc0,
-                                                         int pcn, int pq, int nc0, int ncn, int nq)
+__global__ __launch_bounds__(256) void k_push_chunk_turn(Params p, FT *__restrict__ f,
+                                                         typename AccOf<FT>::T *__restrict__ ring, int pc0, int pcn,
+                                                         int pq, int nc0, int ncn, int nq)
 {
+    using AT = typename AccOf<FT>::T;
     constexpr int NC = Dim<D>::NC, NW = D + 2, BS = 256, N = Shift<D>::N;
     extern __shared__ double smem[];
     const int i = xcd_cell(blockIdx.x);
@@ -2813,8 +2815,13 @@ __global__ __launch_bounds__(256) void k_push_chunk_turn(Params p, FT *__restric
             double v[2] = {0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const FT x = ring[rb + (size_t)c * ch + kk];
-                f[fb + (size_t)c * nv + k] = x;
+                // the moments are taken of the stage-1 value as summed (FP32
+                // for bfloat16 f), as in the two-buffer final kernel
+                const AT x = ring[rb + (size_t)c * ch + kk];
+                if constexpr (sizeof(AT) == sizeof(FT))
+                    f[fb + (size_t)c * nv + k] = x;
+                else
+                    f[fb + (size_t)c * nv + k] = from_f64<FT>(to_f64(x));
                 v[c] = to_f64(x);
             }
             double cv[D], c2 = 0.0;
@@ -2849,7 +2856,7 @@ __global__ __launch_bounds__(256) void k_push_chunk_turn(Params p, FT *__restric
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const double fv = to_f64(f[fb + (size_t)c * nv + k]);
-                const FT sv = from_f64<FT>(fma(cs.hdt_tau, fp[c] - fv, fv));
+                const AT sv = from_f64<AT>(fma(cs.hdt_tau, fp[c] - fv, fv));
                 ring[rb + (size_t)c * ch + kk] = sv;
                 bv[c] = to_f64(sv);
             }
@@ -3010,7 +3017,9 @@ hipError_t push_inplace_t(const Params &p, void *fv, const int *cells, const int
                           const int *wall_cells, int n_wall_cells, hipStream_t s)
 {
     constexpr int MF = Dim<D>::MF, NW = D + 2, BS = 256;
-    FT *f = static_cast<FT *>(fv), *ring = static_cast<FT *>(p.ring);
+    using AT = typename AccOf<FT>::T;
+    FT *f = static_cast<FT *>(fv);
+    AT *ring = static_cast<AT *>(p.ring);
     const size_t tab = sizeof(double) * (size_t)(MF + 1) * (TENSOR ? p.ntab : 0);
     const size_t red = sizeof(double) * ((BS / 64) * (2 * NW + 2) + MF);
     const unsigned gc = (unsigned)sweep_grid(p.nc);
@@ -3058,12 +3067,14 @@ hipError_t push_inplace_d(const Params &p, void *f, const int *cells, const int 
 hipError_t launch_push_inplace(const Params &p, void *f, const int *cells, const int *coff, int ncol,
                                const int *wall_cells, int n_wall_cells, hipStream_t s)
 {
-    if (p.fstore == 2) return hipErrorInvalidValue;  // bfloat16 f takes the gather sweep
+    // bfloat16 f: the ring holds FP32 stage-1 sums
     if (p.dim == 2)
-        return p.fstore ? push_inplace_d<2, float>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
-                        : push_inplace_d<2, double>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s);
-    return p.fstore ? push_inplace_d<3, float>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
-                    : push_inplace_d<3, double>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s);
+        return p.fstore == 2 ? push_inplace_d<2, bf16s>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
+               : p.fstore    ? push_inplace_d<2, float>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                             : push_inplace_d<2, double>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s);
+    return p.fstore == 2 ? push_inplace_d<3, bf16s>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
+           : p.fstore    ? push_inplace_d<3, float>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s)
+                         : push_inplace_d<3, double>(p, f, cells, coff, ncol, wall_cells, n_wall_cells, s);
 }
 
 hipError_t launch_push_step(const Params &p, void *f, void *acc, bool need_base, const int *cells, const int *coff,

@@ -365,10 +365,12 @@ def test_storage_precision_error_per_quantity(fstore, tol):
 @pytest.mark.parametrize("which", ["cylinder_small", "sphere_hex"])
 def test_bf16_push_sweep_matches_the_oracle(which):
     """BF16 f with the push sweep (coloured and unordered; FP32 stage-1 sums
-    in the second buffer) against the FP64 oracle after 20 steps, beside the
-    BF16 gather sweep on the same case: both within the BF16 bound, the push
+    in the second buffer, or in the ring in place, with ragged chunks of 100
+    velocities) against the FP64 oracle after 20 steps, beside the BF16
+    gather sweep on the same case: all within the BF16 bound, the push
     sweep's footprint the estimate's, 2 bytes per value above the gather
-    sweep's; a BF16 push handle is refused by the batched step."""
+    sweep's in two buffers and below it in place; a BF16 push handle is
+    refused by the batched step."""
     ugks = _gpu()
     c = {"cylinder_small": lambda: cases.case_cylinder_small(),
          "sphere_hex": lambda: cases.case_sphere(n=4, n_r=8, nv=12, half_width=8.0, kind="hex")}[which]()
@@ -396,6 +398,15 @@ def test_bf16_push_sweep_matches_the_oracle(which):
             b.step([s], 1)
         b.close()
         s.close()
+        ip = ugks.Solver(c, fstore="bf16", mem="in-place", chunk=100, sweep=sweep)
+        assert ip.sweep == sweep
+        assert ip.footprint_bytes == ugks.footprint_estimate(c, "bf16", "in-place", 100, sweep=sweep)
+        assert ip.footprint_bytes < g.footprint_bytes
+        ip.step(20)
+        e = prim_errors(ip.macros()[0], Wo)
+        _say(f"    bf16 {sweep} in place errors {e}")
+        assert max(e.values()) <= 5e-2
+        ip.close()
 
 
 def test_impulsive_start_cylinder_fp64():

@@ -50,11 +50,11 @@ def test_footprint_estimate_matches_allocation():
                 assert s.sweep == (auto if sw == "auto" else sw), (c.get("name"), fs, sw)
                 assert (s.n_colours > 0) == (s.sweep == "push")
                 s.close()
-    # BF16 f pushes only in two buffers
-    assert ugks.footprint_estimate(cs[0], "bf16", "in-place", sweep="push") == 0
-    with pytest.raises(ugks.UgksError) as e:
-        ugks.Solver(cs[0], fstore="bf16", mem="in-place", sweep="push")
-    assert e.value.code == ugks.UGKS_ERR_ARG
+    # BF16 f pushes in place too (an FP32 ring)
+    s = ugks.Solver(cs[0], fstore="bf16", mem="in-place", sweep="push")
+    assert s.sweep == "push"
+    assert s.footprint_bytes == ugks.footprint_estimate(cs[0], "bf16", "in-place", sweep="push")
+    s.close()
 
 
 @pytest.mark.parametrize("batched", [True, False])

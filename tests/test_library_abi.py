@@ -164,10 +164,9 @@ def test_in_place_footprint_is_one_f_plus_the_ring(dim):
 @pytest.mark.parametrize("dim", [2, 3])
 def test_unordered_push_allocates_what_the_push_sweep_does(dim):
     """The unordered push sweep keeps the push sweep's buffers (its one class
-    lists every cell, as the colour lists do).  With BF16 f both push in two
-    buffers only, the second buffer in FP32 (2 more bytes per value than the
-    gather sweep), and refuse the in-place mode (no footprint for a handle
-    that cannot be created); the automatic choice gathers BF16 f."""
+    lists every cell, as the colour lists do).  With BF16 f both keep FP32
+    stage-1 sums: the second buffer in two buffers, the ring in place (2
+    more bytes per value than BF16); the automatic choice gathers BF16 f."""
     from paper_2412_06546_amd import cases, ugks
     c = cases.case_periodic_wave() if dim == 2 else cases.case_channel_3d(n=3, kind="prism", nv=8)
     for fs in ("f64", "f32"):
@@ -183,4 +182,7 @@ def test_unordered_push_allocates_what_the_push_sweep_does(dim):
         bf = ugks.footprint_estimate(c, "bf16", "two-buffers", sweep=sw)
         f64push = ugks.footprint_estimate(c, "f64", "two-buffers", sweep=sw)
         assert bf == f64push - nc * ncomp * nv * (16 - 6), sw
-        assert ugks.footprint_estimate(c, "bf16", "in-place", sweep=sw) == 0
+        ch = min(ugks.UGKS_DEFAULT_CHUNK, nv)
+        bf_ip = ugks.footprint_estimate(c, "bf16", "in-place", sweep=sw)
+        f64_ip = ugks.footprint_estimate(c, "f64", "in-place", sweep=sw)
+        assert bf_ip == f64_ip - nc * ncomp * (nv * (8 - 2) + ch * (8 - 4)), sw
