@@ -189,8 +189,6 @@ def run_gpu(case, fstore: str, steps: int, warmup: int, mem: str = "two-buffers"
     events around every sweep launch."""
     import torch
     from paper_2412_06546_amd import ugks
-    if fstore == "bf16" and mem == "in-place" and sweep in ("push", "push_unordered"):
-        sweep = "auto"          # BF16 f in place is gathered
     s = ugks.Solver(case, fstore=fstore, mem=mem, chunk=chunk, sweep=sweep)
     nc, nv, ncomp = s.nc, s.nv, s.ncomp
     if warmup:
@@ -336,7 +334,7 @@ def main():
                     help="f in two buffers (f^n, f^{n+1}) or one buffer updated in place by velocity chunks")
     ap.add_argument("--chunk", type=int, default=0, help="in-place mode: velocities per chunk (0 = the library default)")
     ap.add_argument("--sweep", choices=["auto", "gather", "push", "push_unordered"], default=DEFAULT_SWEEP,
-                    help="how the sweep evaluates the face fluxes (UGKS_SWEEP_*); BF16 f in place gathers")
+                    help="how the sweep evaluates the face fluxes (UGKS_SWEEP_*)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the coloured push, the other precisions and workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
