@@ -719,7 +719,7 @@ static void one_step(orc_t *o)
     const int D = o->D, M = o->M, N = o->N, NC = o->NC, NW = o->NW, nc = o->nc, nf = o->nf, nv = o->nv;
     const double dt = o->dt;
 
-    /* line 1: heat flux q^n is the value carried from the previous step
+    /* time step and heat flux: q^n is the value carried from the previous step
      * (direct moment of f at the start); collision time tau^n */
     double *prim = (double *)malloc(sizeof(double) * nc * NW);
     double *tau = (double *)malloc(sizeof(double) * nc);
@@ -728,11 +728,11 @@ static void one_step(orc_t *o)
         tau[i] = tau_of_prim(o, prim + (size_t)i * NW);
     }
 
-    /* line 2: limited gradients of the conservative variables */
+    /* macroscopic reconstruction: limited gradients of the conservative variables */
     double *gW = (double *)calloc((size_t)nc * NW * D, sizeof(double));
     macro_gradients(o, gW, NULL);
 
-    /* line 3: interface equilibrium and time coefficients */
+    /* interface equilibrium and time coefficients */
     orc_face_eq_t *fe = (orc_face_eq_t *)calloc(nf, sizeof(orc_face_eq_t));
 #pragma omp parallel for schedule(static)
     for (int f = 0; f < nf; ++f) {
@@ -767,7 +767,7 @@ static void one_step(orc_t *o)
         time_integrals(dt, e->tau, e->c);
     }
 
-    /* lines 4-8: loop over velocities */
+    /* the velocity loop */
     double *gk = (double *)calloc((size_t)nc * NC * D, sizeof(double)); /* gradient buffer */
     double *Fk = (double *)calloc((size_t)nf * NC, sizeof(double));     /* u_n int f dt */
     double *Fmac = (double *)calloc((size_t)nf * NW, sizeof(double));
@@ -780,12 +780,12 @@ static void one_step(orc_t *o)
         double u2 = 0.0;
         for (int d = 0; d < D; ++d) u2 += uk[d] * uk[d];
 
-        /* line 5: reconstruct f_k */
+        /* reconstruct f_k */
 #pragma omp parallel for schedule(static)
         for (int i = 0; i < nc; ++i)
             for (int c = 0; c < NC; ++c) limited_gradient(o, i, fkk + c, NC, gk + ((size_t)i * NC + c) * D);
 
-        /* line 6: micro flux and its macroscopic contribution */
+        /* micro flux and its macroscopic contribution */
 #pragma omp parallel for schedule(static)
         for (int f = 0; f < nf; ++f) {
             const int bc = o->fbc[f];
@@ -869,7 +869,7 @@ static void one_step(orc_t *o)
             F[D + 1] += o->w[k] * 0.5 * (u2 * Hf + Bf);
         }
 
-        /* line 7: f_k and its gradient at wall faces */
+        /* f_k and its gradient at wall faces */
         for (int wi = 0; wi < o->nwall; ++wi) {
             int f = o->wall_face[wi], l = o->fcell[2 * f];
             for (int c = 0; c < NC; ++c) {
@@ -884,7 +884,7 @@ static void one_step(orc_t *o)
             }
         }
 
-        /* line 8: stage 1 (Eq. microS1), in place */
+        /* stage 1 (Eq. microS1), in place */
 #pragma omp parallel for schedule(static)
         for (int i = 0; i < nc; ++i) {
             const double *p = prim + (size_t)i * NW;
@@ -904,7 +904,7 @@ static void one_step(orc_t *o)
         }
     }
 
-    /* line 9: wall flux.  rho_w makes the net mass flux through the wall
+    /* boundary flux at the wall.  rho_w makes the net mass flux through the wall
      * vanish (Eq. maxWalldes); incident particles carry f_in - t u.grad f_in */
     for (int wi = 0; wi < o->nwall; ++wi) {
         int f = o->wall_face[wi], l = o->fcell[2 * f];
@@ -964,7 +964,7 @@ static void one_step(orc_t *o)
         for (int m = 0; m < NW; ++m) o->wallF[(size_t)wi * NW + m] = F[m] / dt;
     }
 
-    /* line 10: Eq. macroscopicUpdata */
+    /* macroscopic update, Eq. macroscopicUpdata */
     double resnum[ORC_MAXW] = {0};
     for (int i = 0; i < nc; ++i) {
         double *W = o->W + (size_t)i * NW;
@@ -982,7 +982,7 @@ static void one_step(orc_t *o)
     }
     for (int m = 0; m < NW; ++m) o->res[m] = sqrt(resnum[m]);
 
-    /* line 11: tau^{n+1}, q^{n+1} and stage 2 (Eq. microS2) */
+    /* micro update: tau^{n+1}, q^{n+1} and stage 2 (Eq. microS2) */
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < nc; ++i) {
         double p[ORC_MAXW], qt[ORC_MAXD];

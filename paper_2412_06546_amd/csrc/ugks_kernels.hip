@@ -3,24 +3,34 @@
 // Reference: Zhang, Wei, Long, Xu, "An efficiency and memory-saving
 // programming paradigm for the unified gas-kinetic scheme", arXiv:2412.06546.
 //
-// One step (Algorithm 1 of Section 3.2) is three launches on one stream:
-//   k_cell_grad  per cell:  limited least-squares gradient of W (line 2)
+// One step (Algorithm 1 of Section 3.2) on one stream:
+//   k_cell_grad  per cell:  limited least-squares gradient of W (the
+//                           macroscopic reconstruction)
 //   k_face_eq    per face:  interface equilibrium g0, its space and time
-//                           slopes, heat flux and time integrals (line 3)
-//   k_sweep      per cell, one workgroup owning the cell's whole velocity
-//                slab (lines 4-11 fused): for every velocity the limited
-//                slope of f is rebuilt in registers (own cell, and upwind
-//                neighbours when the neighbour is upwind), the interface
-//                flux of Eq. fullSolution is integrated over the step, the
-//                stage-1 value of Eq. microS1 is kept in registers, the wall
-//                density is reduced over velocities, W^{n+1} and q^{n+1}
-//                come from workgroup reductions of the same registers, and
-//                stage 2 (Eq. microS2) is applied before the single store.
+//                           slopes, heat flux and time integrals
+//   then the velocity loop and the updates after it, by one of two sweeps:
+//   push sweep   (default)  each cell computes its own limited slope of f
+//                once per velocity and, for every face the velocity leaves
+//                through, the interface flux of Eq. fullSolution integrated
+//                over the step, added with atomic adds into the stage-1 sums
+//                (Eq. microS1) of both of the face's cells: k_push_wall (wall
+//                densities), k_push_pf / k_push (per colour class of cells,
+//                or one launch of all cells), then k_push_final_r /
+//                k_push_final (W^{n+1}, q^{n+1}, stage 2 of Eq. microS2);
+//   gather sweep k_sweep    per cell, one workgroup owning the cell's whole
+//                velocity slab: for every velocity the limited slope of f is
+//                rebuilt in registers (own cell, and upwind neighbours when
+//                the neighbour is upwind), the stage-1 value is kept in
+//                registers, the wall density is reduced over velocities,
+//                W^{n+1} and q^{n+1} come from workgroup reductions of the
+//                same registers, and stage 2 is applied before the single
+//                store.
 // f is stored [cell][component][velocity]; lanes run over velocities, so a
 // wavefront reads 64 consecutive velocities of one cell (coalesced) and all
-// geometry and face data are wave-uniform (scalar loads).  f is read from
-// one buffer and written to the other (ping-pong): no slope or residual of f
-// ever reaches memory.
+// geometry and face data are wave-uniform (scalar loads).  f^n and the
+// stage-1 sums (push) or f^{n+1} (gather) are in two buffers, or one buffer
+// and a ring of one velocity chunk in place: no slope or residual of f ever
+// reaches memory.
 #include "ugks_internal.h"
 
 #include <algorithm>

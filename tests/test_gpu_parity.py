@@ -491,16 +491,19 @@ def _wall_flux_err(Fg, Fo):
     return (np.abs(Fg - Fo).max(axis=0) / scale).max()
 
 
+@pytest.mark.parametrize("sweep", ["auto", "push_unordered"])
 @pytest.mark.parametrize("which", ["cylinder", "channel3d"])
-def test_wall_flux_matches_oracle(which):
+def test_wall_flux_matches_oracle(which, sweep):
     """Surface quantities (Section 2.5): the macroscopic flux through every
     wall face in the last step, per unit area and time, against the oracle;
-    the 3D channel has a sliding (moving) wall, so shear is non-zero."""
+    the 3D channel has a sliding (moving) wall, so shear is non-zero.  With
+    the automatic sweep (gather for the cylinder, coloured push for the
+    channel) and with the unordered push."""
     ugks = _gpu()
     c = cases.case_cylinder_small() if which == "cylinder" else cases.case_channel_3d(kind="hex")
     steps = 10 if which == "cylinder" else 5
-    _say(f"case {c['name']}: wall flux after {steps} steps, fp64")
-    s, o = ugks.Solver(c), oracle.Oracle(c)
+    _say(f"case {c['name']}: wall flux after {steps} steps, fp64, {sweep} sweep")
+    s, o = ugks.Solver(c, sweep=sweep), oracle.Oracle(c)
     with pytest.raises(ugks.UgksError) as e:
         s.wall_flux()
     assert e.value.code == ugks.UGKS_ERR_STATE
