@@ -130,14 +130,16 @@ def test_cylinder_small_fp64(limiter, steps):
 
 
 @pytest.mark.parametrize("nv,half_width", [(3, 3.0), (8, 5.0), (16, 6.0)])
-def test_velocity_sets_below_and_at_the_block_size(nv, half_width):
+@pytest.mark.parametrize("sweep", ["auto", "push", "push_unordered"])
+def test_velocity_sets_below_and_at_the_block_size(nv, half_width, sweep):
     """9 velocities (fewer than one wavefront's 64 lanes), 64 (one
-    wavefront) and 256 (one 256-thread block, no ragged tail): parity with the
-    oracle after 10 steps; a call for zero steps changes nothing."""
+    wavefront) and 256 (one 256-thread block, no ragged tail), by every
+    sweep: parity with the oracle after 10 steps; a call for zero steps
+    changes nothing."""
     ugks = _gpu()
     c = cases.case_periodic_wave(nx=6, ny=4, nv=nv, half_width=half_width)
-    _say(f"case {c['name']}: fp64, 0 then 10 steps")
-    s, o = ugks.Solver(c), oracle.Oracle(c)
+    _say(f"case {c['name']}: fp64, {sweep} sweep, 0 then 10 steps")
+    s, o = ugks.Solver(c, sweep=sweep), oracle.Oracle(c)
     f0, W0 = s.f(), s.macros()[0]
     s.step(0)
     assert np.array_equal(s.f(), f0) and np.array_equal(s.macros()[0], W0) and s.step_count == 0
@@ -146,14 +148,16 @@ def test_velocity_sets_below_and_at_the_block_size(nv, half_width):
     _compare(s, o)
 
 
-def test_largest_velocity_set():
+@pytest.mark.parametrize("sweep", ["auto", "push_unordered"])
+def test_largest_velocity_set(sweep):
     """16,384 velocities (128 x 128), the most ugks_create accepts: 64
     velocities per thread of a 256-thread block, per-axis tables of 256
-    values, stage-1 values in f_out."""
+    values, stage-1 values in f_out (gather); the push launches split over
+    velocities (unordered push)."""
     ugks = _gpu()
     c = cases.case_periodic_wave(nx=6, ny=4, nv=128, half_width=8.0)
-    _say(f"case {c['name']}: fp64, 3 steps")
-    s, o = ugks.Solver(c), oracle.Oracle(c)
+    _say(f"case {c['name']}: fp64, {sweep} sweep, 3 steps")
+    s, o = ugks.Solver(c, sweep=sweep), oracle.Oracle(c)
     assert s.nv == 16384 and s.tensor_grid
     s.step(3)
     o.step(3)
