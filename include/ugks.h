@@ -283,7 +283,8 @@ int ugks_set_f(ugks_t *h, const double *f_in);
  * buffer of at least that size; ugks_set_state restores it into a handle
  * created from the same inputs (sizes, storage and the library's cell and
  * velocity orders are checked: UGKS_ERR_ARG otherwise), after which the
- * steps continue bit for bit as the saved run would have.  Unlike
+ * steps continue bit for bit as the saved run would have (with
+ * UGKS_SWEEP_PUSH_UNORDERED, to rounding: its sums have no fixed order).  Unlike
  * ugks_set_f, W and q are restored, not recomputed as moments of f.  The
  * blob is in host byte order. */
 size_t ugks_state_bytes(const ugks_t *h);
