@@ -319,10 +319,11 @@ int ugks_sweep_colours(const ugks_t *h);
  * per-step wall time the paper reports in Table UGKSeff).
  * ugks_profile(h, 1) resets the counters and records events around every
  * launch from then on (0 stops).  ugks_profile_read gives ms_out[0] = total
- * milliseconds in the sweep (the velocity loop of Algorithm 1 and the updates after it: every kernel of it, e.g. the
- * push sweep's wall, colour and final launches), ms_out[1] = total in the
- * two prologue kernels (macro gradients and interface equilibria, lines
- * 1-3), and the number of steps timed. */
+ * milliseconds in the sweep (the velocity loop of Algorithm 1 and the
+ * updates after it: every kernel of it, e.g. the push sweep's wall, push
+ * and final launches), ms_out[1] = total in the two prologue kernels (macro
+ * gradients and interface equilibria, the steps of Algorithm 1 before its
+ * velocity loop), and the number of steps timed. */
 int ugks_profile(ugks_t *h, int enable);
 int ugks_profile_read(const ugks_t *h, double *ms_out, long *launches);
 
