@@ -487,45 +487,70 @@ __device__ __forceinline__ void cell_grad(const Params p, int i)
     constexpr int NW = D + 2, MF = Dim<D>::MF;
     if (i >= p.nc) return;
     const CellGeo<D> &g = static_cast<const CellGeo<D> *>(p.cgeo)[i];
-    double gr[NW][D], Wi[NW];
+    const int nf = g.nf;
+    // the cell's W and its neighbours' (the cell's own where a slot has no
+    // neighbour: its difference is exactly zero), all loads issued at once
+    double Wi[NW], Wn[MF][NW];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) Wi[m] = p.W[(size_t)i * NW + m];
+#pragma unroll
+    for (int j = 0; j < MF; ++j) {
+        const int n = j < nf ? g.nb[j] : -1;
+        const size_t src = (size_t)(n < 0 ? i : n) * NW;
+#pragma unroll
+        for (int m = 0; m < NW; ++m) Wn[j][m] = p.W[src + m];
+    }
+    double gr[NW][D];
+#pragma unroll
     for (int m = 0; m < NW; ++m) {
-        Wi[m] = p.W[(size_t)i * NW + m];
         double mx = Wi[m], mn = Wi[m];
+#pragma unroll
         for (int d = 0; d < D; ++d) gr[m][d] = 0.0;
-        for (int j = 0; j < g.nf; ++j) {
-            int n = g.nb[j];
-            if (n < 0) continue;
-            double wj = p.W[(size_t)n * NW + m];
+#pragma unroll
+        for (int j = 0; j < MF; ++j) {
+            if (j >= nf) break;
+            const double wj = Wn[j][m];
+#pragma unroll
             for (int d = 0; d < D; ++d) gr[m][d] += g.lsq[j][d] * (wj - Wi[m]);
             mx = fmax(mx, wj);
             mn = fmin(mn, wj);
         }
         if (p.limiter) {
             double phi = 1.0;
-            for (int j = 0; j < g.nf; ++j) {
+#pragma unroll
+            for (int j = 0; j < MF; ++j) {
+                if (j >= nf) break;
                 double dm = 0.0;
+#pragma unroll
                 for (int d = 0; d < D; ++d) dm += gr[m][d] * g.dvec[j][d];
                 if (dm == 0.0) continue;
                 double dp = dm > 0.0 ? mx - Wi[m] : mn - Wi[m];
                 double ph = (dp * dp + g.eps2 + 2.0 * dm * dp) / (dp * dp + 2.0 * dm * dm + dm * dp + g.eps2);
                 phi = fmin(phi, ph);
             }
+#pragma unroll
             for (int d = 0; d < D; ++d) gr[m][d] *= phi;
         }
     }
     // first order where a reconstructed face state is not physical
     bool bad = false;
-    for (int j = 0; j < g.nf; ++j) {
+#pragma unroll
+    for (int j = 0; j < MF; ++j) {
+        if (j >= nf) break;
         double Wf[NW], ke = 0.0;
+#pragma unroll
         for (int m = 0; m < NW; ++m) {
             Wf[m] = Wi[m];
+#pragma unroll
             for (int d = 0; d < D; ++d) Wf[m] += gr[m][d] * g.dvec[j][d];
         }
+#pragma unroll
         for (int d = 0; d < D; ++d) ke += Wf[1 + d] * Wf[1 + d];
         if (!(Wf[0] > 0.0) || !(Wf[NW - 1] - 0.5 * ke / Wf[0] > 0.0)) bad = true;
     }
-    (void)MF;
+#pragma unroll
     for (int m = 0; m < NW; ++m)
+#pragma unroll
         for (int d = 0; d < D; ++d) p.gW[((size_t)i * NW + m) * D + d] = bad ? 0.0 : gr[m][d];
 }
 
